@@ -1,0 +1,244 @@
+"""CPU oracle for 3D-BBS (arXiv 2310.10023): Python loader for `bbs_oracle.c`.
+
+TEST INFRASTRUCTURE ONLY.  The oracle is the plain reference that the HIP
+library is checked against.  Only the test suite, the smoke check and the
+CPU-baseline leg of the benchmark may import this package; the library itself
+never does, and the two share no code.
+
+Parity pins for each function live in `tests/test_oracle_*.py`.  Parts with no
+external pin (the exact node counts of the search schedule) are marked
+"parity unpinned" there.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "bbs_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle_bbs.so")
+
+MAX_LEVELS = 16
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O2, no FP contraction, no fast math)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
+                               "-fopenmp", "-fPIC", "-shared", "-Wall", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class Grid(C.Structure):
+    _fields_ = [("levels", C.c_int32), ("translation_only", C.c_int32), ("r", C.c_float),
+                ("dmax", C.c_double), ("delta", C.c_double * MAX_LEVELS),
+                ("n", (C.c_int32 * MAX_LEVELS) * 3), ("dprime", (C.c_double * MAX_LEVELS) * 3),
+                ("a", (C.c_int32 * MAX_LEVELS) * 3), ("wmin", C.c_double * 3), ("wmax", C.c_double * 3),
+                ("lo", C.c_int32 * 3), ("hi", C.c_int32 * 3)]
+
+
+class Result(C.Structure):
+    _fields_ = [("found", C.c_int32), ("score", C.c_int32), ("leaf", C.c_int32 * 6),
+                ("pose", C.c_double * 6), ("nodes_expanded", C.c_int64), ("nodes_scored", C.c_int64),
+                ("flushes", C.c_int64), ("leaves_accepted", C.c_int64), ("initial_size", C.c_int64),
+                ("initial_kept", C.c_int64), ("bound_checks", C.c_int64), ("bound_violations", C.c_int64),
+                ("violation_excess_sum", C.c_double)]
+
+    def as_dict(self):
+        return {"found": self.found, "score": self.score, "leaf": list(self.leaf),
+                "pose": list(self.pose), "nodes_expanded": self.nodes_expanded,
+                "nodes_scored": self.nodes_scored, "flushes": self.flushes,
+                "leaves_accepted": self.leaves_accepted, "initial_size": self.initial_size,
+                "initial_kept": self.initial_kept, "bound_checks": self.bound_checks,
+                "bound_violations": self.bound_violations,
+                "violation_excess_sum": self.violation_excess_sum}
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        L = C.CDLL(_LIB)
+        P, I32, I64, F = C.c_void_p, C.c_int32, C.c_int64, C.c_float
+        L.orc_build_map.argtypes = [P, I64, F, I32, I32, C.POINTER(P)]
+        L.orc_build_map.restype = C.c_int
+        L.orc_free_map.argtypes = [P]
+        L.orc_map_level_size.argtypes = [P, I32]
+        L.orc_map_level_size.restype = I64
+        L.orc_map_level_keys.argtypes = [P, I32, P, I64]
+        L.orc_map_level_keys.restype = I64
+        L.orc_map_contains.argtypes = [P, I32, I32, I32, I32]
+        L.orc_map_contains.restype = I32
+        L.orc_setup.argtypes = [P, I64, P, P, F, I32, I32, C.POINTER(Grid)]
+        L.orc_setup.restype = C.c_int
+        L.orc_rotation.argtypes = [C.POINTER(Grid), I32, I32, I32, I32, P]
+        L.orc_score.argtypes = [P, P, I64, C.POINTER(Grid), I32, I32, I32, I32, I32, I32, I32]
+        L.orc_score.restype = I32
+        L.orc_score_nodes.argtypes = [P, P, I64, C.POINTER(Grid), P, I64, P, I32]
+        L.orc_localize.argtypes = [P, P, I64, C.POINTER(Grid), I32, I64, I32, I64, C.POINTER(Result), P, I64]
+        L.orc_localize.restype = C.c_int
+        L.orc_bruteforce.argtypes = [P, P, I64, C.POINTER(Grid), I32, I32, C.POINTER(Result)]
+        L.orc_bruteforce.restype = C.c_int
+        L.orc_all_leaf_scores.argtypes = [P, P, I64, C.POINTER(Grid), P, I64, I32]
+        L.orc_all_leaf_scores.restype = I64
+        L.orc_children.argtypes = [C.POINTER(Grid), P, P, I64]
+        L.orc_children.restype = I64
+        L.orc_sizeof_grid.restype = I64
+        L.orc_sizeof_result.restype = I64
+        assert L.orc_sizeof_grid() == C.sizeof(Grid), "oracle Grid layout mismatch"
+        assert L.orc_sizeof_result() == C.sizeof(Result), "oracle Result layout mismatch"
+        _lib = L
+    return _lib
+
+
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+class Map:
+    """The dilated multi-resolution voxel sets D_0 .. D_levels (Sec. III-C)."""
+
+    def __init__(self, points, r: float, levels: int, dilate_leaf: bool = True):
+        pts = _f32(points).reshape(-1, 3)
+        h = C.c_void_p()
+        rc = lib().orc_build_map(pts.ctypes.data, len(pts), float(r), int(levels), int(dilate_leaf), C.byref(h))
+        if rc != 0:
+            raise OracleError(f"orc_build_map failed ({rc})")
+        self._h = h
+        self.r = float(np.float32(r))
+        self.levels = int(levels)
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.orc_free_map(self._h)
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def level_size(self, l: int) -> int:
+        return int(lib().orc_map_level_size(self._h, l))
+
+    def level_keys(self, l: int) -> np.ndarray:
+        n = self.level_size(l)
+        out = np.zeros((max(n, 1), 3), dtype=np.int32)
+        lib().orc_map_level_keys(self._h, l, out.ctypes.data, n)
+        return out[:n]
+
+    def contains(self, l: int, x: int, y: int, z: int) -> bool:
+        return bool(lib().orc_map_contains(self._h, l, int(x), int(y), int(z)))
+
+
+class Search:
+    """A scan plus its search ranges: the angular/translational grid and the
+    oracle's score, branching and search."""
+
+    def __init__(self, omap: Map, scan, rmin, rmax, translation_only: bool = False):
+        self.map = omap
+        self.scan = _f32(scan).reshape(-1, 3)
+        self.rmin = _f32(rmin)
+        self.rmax = _f32(rmax)
+        self.grid = Grid()
+        rc = lib().orc_setup(self.scan.ctypes.data, len(self.scan), self.rmin.ctypes.data, self.rmax.ctypes.data,
+                             omap.r, omap.levels, int(translation_only), C.byref(self.grid))
+        if rc != 0:
+            raise OracleError(f"orc_setup failed ({rc})")
+
+    # grid accessors
+    @property
+    def k(self):
+        return len(self.scan)
+
+    def n(self, ax: int, l: int) -> int:
+        return int(self.grid.n[ax][l])
+
+    def a(self, ax: int, l: int) -> int:
+        return int(self.grid.a[ax][l])
+
+    def delta(self, l: int) -> float:
+        return float(self.grid.delta[l])
+
+    def dprime(self, ax: int, l: int) -> float:
+        return float(self.grid.dprime[ax][l])
+
+    @property
+    def lo(self):
+        return tuple(self.grid.lo)
+
+    @property
+    def hi(self):
+        return tuple(self.grid.hi)
+
+    def rotation(self, level, ia, ib, ig) -> np.ndarray:
+        R = np.zeros(9, dtype=np.float32)
+        lib().orc_rotation(C.byref(self.grid), level, ia, ib, ig, R.ctypes.data)
+        return R.reshape(3, 3)
+
+    def score(self, level, x, y, z, ia, ib, ig) -> int:
+        return int(lib().orc_score(self.map.handle, self.scan.ctypes.data, self.k, C.byref(self.grid),
+                                   level, x, y, z, ia, ib, ig))
+
+    def score_nodes(self, nodes, threads: int = 1) -> np.ndarray:
+        """nodes: (n, 7) int32 rows (level, x, y, z, roll, pitch, yaw)."""
+        nodes = _i32(nodes).reshape(-1, 7)
+        out = np.zeros(len(nodes), dtype=np.int32)
+        lib().orc_score_nodes(self.map.handle, self.scan.ctypes.data, self.k, C.byref(self.grid),
+                              nodes.ctypes.data, len(nodes), out.ctypes.data, threads)
+        return out
+
+    def children(self, node) -> np.ndarray:
+        node = _i32(node)
+        cap = 8 * 64 * 8
+        out = np.zeros((cap, 7), dtype=np.int32)
+        n = lib().orc_children(C.byref(self.grid), node.ctypes.data, out.ctypes.data, cap)
+        return out[:n]
+
+    def localize(self, threshold: int, batch: int = 10000, threads: int = 1, max_scored: int = 0,
+                 trace_cap: int = 0) -> dict:
+        res = Result()
+        tr = np.zeros(max(trace_cap, 1), dtype=np.int64)
+        rc = lib().orc_localize(self.map.handle, self.scan.ctypes.data, self.k, C.byref(self.grid), int(threshold),
+                                int(batch), int(threads), int(max_scored), C.byref(res),
+                                tr.ctypes.data if trace_cap else None, int(trace_cap))
+        if rc != 0:
+            raise OracleError(f"orc_localize failed ({rc})")
+        d = res.as_dict()
+        if trace_cap:
+            d["flush_sizes"] = tr[:min(trace_cap, res.flushes)].tolist()
+        return d
+
+    def bruteforce(self, threshold: int, threads: int = 1) -> dict:
+        res = Result()
+        rc = lib().orc_bruteforce(self.map.handle, self.scan.ctypes.data, self.k, C.byref(self.grid),
+                                  int(threshold), int(threads), C.byref(res))
+        if rc != 0:
+            raise OracleError(f"orc_bruteforce failed ({rc})")
+        return res.as_dict()
+
+    def all_leaf_scores(self, threads: int = 1) -> np.ndarray:
+        """Scores of every valid leaf, shaped (nx, ny, nz, n_roll, n_pitch, n_yaw)."""
+        g = self.grid
+        shape = tuple(int(g.hi[i] - g.lo[i] + 1) for i in range(3)) + tuple(int(g.n[i][0]) for i in range(3))
+        total = int(np.prod(shape))
+        out = np.zeros(total, dtype=np.int32)
+        lib().orc_all_leaf_scores(self.map.handle, self.scan.ctypes.data, self.k, C.byref(self.grid),
+                                  out.ctypes.data, total, threads)
+        return out.reshape(shape)

@@ -1,0 +1,722 @@
+/*
+ * CPU oracle for 3D-BBS global localization (Aoki et al., "3D-BBS: Global
+ * Localization for 3D Point Cloud Scan Matching Using Branch-and-Bound
+ * Algorithm", arXiv 2310.10023).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow, obviously correct
+ * reference that the HIP library is checked against.  Only the test suite,
+ * the smoke check and the CPU-baseline leg of the benchmark may load it.  It
+ * shares no code, header, table or helper with the HIP library.
+ *
+ * Every function follows the paper's text in the order it states things:
+ *   - multi-resolution voxel map and its dilation ........ Sec. III-C
+ *   - node score = upper bound, Eq. (eq:3Dupperbound) ..... Sec. III-C
+ *   - rotational step delta(r), Eq. (2) ................... Sec. III-B
+ *   - per-level step delta'(r_l), divisions a ............. Sec. III-D
+ *   - roto-translational branching ........................ Sec. III-D
+ *   - best-first batched search, Alg. 2 ................... Sec. III-E
+ * Where the paper is silent the reading used is stated at the point of use.
+ *
+ * Precision: the rotation entries are formed in double and rounded once to
+ * float; the point transform, the division by the voxel size and the floor are
+ * float, evaluated in a fixed order (build with -ffp-contract=off, no fast
+ * math).  Everything after the floor is integer.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_MAX_LEVELS 16
+#define ORC_KEY_BIAS (1 << 20)
+
+enum { ORC_OK = 0, ORC_ERR_ARG = -1, ORC_ERR_OOM = -2 };
+
+/* ------------------------------------------------------------------ helpers */
+
+/* floor(v / 2^l) written out, without relying on the shift of a negative int */
+static int32_t floor_div_pow2(int32_t v, int l)
+{
+    int32_t d = (int32_t)1 << l;
+    if (v >= 0) return v / d;
+    return -((-v + d - 1) / d);
+}
+
+static int key_in_range(int32_t x, int32_t y, int32_t z)
+{
+    return x >= -ORC_KEY_BIAS && x < ORC_KEY_BIAS && y >= -ORC_KEY_BIAS && y < ORC_KEY_BIAS &&
+           z >= -ORC_KEY_BIAS && z < ORC_KEY_BIAS;
+}
+
+static int64_t pack_key(int32_t x, int32_t y, int32_t z)
+{
+    return ((int64_t)(x + ORC_KEY_BIAS) << 42) | ((int64_t)(y + ORC_KEY_BIAS) << 21) |
+           (int64_t)(z + ORC_KEY_BIAS);
+}
+
+static int cmp_i64(const void *a, const void *b)
+{
+    int64_t x = *(const int64_t *)a, y = *(const int64_t *)b;
+    return (x > y) - (x < y);
+}
+
+static int64_t sort_unique(int64_t *v, int64_t n)
+{
+    if (n == 0) return 0;
+    qsort(v, (size_t)n, sizeof(int64_t), cmp_i64);
+    int64_t m = 1;
+    for (int64_t i = 1; i < n; ++i)
+        if (v[i] != v[m - 1]) v[m++] = v[i];
+    return m;
+}
+
+/* ------------------------------------------------------------------ map (Sec. III-C) */
+
+typedef struct {
+    float r;                           /* minimum voxel size r */
+    int32_t levels;                    /* l_max: tables exist for l = 0..l_max */
+    int32_t dilate_leaf;               /* 1: level 0 is dilated like every other level */
+    int64_t n_keys[ORC_MAX_LEVELS];
+    int64_t *keys[ORC_MAX_LEVELS];     /* sorted set D_l of packed voxel keys */
+} orc_map;
+
+void orc_free_map(orc_map *m)
+{
+    if (!m) return;
+    for (int l = 0; l < ORC_MAX_LEVELS; ++l) free(m->keys[l]);
+    free(m);
+}
+
+/*
+ * Build D_l for l = 0..levels.
+ * Occupied voxels at level l are v = floor(p / r_l) with r_l = 2^l r (Sec. III-C).
+ * Reading: v is computed as floor(float(p / r)) at level 0 and then divided by
+ * 2^l with floor division, which equals floor(p / r_l) in exact arithmetic and
+ * keeps the levels nested.
+ * Dilation: every occupied voxel also contributes its neighbours v - j for
+ * j in {0,1}^3 (V_add, Sec. III-C), at every level (level 0 too unless
+ * dilate_leaf is 0).
+ */
+int orc_build_map(const float *xyz, int64_t n, float r, int32_t levels, int32_t dilate_leaf,
+                  orc_map **out)
+{
+    *out = NULL;
+    if (!xyz || n < 1 || !(r > 0.0f) || !isfinite(r) || levels < 0 || levels >= ORC_MAX_LEVELS)
+        return ORC_ERR_ARG;
+    orc_map *m = (orc_map *)calloc(1, sizeof(orc_map));
+    if (!m) return ORC_ERR_OOM;
+    m->r = r;
+    m->levels = levels;
+    m->dilate_leaf = dilate_leaf;
+    /* occupied level-0 voxels, as a set: duplicates change no D_l */
+    int64_t *occ = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+    if (!occ) { orc_free_map(m); return ORC_ERR_OOM; }
+    for (int64_t i = 0; i < n; ++i) {
+        int32_t v[3];
+        for (int a = 0; a < 3; ++a) {
+            float c = xyz[3 * i + a];
+            if (!isfinite(c)) { free(occ); orc_free_map(m); return ORC_ERR_ARG; }
+            float q = c / r;
+            double f = floor((double)q);
+            if (f < -(double)ORC_KEY_BIAS + 2 || f >= (double)ORC_KEY_BIAS - 2) {
+                free(occ); orc_free_map(m); return ORC_ERR_ARG;
+            }
+            v[a] = (int32_t)f;
+        }
+        occ[i] = pack_key(v[0], v[1], v[2]);
+    }
+    int64_t n_occ = sort_unique(occ, n);
+    int64_t *buf = (int64_t *)malloc((size_t)n_occ * 8 * sizeof(int64_t));
+    if (!buf) { free(occ); orc_free_map(m); return ORC_ERR_OOM; }
+    for (int l = 0; l <= levels; ++l) {
+        int dilate = (l > 0) || dilate_leaf;
+        int64_t cnt = 0;
+        for (int64_t i = 0; i < n_occ; ++i) {
+            int32_t vx = floor_div_pow2((int32_t)((occ[i] >> 42) & 0x1FFFFF) - ORC_KEY_BIAS, l);
+            int32_t vy = floor_div_pow2((int32_t)((occ[i] >> 21) & 0x1FFFFF) - ORC_KEY_BIAS, l);
+            int32_t vz = floor_div_pow2((int32_t)(occ[i] & 0x1FFFFF) - ORC_KEY_BIAS, l);
+            if (!dilate) { buf[cnt++] = pack_key(vx, vy, vz); continue; }
+            for (int jx = 0; jx <= 1; ++jx)
+                for (int jy = 0; jy <= 1; ++jy)
+                    for (int jz = 0; jz <= 1; ++jz)
+                        buf[cnt++] = pack_key(vx - jx, vy - jy, vz - jz);
+        }
+        cnt = sort_unique(buf, cnt);
+        m->keys[l] = (int64_t *)malloc((size_t)(cnt ? cnt : 1) * sizeof(int64_t));
+        if (!m->keys[l]) { free(occ); free(buf); orc_free_map(m); return ORC_ERR_OOM; }
+        memcpy(m->keys[l], buf, (size_t)cnt * sizeof(int64_t));
+        m->n_keys[l] = cnt;
+    }
+    free(occ);
+    free(buf);
+    *out = m;
+    return ORC_OK;
+}
+
+int64_t orc_map_level_size(const orc_map *m, int32_t l)
+{
+    if (!m || l < 0 || l > m->levels) return -1;
+    return m->n_keys[l];
+}
+
+/* Dump D_l as (x, y, z) triples in increasing packed-key order. */
+int64_t orc_map_level_keys(const orc_map *m, int32_t l, int32_t *out_xyz, int64_t cap)
+{
+    if (!m || l < 0 || l > m->levels) return -1;
+    int64_t n = m->n_keys[l] < cap ? m->n_keys[l] : cap;
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t k = m->keys[l][i];
+        out_xyz[3 * i + 0] = (int32_t)((k >> 42) & 0x1FFFFF) - ORC_KEY_BIAS;
+        out_xyz[3 * i + 1] = (int32_t)((k >> 21) & 0x1FFFFF) - ORC_KEY_BIAS;
+        out_xyz[3 * i + 2] = (int32_t)(k & 0x1FFFFF) - ORC_KEY_BIAS;
+    }
+    return m->n_keys[l];
+}
+
+/* H^l(v): binary occupancy of voxel v in the dilated level-l map (Sec. III-C). */
+int32_t orc_map_contains(const orc_map *m, int32_t l, int32_t x, int32_t y, int32_t z)
+{
+    if (!key_in_range(x, y, z)) return 0;
+    int64_t key = pack_key(x, y, z);
+    const int64_t *k = m->keys[l];
+    int64_t lo = 0, hi = m->n_keys[l];
+    while (lo < hi) {
+        int64_t mid = lo + (hi - lo) / 2;
+        if (k[mid] < key) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo < m->n_keys[l] && k[lo] == key;
+}
+
+/* ------------------------------------------------------------------ search grid */
+
+typedef struct {
+    int32_t levels;
+    int32_t translation_only;
+    float r;
+    double dmax;                           /* largest scan range d_max */
+    double delta[ORC_MAX_LEVELS];          /* delta(r_l), Eq. (2) with r -> r_l */
+    int32_t n[3][ORC_MAX_LEVELS];          /* angular cells per axis (roll, pitch, yaw) */
+    double dprime[3][ORC_MAX_LEVELS];      /* delta'(r_l), Sec. III-D */
+    int32_t a[3][ORC_MAX_LEVELS];          /* divisions a from level l to l - 1 (l >= 1) */
+    double wmin[3], wmax[3];               /* angular ranges */
+    int32_t lo[3], hi[3];                  /* leaf translation index range per axis */
+} orc_grid;
+
+/*
+ * Angular and translational discretisation.
+ *  delta(r) = arccos(1 - r^2 / (2 d_max^2))                       Eq. (2)
+ *  delta'(r_l) = W / ceil(W / delta(r_l)),   W = W_max - W_min      Sec. III-D
+ *  a = ceil(delta'(r_l) / delta'(r_{l-1})) if delta'(r_{l-1}) < W else 1.
+ * Readings: d_max = largest |s_k| (double); the arccos argument is clamped to
+ * [-1, 1]; an axis with W = 0 has one cell; n_l = ceil(W / delta_l) cells of
+ * width delta'_l = W / n_l, so delta'_l / delta'_{l-1} = n_{l-1} / n_l and
+ * a = ceil(n_{l-1} / n_l) (which is 1 exactly when n_{l-1} = 1).  In
+ * translation-only mode (Table I, "Trans.") every level keeps the leaf grid.
+ * Translation: leaf indices i with W_min <= r i <= W_max (the set of Eq. (1)),
+ * i.e. [ceil(W_min / r), floor(W_max / r)].
+ */
+int orc_setup(const float *scan, int64_t k, const float rmin[6], const float rmax[6], float r,
+              int32_t levels, int32_t translation_only, orc_grid *g)
+{
+    memset(g, 0, sizeof(*g));
+    if (!scan || k < 1 || !(r > 0.0f) || levels < 0 || levels >= ORC_MAX_LEVELS) return ORC_ERR_ARG;
+    for (int i = 0; i < 6; ++i)
+        if (!isfinite(rmin[i]) || !isfinite(rmax[i]) || rmin[i] > rmax[i]) return ORC_ERR_ARG;
+    g->levels = levels;
+    g->translation_only = translation_only;
+    g->r = r;
+    double dmax = 0.0;
+    for (int64_t i = 0; i < k; ++i) {
+        double x = scan[3 * i], y = scan[3 * i + 1], z = scan[3 * i + 2];
+        if (!isfinite(x) || !isfinite(y) || !isfinite(z)) return ORC_ERR_ARG;
+        double d = sqrt(x * x + y * y + z * z);
+        if (d > dmax) dmax = d;
+    }
+    g->dmax = dmax;
+    for (int l = 0; l <= levels; ++l) {
+        double rl = ldexp((double)r, l);
+        double c = 1.0 - (rl * rl) / (2.0 * dmax * dmax);
+        if (c < -1.0) c = -1.0;
+        if (c > 1.0) c = 1.0;
+        g->delta[l] = acos(c);
+    }
+    for (int ax = 0; ax < 3; ++ax) {
+        g->wmin[ax] = rmin[3 + ax];
+        g->wmax[ax] = rmax[3 + ax];
+        double W = g->wmax[ax] - g->wmin[ax];
+        for (int l = 0; l <= levels; ++l) {
+            int src = translation_only ? 0 : l;
+            int32_t n;
+            if (W == 0.0) n = 1;
+            else {
+                double q = ceil(W / g->delta[src]);
+                if (!(q >= 1.0)) q = 1.0;
+                if (q > 1.0e8) return ORC_ERR_ARG;
+                n = (int32_t)q;
+            }
+            g->n[ax][l] = n;
+            g->dprime[ax][l] = W / n;
+        }
+        g->a[ax][0] = 1;
+        for (int l = 1; l <= levels; ++l)
+            g->a[ax][l] = (g->n[ax][l - 1] + g->n[ax][l] - 1) / g->n[ax][l];
+    }
+    for (int ax = 0; ax < 3; ++ax) {
+        double lo = ceil((double)rmin[ax] / (double)r);
+        double hi = floor((double)rmax[ax] / (double)r);
+        if (lo > hi) return ORC_ERR_ARG;
+        if (lo < -(double)ORC_KEY_BIAS / 4 || hi > (double)ORC_KEY_BIAS / 4) return ORC_ERR_ARG;
+        g->lo[ax] = (int32_t)lo;
+        g->hi[ax] = (int32_t)hi;
+    }
+    /* every transformed key must stay inside the packable range */
+    if (dmax / r + 4.0 >= (double)ORC_KEY_BIAS / 4) return ORC_ERR_ARG;
+    return ORC_OK;
+}
+
+/* Angle of cell c of axis ax at level l.  Reading: cells are anchored at their
+ * centres, W_min + delta'_l (c + 1/2). */
+static double cell_angle(const orc_grid *g, int ax, int32_t c, int l)
+{
+    return g->wmin[ax] + g->dprime[ax][l] * ((double)c + 0.5);
+}
+
+/*
+ * Rotation of the pose's Euler angles (roll alpha, pitch beta, yaw gamma),
+ * Sec. III-A.  Reading: R = Rz(gamma) Ry(beta) Rx(alpha), entries formed in
+ * double with the products evaluated left to right, then rounded to float.
+ */
+static void euler_to_float_matrix(double al, double be, double ga, float R[9])
+{
+    double ca = cos(al), sa = sin(al);
+    double cb = cos(be), sb = sin(be);
+    double cg = cos(ga), sg = sin(ga);
+    R[0] = (float)(cg * cb);
+    R[1] = (float)(cg * sb * sa - sg * ca);
+    R[2] = (float)(cg * sb * ca + sg * sa);
+    R[3] = (float)(sg * cb);
+    R[4] = (float)(sg * sb * sa + cg * ca);
+    R[5] = (float)(sg * sb * ca - cg * sa);
+    R[6] = (float)(-sb);
+    R[7] = (float)(cb * sa);
+    R[8] = (float)(cb * ca);
+}
+
+void orc_rotation(const orc_grid *g, int32_t level, int32_t ia, int32_t ib, int32_t ig, float R[9])
+{
+    euler_to_float_matrix(cell_angle(g, 0, ia, level), cell_angle(g, 1, ib, level),
+                          cell_angle(g, 2, ig, level), R);
+}
+
+static int translation_valid(const orc_grid *g, int ax, int32_t c, int l)
+{
+    return c >= floor_div_pow2(g->lo[ax], l) && c <= floor_div_pow2(g->hi[ax], l);
+}
+
+static int node_valid(const orc_grid *g, int l, const int32_t t[3], const int32_t ang[3])
+{
+    for (int ax = 0; ax < 3; ++ax) {
+        if (!translation_valid(g, ax, t[ax], l)) return 0;
+        if (ang[ax] < 0 || ang[ax] >= g->n[ax][l]) return 0;
+    }
+    return 1;
+}
+
+/* ------------------------------------------------------------------ score (Eq. eq:3Dupperbound) */
+
+/*
+ * score(c) = sum_k H^{c_l}(T_{x_c} s_k).
+ * The node's translation is x_c = r_l c (the 2D rule of Sec. III-B carried to
+ * 3D).  Reading: the level-l voxel of R s_k + r_l c is computed as
+ * floor(floor(float(R s_k) / r) / 2^l) + c, which equals
+ * floor((R s_k + r_l c) / r_l) in exact arithmetic.
+ */
+int32_t orc_score(const orc_map *m, const float *scan, int64_t k, const orc_grid *g, int32_t level,
+                  int32_t x, int32_t y, int32_t z, int32_t ia, int32_t ib, int32_t ig)
+{
+    float R[9];
+    orc_rotation(g, level, ia, ib, ig, R);
+    const float r = g->r;
+    int32_t count = 0;
+    for (int64_t i = 0; i < k; ++i) {
+        float sx = scan[3 * i], sy = scan[3 * i + 1], sz = scan[3 * i + 2];
+        int32_t key[3];
+        for (int row = 0; row < 3; ++row) {
+            float t0 = R[3 * row + 0] * sx;
+            float t1 = R[3 * row + 1] * sy;
+            float t2 = R[3 * row + 2] * sz;
+            float p = (t0 + t1) + t2;
+            float q = p / r;
+            key[row] = (int32_t)floorf(q);
+        }
+        int32_t vx = floor_div_pow2(key[0], level) + x;
+        int32_t vy = floor_div_pow2(key[1], level) + y;
+        int32_t vz = floor_div_pow2(key[2], level) + z;
+        count += orc_map_contains(m, level, vx, vy, vz);
+    }
+    return count;
+}
+
+/* nodes: n records of 7 int32 (level, x, y, z, roll, pitch, yaw) */
+void orc_score_nodes(const orc_map *m, const float *scan, int64_t k, const orc_grid *g,
+                     const int32_t *nodes, int64_t n, int32_t *scores, int32_t threads)
+{
+#pragma omp parallel for schedule(dynamic, 16) num_threads(threads > 0 ? threads : 1)
+    for (int64_t i = 0; i < n; ++i) {
+        const int32_t *c = nodes + 7 * i;
+        scores[i] = orc_score(m, scan, k, g, c[0], c[1], c[2], c[3], c[4], c[5], c[6]);
+    }
+}
+
+/* ------------------------------------------------------------------ search (Alg. 2) */
+
+typedef struct {
+    int32_t t[3], ang[3];
+    int32_t level, score, parent_score;
+    int64_t seq;
+} orc_node;
+
+typedef struct {
+    orc_node *v;
+    int64_t n, cap;
+} node_vec;
+
+static int vec_push(node_vec *q, const orc_node *x)
+{
+    if (q->n == q->cap) {
+        int64_t cap = q->cap ? 2 * q->cap : 1024;
+        orc_node *p = (orc_node *)realloc(q->v, (size_t)cap * sizeof(orc_node));
+        if (!p) return ORC_ERR_OOM;
+        q->v = p;
+        q->cap = cap;
+    }
+    q->v[q->n++] = *x;
+    return ORC_OK;
+}
+
+/*
+ * Queue order.  The paper sorts C in descending order of score (Sec. III-D,
+ * Alg. 2).  Reading for ties: lower level first (the depth preference of
+ * Alg. 1), then first-in first-out.
+ */
+static int before(const orc_node *a, const orc_node *b)
+{
+    if (a->score != b->score) return a->score > b->score;
+    if (a->level != b->level) return a->level < b->level;
+    return a->seq < b->seq;
+}
+
+static int heap_push(node_vec *h, const orc_node *x)
+{
+    if (vec_push(h, x)) return ORC_ERR_OOM;
+    int64_t i = h->n - 1;
+    while (i > 0) {
+        int64_t p = (i - 1) / 2;
+        if (!before(&h->v[i], &h->v[p])) break;
+        orc_node t = h->v[i]; h->v[i] = h->v[p]; h->v[p] = t;
+        i = p;
+    }
+    return ORC_OK;
+}
+
+static orc_node heap_pop(node_vec *h)
+{
+    orc_node top = h->v[0];
+    h->v[0] = h->v[--h->n];
+    int64_t i = 0;
+    for (;;) {
+        int64_t l = 2 * i + 1, r = l + 1, m = i;
+        if (l < h->n && before(&h->v[l], &h->v[m])) m = l;
+        if (r < h->n && before(&h->v[r], &h->v[m])) m = r;
+        if (m == i) break;
+        orc_node t = h->v[i]; h->v[i] = h->v[m]; h->v[m] = t;
+        i = m;
+    }
+    return top;
+}
+
+static int leaf_lex_less(const orc_node *a, const orc_node *b)
+{
+    for (int i = 0; i < 3; ++i) if (a->t[i] != b->t[i]) return a->t[i] < b->t[i];
+    for (int i = 0; i < 3; ++i) if (a->ang[i] != b->ang[i]) return a->ang[i] < b->ang[i];
+    return 0;
+}
+
+typedef struct {
+    int32_t found, score;
+    int32_t leaf[6];                 /* i_x, i_y, i_z, i_roll, i_pitch, i_yaw */
+    double pose[6];                  /* x, y, z [m], roll, pitch, yaw [rad] */
+    int64_t nodes_expanded;          /* accepted non-leaf pops (branched nodes) */
+    int64_t nodes_scored;            /* initial set + every flushed child */
+    int64_t flushes;                 /* batches sent to scoring */
+    int64_t leaves_accepted;         /* leaf pops with score >= best */
+    int64_t initial_size, initial_kept;
+    int64_t bound_checks, bound_violations;  /* children scored / children above parent */
+    double violation_excess_sum;             /* sum of (child - parent) / parent */
+} orc_result;
+
+/*
+ * Children of node c (Sec. III-D, roto-translational branching):
+ *   (2c_x + j_x, 2c_y + j_y, 2c_z + j_z, a_a c_a + j_a, a_b c_b + j_b, a_g c_g + j_g, l - 1).
+ * Readings: enumeration with the rotational offsets outer (j_a, j_b, j_g in
+ * lexicographic order) and the translational ones inner (j_x, j_y, j_z); a
+ * child whose angle index reaches the level's cell count, or whose leaf
+ * interval misses the translation range, is not generated.
+ */
+static int branch(const orc_grid *g, const orc_node *c, node_vec *pending)
+{
+    int l = c->level, cl = l - 1;
+    int32_t ja[3];
+    for (ja[0] = 0; ja[0] < g->a[0][l]; ++ja[0])
+        for (ja[1] = 0; ja[1] < g->a[1][l]; ++ja[1])
+            for (ja[2] = 0; ja[2] < g->a[2][l]; ++ja[2]) {
+                orc_node ch;
+                memset(&ch, 0, sizeof(ch));
+                ch.level = cl;
+                ch.parent_score = c->score;
+                for (int ax = 0; ax < 3; ++ax) ch.ang[ax] = g->a[ax][l] * c->ang[ax] + ja[ax];
+                for (int jx = 0; jx <= 1; ++jx)
+                    for (int jy = 0; jy <= 1; ++jy)
+                        for (int jz = 0; jz <= 1; ++jz) {
+                            ch.t[0] = 2 * c->t[0] + jx;
+                            ch.t[1] = 2 * c->t[1] + jy;
+                            ch.t[2] = 2 * c->t[2] + jz;
+                            if (!node_valid(g, cl, ch.t, ch.ang)) continue;
+                            if (vec_push(pending, &ch)) return ORC_ERR_OOM;
+                        }
+            }
+    return ORC_OK;
+}
+
+static void score_vec(const orc_map *m, const float *scan, int64_t k, const orc_grid *g, node_vec *v,
+                      int32_t threads)
+{
+#pragma omp parallel for schedule(dynamic, 8) num_threads(threads > 0 ? threads : 1)
+    for (int64_t i = 0; i < v->n; ++i) {
+        orc_node *c = &v->v[i];
+        c->score = orc_score(m, scan, k, g, c->level, c->t[0], c->t[1], c->t[2], c->ang[0], c->ang[1],
+                             c->ang[2]);
+    }
+}
+
+static void decode_pose(const orc_grid *g, const int32_t leaf[6], double pose[6])
+{
+    for (int ax = 0; ax < 3; ++ax) pose[ax] = (double)g->r * leaf[ax];
+    for (int ax = 0; ax < 3; ++ax) pose[3 + ax] = cell_angle(g, ax, leaf[3 + ax], 0);
+}
+
+/*
+ * Batched best-first branch and bound, Alg. 2.
+ *  - best_score starts at score_threshold; initial nodes below it are removed
+ *    (Sec. III-D, search strategy).
+ *  - pop c; skip it if its score is below best_score;
+ *  - a leaf becomes the match and sets best_score.  Reading: among leaves of
+ *    equal score the lexicographically smallest index (x, y, z, roll, pitch,
+ *    yaw) is kept;
+ *  - otherwise c is branched and its children are appended to the pending set;
+ *  - when more than b nodes are pending they are scored and pushed.
+ * Reading: when the queue runs empty while nodes are still pending, they are
+ * scored and pushed too, so no branched child is lost.
+ * Initial set (Sec. III-D: every pose in the search range at l_max).  Reading
+ * for its order: the top-level cells are enumerated as the valid children of
+ * virtual cells one level above, visited in lexicographic order, each
+ * expanded like a branch (rotations outer, translations inner).
+ * max_pops bounds the number of queue pops (0 = no bound); a bounded run
+ * returns found = -1 when it stops early.
+ */
+int orc_localize(const orc_map *m, const float *scan, int64_t k, const orc_grid *g, int32_t threshold,
+                 int64_t batch, int32_t threads, int64_t max_scored, orc_result *res,
+                 int64_t *trace_flush, int64_t trace_cap)
+{
+    memset(res, 0, sizeof(*res));
+    if (!m || !scan || k < 1 || batch < 1 || g->levels != m->levels) return ORC_ERR_ARG;
+    const int L = g->levels;
+    node_vec heap = {0}, pending = {0};
+    int64_t seq = 0;
+    int32_t best = threshold;
+    int have_match = 0;
+    orc_node match;
+    memset(&match, 0, sizeof(match));
+    int rc = ORC_OK;
+
+    /* initial set C_{l_max} */
+    int32_t plo[3], phi[3];
+    for (int ax = 0; ax < 3; ++ax) {
+        plo[ax] = floor_div_pow2(g->lo[ax], L + 1);
+        phi[ax] = floor_div_pow2(g->hi[ax], L + 1);
+    }
+    orc_node top;
+    memset(&top, 0, sizeof(top));
+    top.level = L;
+    for (int32_t px = plo[0]; px <= phi[0]; ++px)
+        for (int32_t py = plo[1]; py <= phi[1]; ++py)
+            for (int32_t pz = plo[2]; pz <= phi[2]; ++pz)
+                for (top.ang[0] = 0; top.ang[0] < g->n[0][L]; ++top.ang[0])
+                    for (top.ang[1] = 0; top.ang[1] < g->n[1][L]; ++top.ang[1])
+                        for (top.ang[2] = 0; top.ang[2] < g->n[2][L]; ++top.ang[2])
+                            for (int jx = 0; jx <= 1; ++jx)
+                                for (int jy = 0; jy <= 1; ++jy)
+                                    for (int jz = 0; jz <= 1; ++jz) {
+                                        top.t[0] = 2 * px + jx;
+                                        top.t[1] = 2 * py + jy;
+                                        top.t[2] = 2 * pz + jz;
+                                        if (!node_valid(g, L, top.t, top.ang)) continue;
+                                        if ((rc = vec_push(&pending, &top))) goto done;
+                                    }
+    score_vec(m, scan, k, g, &pending, threads);
+    res->initial_size = pending.n;
+    res->nodes_scored = pending.n;
+    for (int64_t i = 0; i < pending.n; ++i) {
+        if (pending.v[i].score < threshold) continue;
+        pending.v[i].seq = seq++;
+        if ((rc = heap_push(&heap, &pending.v[i]))) goto done;
+        res->initial_kept++;
+    }
+    pending.n = 0;
+
+    for (;;) {
+        if (max_scored > 0 && res->nodes_scored >= max_scored) { res->found = -1; goto done; }
+        int flush = 0;
+        if (heap.n == 0) {
+            if (pending.n == 0) break;
+            flush = 1;                                     /* termination flush */
+        } else {
+            orc_node c = heap_pop(&heap);
+            if (c.score < best) continue;                  /* pruned */
+            if (c.level == 0) {
+                res->leaves_accepted++;
+                if (!have_match || c.score > best || leaf_lex_less(&c, &match)) match = c;
+                have_match = 1;
+                best = c.score;
+            } else {
+                res->nodes_expanded++;
+                if ((rc = branch(g, &c, &pending))) goto done;
+            }
+            if (pending.n > batch) flush = 1;
+        }
+        if (flush) {
+            score_vec(m, scan, k, g, &pending, threads);
+            if (trace_flush && res->flushes < trace_cap) trace_flush[res->flushes] = pending.n;
+            res->flushes++;
+            res->nodes_scored += pending.n;
+            for (int64_t i = 0; i < pending.n; ++i) {
+                orc_node *ch = &pending.v[i];
+                res->bound_checks++;
+                if (ch->score > ch->parent_score) {
+                    res->bound_violations++;
+                    res->violation_excess_sum +=
+                        (double)(ch->score - ch->parent_score) / (double)(ch->parent_score > 0 ? ch->parent_score : 1);
+                }
+                ch->seq = seq++;
+                if ((rc = heap_push(&heap, ch))) goto done;
+            }
+            pending.n = 0;
+        }
+    }
+    if (have_match) {
+        res->found = 1;
+        res->score = match.score;
+        for (int ax = 0; ax < 3; ++ax) {
+            res->leaf[ax] = match.t[ax];
+            res->leaf[3 + ax] = match.ang[ax];
+        }
+        decode_pose(g, res->leaf, res->pose);
+    }
+done:
+    free(heap.v);
+    free(pending.v);
+    return rc;
+}
+
+/*
+ * Exhaustive search over the leaf set (the full search that branch and bound
+ * must equal, Sec. III-B): argmax of the level-0 score over all valid leaves
+ * with score >= threshold, ties to the lexicographically smallest index.
+ */
+int orc_bruteforce(const orc_map *m, const float *scan, int64_t k, const orc_grid *g, int32_t threshold,
+                   int32_t threads, orc_result *res)
+{
+    memset(res, 0, sizeof(*res));
+    int64_t nx = g->hi[0] - g->lo[0] + 1, ny = g->hi[1] - g->lo[1] + 1, nz = g->hi[2] - g->lo[2] + 1;
+    int64_t na = g->n[0][0], nb = g->n[1][0], ng = g->n[2][0];
+    int64_t total = nx * ny * nz * na * nb * ng;
+    int32_t *sc = (int32_t *)malloc((size_t)total * sizeof(int32_t));
+    if (!sc) return ORC_ERR_OOM;
+#pragma omp parallel for schedule(dynamic, 64) num_threads(threads > 0 ? threads : 1)
+    for (int64_t i = 0; i < total; ++i) {
+        int64_t q = i;
+        int32_t ig = (int32_t)(q % ng); q /= ng;
+        int32_t ib = (int32_t)(q % nb); q /= nb;
+        int32_t ia = (int32_t)(q % na); q /= na;
+        int32_t z = (int32_t)(q % nz) + g->lo[2]; q /= nz;
+        int32_t y = (int32_t)(q % ny) + g->lo[1]; q /= ny;
+        int32_t x = (int32_t)q + g->lo[0];
+        sc[i] = orc_score(m, scan, k, g, 0, x, y, z, ia, ib, ig);
+    }
+    int64_t arg = -1;
+    int32_t best = threshold;
+    for (int64_t i = 0; i < total; ++i)      /* row-major order is lexicographic order */
+        if (sc[i] > best || (sc[i] == best && arg < 0)) { best = sc[i]; arg = i; }
+    res->nodes_scored = total;
+    if (arg >= 0) {
+        int64_t q = arg;
+        res->leaf[5] = (int32_t)(q % ng); q /= ng;
+        res->leaf[4] = (int32_t)(q % nb); q /= nb;
+        res->leaf[3] = (int32_t)(q % na); q /= na;
+        res->leaf[2] = (int32_t)(q % nz) + g->lo[2]; q /= nz;
+        res->leaf[1] = (int32_t)(q % ny) + g->lo[1]; q /= ny;
+        res->leaf[0] = (int32_t)q + g->lo[0];
+        res->found = 1;
+        res->score = best;
+        decode_pose(g, res->leaf, res->pose);
+    }
+    free(sc);
+    return ORC_OK;
+}
+
+/* Score of every valid leaf in lexicographic order (tests on tiny grids). */
+int64_t orc_all_leaf_scores(const orc_map *m, const float *scan, int64_t k, const orc_grid *g,
+                            int32_t *out, int64_t cap, int32_t threads)
+{
+    int64_t nx = g->hi[0] - g->lo[0] + 1, ny = g->hi[1] - g->lo[1] + 1, nz = g->hi[2] - g->lo[2] + 1;
+    int64_t na = g->n[0][0], nb = g->n[1][0], ng = g->n[2][0];
+    int64_t total = nx * ny * nz * na * nb * ng;
+    if (total > cap) return total;
+#pragma omp parallel for schedule(dynamic, 64) num_threads(threads > 0 ? threads : 1)
+    for (int64_t i = 0; i < total; ++i) {
+        int64_t q = i;
+        int32_t ig = (int32_t)(q % ng); q /= ng;
+        int32_t ib = (int32_t)(q % nb); q /= nb;
+        int32_t ia = (int32_t)(q % na); q /= na;
+        int32_t z = (int32_t)(q % nz) + g->lo[2]; q /= nz;
+        int32_t y = (int32_t)(q % ny) + g->lo[1]; q /= ny;
+        int32_t x = (int32_t)q + g->lo[0];
+        out[i] = orc_score(m, scan, k, g, 0, x, y, z, ia, ib, ig);
+    }
+    return total;
+}
+
+/* Children of one node, in the branching order used by orc_localize
+ * (7 int32 per child: level, x, y, z, roll, pitch, yaw).  Returns the count. */
+int64_t orc_children(const orc_grid *g, const int32_t *node, int32_t *out, int64_t cap)
+{
+    orc_node c;
+    memset(&c, 0, sizeof(c));
+    c.level = node[0];
+    if (c.level < 1 || c.level > g->levels) return 0;
+    for (int ax = 0; ax < 3; ++ax) { c.t[ax] = node[1 + ax]; c.ang[ax] = node[4 + ax]; }
+    node_vec v = {0};
+    if (branch(g, &c, &v)) { free(v.v); return -1; }
+    int64_t n = v.n;
+    for (int64_t i = 0; i < n && i < cap; ++i) {
+        out[7 * i] = v.v[i].level;
+        for (int ax = 0; ax < 3; ++ax) { out[7 * i + 1 + ax] = v.v[i].t[ax]; out[7 * i + 4 + ax] = v.v[i].ang[ax]; }
+    }
+    free(v.v);
+    return n;
+}
+
+/* Size of the orc_grid and orc_result structs, so that the loader can check its layout. */
+int64_t orc_sizeof_grid(void) { return (int64_t)sizeof(orc_grid); }
+int64_t orc_sizeof_result(void) { return (int64_t)sizeof(orc_result); }

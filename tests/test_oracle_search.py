@@ -1,0 +1,201 @@
+"""Pins for the oracle's batched best-first branch and bound (Alg. 2, Sec. III-E).
+
+  * Exactness: with translation-only branching (Table I, configurations
+    (d)-(f)) the bound is valid, so branch and bound must return the full
+    search's optimum (Sec. III-B): the argmax of the leaf score with the
+    lexicographically smallest leaf on ties, for every batch size b.  The full
+    search is an exhaustive scan of all leaves (argmax taken by numpy here).
+  * The bound invariant parent >= child, exhaustively on tiny grids, in
+    translation-only mode (dilated coarse levels, Sec. III-C).
+  * Special cases: l_max = 0 is the full search; a threshold above K finds
+    nothing and branches nothing.
+  * Known-pose recovery on noise-free scans, and the paper's success criterion
+    (2.0 m, 0.05 rad, Sec. IV) on noisy scans of the room.
+  * Schedule invariants of the node counters.  The exact node counts of the
+    schedule have no external pin (the paper prints none): parity unpinned.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+
+def tiny_case(seed, k=200, translation_only=True, rp_deg=0.0, levels=3, z_w=0.0):
+    scene = synth.tiny_scene(seed, n_map=500)
+    scan = synth.scan_scene(scene, seed, k, z=1.0, rp_deg=max(rp_deg, 0.5), n_beams=16, n_az=256,
+                            max_range=12.0).points
+    m = oracle.Map(scene.points, 0.5, levels)
+    rp = math.radians(rp_deg)
+    lo = np.array([-2, -2, 1.0 - z_w, -rp, -rp, 0.0], np.float32)
+    hi = np.array([2, 2, 1.0 + z_w, rp, rp, 2 * math.pi], np.float32)
+    return oracle.Search(m, scan, lo, hi, translation_only=translation_only)
+
+
+def numpy_full_search(s, threshold):
+    sc = s.all_leaf_scores(threads=8)
+    flat = sc.ravel()
+    i = int(np.argmax(flat))               # first maximum in row-major = lexicographic order
+    if flat[i] < threshold:
+        return None
+    idx = np.unravel_index(i, sc.shape)
+    leaf = [int(idx[0]) + s.lo[0], int(idx[1]) + s.lo[1], int(idx[2]) + s.lo[2],
+            int(idx[3]), int(idx[4]), int(idx[5])]
+    return int(flat[i]), leaf
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+@pytest.mark.parametrize("frac", [0.0, 0.5, 0.9])
+def test_translation_only_bnb_equals_full_search(seed, frac):
+    s = tiny_case(seed)
+    T = int(math.ceil(frac * s.k))
+    want = numpy_full_search(s, T)
+    bf = s.bruteforce(T, threads=8)
+    if want is None:
+        assert bf["found"] == 0
+    else:
+        assert bf["found"] == 1 and bf["score"] == want[0] and bf["leaf"] == want[1]
+    for b in (1, 7, 64, 10000):
+        r = s.localize(T, batch=b, threads=8)
+        assert r["found"] == bf["found"], b
+        if bf["found"]:
+            assert r["score"] == bf["score"] and r["leaf"] == bf["leaf"], b
+
+
+def test_translation_only_with_z_and_tilt_axes():
+    s = tiny_case(5, k=120, rp_deg=2.0, z_w=0.5)
+    T = int(0.6 * s.k)
+    bf = s.bruteforce(T, threads=8)
+    for b in (3, 500):
+        r = s.localize(T, batch=b, threads=8)
+        assert (r["found"], r["score"], r["leaf"]) == (bf["found"], bf["score"], bf["leaf"])
+
+
+def all_nodes(s, level):
+    out = []
+    for x in range(s.lo[0] >> level, (s.hi[0] >> level) + 1):
+        for y in range(s.lo[1] >> level, (s.hi[1] >> level) + 1):
+            for z in range(s.lo[2] >> level, (s.hi[2] >> level) + 1):
+                for a in range(s.n(0, level)):
+                    for b in range(s.n(1, level)):
+                        for c in range(s.n(2, level)):
+                            out.append((level, x, y, z, a, b, c))
+    return np.array(out, np.int32)
+
+
+@pytest.mark.parametrize("seed", [0, 3])
+def test_bound_invariant_translation_only(seed):
+    """Every child's score is at most its parent's (exact with the dilated map)."""
+    s = tiny_case(seed, k=150, rp_deg=1.0, z_w=0.5)
+    checked = 0
+    for level in range(1, 4):
+        nodes = all_nodes(s, level)
+        ps = s.score_nodes(nodes, threads=8)
+        for nd, p in zip(nodes, ps):
+            ch = s.children(nd)
+            if len(ch) == 0:
+                continue
+            cs = s.score_nodes(ch, threads=1)
+            assert cs.max() <= p, (nd, p, cs.max())
+            checked += len(ch)
+    assert checked > 10000
+
+
+def test_rotational_branching_violations_are_rare():
+    """With rotational branching the bound is approximate (Sec. III-D); the
+    oracle counts children scoring above their parent."""
+    s = tiny_case(1, k=300, translation_only=False, rp_deg=2.0)
+    r = s.localize(int(0.5 * s.k), batch=64, threads=8)
+    assert r["bound_checks"] > 0
+    assert r["bound_violations"] / r["bound_checks"] < 0.05
+
+
+@pytest.mark.parametrize("translation_only", [False, True])
+def test_single_level_is_full_search(translation_only):
+    s = tiny_case(2, k=100, translation_only=translation_only, rp_deg=1.0, levels=0)
+    for T in (0, 60):
+        bf = s.bruteforce(T, threads=8)
+        r = s.localize(T, batch=50, threads=8)
+        assert (r["found"], r["score"], r["leaf"]) == (bf["found"], bf["score"], bf["leaf"])
+        assert r["nodes_expanded"] == 0 and r["flushes"] == 0
+
+
+def test_threshold_above_k_finds_nothing():
+    s = tiny_case(0, k=100, translation_only=False, rp_deg=1.0)
+    r = s.localize(s.k + 1, batch=100, threads=8)
+    assert r["found"] == 0 and r["nodes_expanded"] == 0 and r["initial_kept"] == 0
+    assert r["nodes_scored"] == r["initial_size"] > 0
+
+
+@pytest.mark.parametrize("b", [1, 10, 333])
+def test_schedule_counter_invariants(b):
+    s = tiny_case(4, k=150, translation_only=False, rp_deg=2.0)
+    r = s.localize(int(0.7 * s.k), batch=b, threads=8, trace_cap=1 << 20)
+    sizes = r["flush_sizes"]
+    assert r["nodes_scored"] == r["initial_size"] + sum(sizes)
+    assert len(sizes) == r["flushes"]
+    fan = max(s.a(0, l) * s.a(1, l) * s.a(2, l) * 8 for l in range(1, 4))
+    # a flush is triggered by exceeding b, or by the termination rule (queue empty)
+    assert all(1 <= n <= b + fan for n in sizes)
+    assert sum(n > b for n in sizes) >= len(sizes) - r["nodes_expanded"]
+    assert r["bound_checks"] == sum(sizes)
+
+
+def known_pose_scan(scene, t, angles, radius, n, seed):
+    """Map points within `radius` of t, expressed in the frame of pose (t, angles)."""
+    rng = np.random.default_rng(seed)
+    d = np.linalg.norm(scene.points.astype(np.float64) - t, axis=1)
+    cand = np.nonzero(d < radius)[0]
+    pts = scene.points[rng.choice(cand, size=n, replace=False)].astype(np.float64)
+    R = synth.rotation_zyx(*angles)
+    return ((pts - t) @ R).astype(np.float32)    # R^T (m - t), row-vector form
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_noise_free_known_pose_recovery(seed):
+    """A noise-free scan taken at a leaf-grid rotation and a translation inside
+    a leaf cell scores K at that leaf (dilated leaf level), and translation-only
+    branch and bound returns a K-scoring leaf."""
+    rng = np.random.default_rng(seed)
+    scene = synth.room_scene(seed)
+    r, L = 0.5, 3
+    m = oracle.Map(scene.points, r, L)
+    ti = np.array([rng.integers(-8, 8), rng.integers(-8, 8), 3])
+    frac = rng.uniform(0.05, 0.95, size=3)
+    t = (ti + frac) * r
+    pts_probe = known_pose_scan(scene, t, (0, 0, 0), 9.0, 300, seed)
+    lo = np.array([-6, -6, 1.5, 0, 0, 0], np.float32)
+    hi = np.array([6, 6, 1.5, 0, 0, 2 * math.pi], np.float32)
+    lo[:2] = t[:2] - 2.0
+    hi[:2] = t[:2] + 2.0
+    probe = oracle.Search(m, pts_probe, lo, hi, translation_only=True)
+    # d_max does not depend on the rotation, so the yaw grid is known before the scan is rotated
+    iy = int(rng.integers(0, probe.n(2, 0)))
+    yaw = float(lo[5]) + probe.dprime(2, 0) * (iy + 0.5)
+    scan = known_pose_scan(scene, t, (0, 0, yaw), 9.0, 300, seed)
+    s = oracle.Search(m, scan, lo, hi, translation_only=True)
+    assert s.n(2, 0) == probe.n(2, 0)
+    assert s.score(0, int(ti[0]), int(ti[1]), int(ti[2]), 0, 0, iy) == s.k
+    res = s.localize(s.k, batch=1000, threads=8)
+    assert res["found"] == 1 and res["score"] == s.k
+    assert abs(res["pose"][0] - t[0]) < 2 * r and abs(res["pose"][1] - t[1]) < 2 * r
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_room_success_criterion(seed):
+    """Tiny-indoor configuration: noisy 2,000-point scans are localized within
+    2.0 m and 0.05 rad (the success criterion of Sec. IV)."""
+    scene = synth.room_scene(0)
+    m = oracle.Map(scene.points, 0.5, 4)
+    sc = synth.scan_scene(scene, seed, 2000, z=1.5, z_jitter=0.25, rp_deg=2.0)
+    lo, hi = synth.search_range_room()
+    s = oracle.Search(m, sc.points, lo, hi)
+    res = s.localize(synth.threshold_95(2000), batch=10000, threads=8)
+    assert res["found"] == 1
+    err_t = np.linalg.norm(np.array(res["pose"][:3]) - sc.pose[:3])
+    R_est = synth.rotation_zyx(*res["pose"][3:])
+    R_true = synth.rotation_zyx(*sc.pose[3:])
+    err_r = math.acos(max(-1.0, min(1.0, (np.trace(R_est.T @ R_true) - 1) / 2)))
+    assert err_t < 2.0 and err_r < 0.05, (err_t, err_r)
