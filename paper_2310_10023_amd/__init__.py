@@ -1,0 +1,261 @@
+"""Python binding of libbbs: 3D-BBS batched branch-and-bound scan matching on
+AMD Instinct MI355X (gfx950).
+
+Argument marshalling only: every step of the search runs in the HIP library
+(`_lib/libbbs.so`, built by `python -m paper_2310_10023_amd.build`).  Inputs may
+be numpy arrays (host) or torch tensors on the GPU (device pointers are passed
+straight through, with torch's current stream).  There is no CPU fallback:
+if the library is missing, importing the library functions raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+__all__ = ["LibraryMissing", "BbsError", "Map", "Workspace", "localize", "score_nodes", "lib", "library_path",
+           "EXPORTED_SYMBOLS"]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "_lib", "libbbs.so")
+MAX_LEVELS = 16
+
+EXPORTED_SYMBOLS = (
+    "bbs_default_options", "bbs_abi_version", "bbs_last_error", "bbs_build_map", "bbs_free_map", "bbs_map_info",
+    "bbs_map_dump_level", "bbs_map_contains", "bbs_workspace_create", "bbs_workspace_free", "bbs_localize",
+    "bbs_score_nodes",
+)
+
+STATUS = {0: "OK", -1: "INVALID_ARG", -2: "OOM", -3: "DEVICE", -4: "QUEUE_OVERFLOW", -5: "INTERNAL"}
+
+
+class LibraryMissing(ImportError):
+    pass
+
+
+class BbsError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class SearchRange(C.Structure):
+    _fields_ = [("min", C.c_float * 6), ("max", C.c_float * 6)]
+
+
+class Options(C.Structure):
+    _fields_ = [("batch_size", C.c_int32), ("translation_only", C.c_int32), ("profile", C.c_int32),
+                ("reserved0", C.c_int32), ("stream", C.c_void_p), ("reserved", C.c_int64 * 4)]
+
+
+class Result(C.Structure):
+    _fields_ = [("found", C.c_int32), ("score", C.c_int32), ("leaf", C.c_int32 * 6), ("pose", C.c_float * 6),
+                ("nodes_expanded", C.c_int64), ("nodes_scored", C.c_int64), ("flushes", C.c_int64),
+                ("leaves_accepted", C.c_int64), ("initial_size", C.c_int64), ("initial_kept", C.c_int64),
+                ("score_kernel_ms", C.c_double), ("score_launches", C.c_int64), ("score_pairs", C.c_int64),
+                ("phase_ms", C.c_double * 4)]
+
+    def as_dict(self):
+        return {"found": self.found, "score": self.score, "leaf": list(self.leaf), "pose": list(self.pose),
+                "nodes_expanded": self.nodes_expanded, "nodes_scored": self.nodes_scored, "flushes": self.flushes,
+                "leaves_accepted": self.leaves_accepted, "initial_size": self.initial_size,
+                "initial_kept": self.initial_kept, "score_kernel_ms": self.score_kernel_ms,
+                "score_launches": self.score_launches, "score_pairs": self.score_pairs,
+                "phase_ms": list(self.phase_ms)}
+
+
+_lib = None
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def lib():
+    """The loaded libbbs (raises LibraryMissing if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise LibraryMissing(f"libbbs is not built ({_LIB_PATH}); run python -m paper_2310_10023_amd.build")
+        L = C.CDLL(_LIB_PATH)
+        P, I32, I64, F = C.c_void_p, C.c_int32, C.c_int64, C.c_float
+        L.bbs_default_options.argtypes = [C.POINTER(Options)]
+        L.bbs_abi_version.restype = I32
+        L.bbs_last_error.restype = C.c_char_p
+        L.bbs_build_map.argtypes = [P, I64, I32, F, I32, I32, P, C.POINTER(P)]
+        L.bbs_build_map.restype = C.c_int
+        L.bbs_free_map.argtypes = [P]
+        L.bbs_map_info.argtypes = [P, C.POINTER(I32), C.POINTER(F), P, P, P]
+        L.bbs_map_info.restype = C.c_int
+        L.bbs_map_dump_level.argtypes = [P, I32, P, I64, C.POINTER(I64)]
+        L.bbs_map_dump_level.restype = C.c_int
+        L.bbs_map_contains.argtypes = [P, I32, P, I64, P]
+        L.bbs_map_contains.restype = C.c_int
+        L.bbs_workspace_create.argtypes = [I64, C.POINTER(P)]
+        L.bbs_workspace_create.restype = C.c_int
+        L.bbs_workspace_free.argtypes = [P]
+        L.bbs_localize.argtypes = [P, P, P, I64, I32, C.POINTER(SearchRange), I32, C.POINTER(Options),
+                                   C.POINTER(Result)]
+        L.bbs_localize.restype = C.c_int
+        L.bbs_score_nodes.argtypes = [P, P, I64, C.POINTER(SearchRange), I32, P, I64, P]
+        L.bbs_score_nodes.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != 0:
+        raise BbsError(rc, lib().bbs_last_error().decode())
+
+
+def _points(x, name):
+    """(pointer, count, on_device, keepalive) of an n x 3 float32 point array."""
+    try:
+        import torch
+        if isinstance(x, torch.Tensor):
+            if x.dtype != torch.float32 or x.dim() != 2 or x.shape[1] != 3:
+                raise ValueError(f"{name} must be an (n, 3) float32 tensor")
+            if x.is_cuda:
+                x = x.contiguous()
+                return x.data_ptr(), x.shape[0], 1, x
+            x = x.numpy()
+    except ImportError:
+        pass
+    a = np.ascontiguousarray(x, dtype=np.float32).reshape(-1, 3)
+    return a.ctypes.data, a.shape[0], 0, a
+
+
+def _stream(stream):
+    if stream is not None:
+        return stream
+    try:
+        import torch
+        if torch.cuda.is_available() and torch.cuda.is_initialized():
+            return torch.cuda.current_stream().cuda_stream
+    except ImportError:
+        pass
+    return None
+
+
+def _range(rmin, rmax):
+    r = SearchRange()
+    lo = np.asarray(rmin, dtype=np.float32).reshape(6)
+    hi = np.asarray(rmax, dtype=np.float32).reshape(6)
+    for i in range(6):
+        r.min[i] = float(lo[i])
+        r.max[i] = float(hi[i])
+    return r
+
+
+class Map:
+    """Sparse multi-resolution voxel map (Sec. III-C) resident on the GPU."""
+
+    def __init__(self, points, min_res: float, levels: int, dilate_leaf: bool = True, stream=None):
+        ptr, n, dev, keep = _points(points, "points")
+        h = C.c_void_p()
+        _check(lib().bbs_build_map(ptr, n, dev, float(min_res), int(levels), int(dilate_leaf), _stream(stream),
+                                   C.byref(h)))
+        del keep
+        self._h = h
+        self.min_res = float(np.float32(min_res))
+        self.levels = int(levels)
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().bbs_free_map(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> dict:
+        lv = C.c_int32()
+        r = C.c_float()
+        vox = np.zeros(MAX_LEVELS, np.int64)
+        slots = np.zeros(MAX_LEVELS, np.int64)
+        bricks = np.zeros(MAX_LEVELS, np.int64)
+        _check(lib().bbs_map_info(self._h, C.byref(lv), C.byref(r), vox.ctypes.data, slots.ctypes.data,
+                                  bricks.ctypes.data))
+        n = lv.value + 1
+        return {"levels": lv.value, "min_res": r.value, "voxels": vox[:n].tolist(), "slots": slots[:n].tolist(),
+                "bricks": bricks[:n].tolist()}
+
+    def dump_level(self, level: int) -> np.ndarray:
+        """Voxels of D_level as an (m, 3) int32 array, sorted lexicographically."""
+        cnt = C.c_int64()
+        _check(lib().bbs_map_dump_level(self._h, level, None, 0, C.byref(cnt)))
+        out = np.zeros((max(cnt.value, 1), 3), np.int32)
+        _check(lib().bbs_map_dump_level(self._h, level, out.ctypes.data, cnt.value, C.byref(cnt)))
+        out = out[:cnt.value]
+        return out[np.lexsort((out[:, 2], out[:, 1], out[:, 0]))]
+
+    def contains(self, level: int, voxels) -> np.ndarray:
+        v = np.ascontiguousarray(voxels, dtype=np.int32).reshape(-1, 3)
+        out = np.zeros(len(v), np.uint8)
+        _check(lib().bbs_map_contains(self._h, level, v.ctypes.data, len(v), out.ctypes.data))
+        return out.astype(bool)
+
+
+class Workspace:
+    """Device node queue and buffers for one search at a time."""
+
+    def __init__(self, max_queue_nodes: int = 0):
+        h = C.c_void_p()
+        _check(lib().bbs_workspace_create(int(max_queue_nodes), C.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().bbs_workspace_free(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+
+def localize(bmap: Map, scan, rmin, rmax, score_threshold: int, *, batch_size: int = 10000,
+             translation_only: bool = False, profile: bool = False, workspace: Workspace | None = None,
+             stream=None) -> dict:
+    """Global localization of one scan (Alg. 2 on the GPU).  Returns the result
+    fields as a dict (found, score, leaf, pose, node counters, timings)."""
+    ptr, k, dev, keep = _points(scan, "scan")
+    opt = Options()
+    lib().bbs_default_options(C.byref(opt))
+    opt.batch_size = int(batch_size)
+    opt.translation_only = int(translation_only)
+    opt.profile = int(profile)
+    st = _stream(stream)
+    opt.stream = st
+    rng = _range(rmin, rmax)
+    res = Result()
+    _check(lib().bbs_localize(bmap.handle, workspace.handle if workspace else None, ptr, k, dev, C.byref(rng),
+                              int(score_threshold), C.byref(opt), C.byref(res)))
+    del keep
+    return res.as_dict()
+
+
+def score_nodes(bmap: Map, scan, rmin, rmax, nodes, translation_only: bool = False) -> np.ndarray:
+    """Scores of arbitrary nodes (rows level, x, y, z, i_roll, i_pitch, i_yaw)
+    computed by the device scoring kernel."""
+    s = np.ascontiguousarray(scan, dtype=np.float32).reshape(-1, 3)
+    nd = np.ascontiguousarray(nodes, dtype=np.int32).reshape(-1, 7)
+    out = np.zeros(len(nd), np.int32)
+    rng = _range(rmin, rmax)
+    _check(lib().bbs_score_nodes(bmap.handle, s.ctypes.data, len(s), C.byref(rng), int(translation_only),
+                                 nd.ctypes.data, len(nd), out.ctypes.data))
+    return out

@@ -1,0 +1,603 @@
+// Multi-resolution voxel map on the device (Sec. III-C).
+//
+// Level l holds D_l: the voxels floor(floor(m / r) / 2^l) of the map points m
+// and, for dilated levels, every v - j with j in {0,1}^3 (the set V_add of
+// Sec. III-C).  Build steps, all on the device:
+//   1. voxelize: level-0 voxel of every point (float32 division, floor);
+//   2. dedupe: a set of distinct level-0 voxels (open addressing, CAS);
+//   3. per level: shift, dilate and OR each voxel into every brick that
+//      covers it (a scratch table sized from the voxel count, grown and
+//      rebuilt if it would pass half load);
+//   4. compact: re-insert the bricks into a table at load <= 1/2 and record
+//      the level's brick bounding box and voxel count.
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <vector>
+
+#include "bbs_internal.h"
+
+namespace bbs {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr unsigned long long kEmpty64 = 0xFFFFFFFFFFFFFFFFull;
+constexpr int32_t kPackBias = 1 << 20;
+
+inline int grid_for(int64_t n, int threads = kThreads, int cap = 8192)
+{
+    int64_t g = (n + threads - 1) / threads;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(g, cap));
+}
+
+inline uint64_t next_pow2(uint64_t v)
+{
+    uint64_t p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+__device__ inline unsigned long long pack_voxel(int32_t x, int32_t y, int32_t z)
+{
+    return ((unsigned long long)(uint32_t)(x + kPackBias) << 42) |
+           ((unsigned long long)(uint32_t)(y + kPackBias) << 21) | (unsigned long long)(uint32_t)(z + kPackBias);
+}
+
+__device__ inline void unpack_voxel(unsigned long long k, int32_t &x, int32_t &y, int32_t &z)
+{
+    x = (int32_t)((k >> 42) & 0x1FFFFF) - kPackBias;
+    y = (int32_t)((k >> 21) & 0x1FFFFF) - kPackBias;
+    z = (int32_t)(k & 0x1FFFFF) - kPackBias;
+}
+
+__device__ inline unsigned long long mix64(unsigned long long x)
+{
+    x ^= x >> 30;
+    x *= 0xbf58476d1ce4e5b9ull;
+    x ^= x >> 27;
+    x *= 0x94d049bb133111ebull;
+    x ^= x >> 31;
+    return x;
+}
+
+__global__ void k_fill_slots(Slot *s, uint64_t n)
+{
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        s[i].head = make_uint4(kEmptyLo, kEmptyHi, 0u, 0u);
+        s[i].bits = make_uint4(0u, 0u, 0u, 0u);
+    }
+}
+
+__global__ void k_fill_u64(unsigned long long *p, uint64_t n, unsigned long long v)
+{
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// Level-0 voxel of each point: floor(m / r) in float32.  err |= 1 on a
+// non-finite coordinate or a voxel outside (-2^20 + 2, 2^20 - 2).
+__global__ void k_voxelize(const float *xyz, int64_t n, float r, float inv_r, int r_pow2, unsigned long long *keys,
+                           int *err)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        int32_t v[3];
+        bool ok = true;
+        for (int a = 0; a < 3; ++a) {
+            float c = xyz[3 * i + a];
+            if (!isfinite(c)) ok = false;
+            float q = r_pow2 ? c * inv_r : c / r;
+            float f = floorf(q);
+            if (!(f >= -(float)kVoxelLimit + 2.0f && f < (float)kVoxelLimit - 2.0f)) ok = false;
+            v[a] = ok ? (int32_t)f : 0;
+        }
+        if (!ok) atomicOr(err, 1);
+        keys[i] = pack_voxel(v[0], v[1], v[2]);
+    }
+}
+
+// Distinct level-0 voxels.  err |= 2 if the set runs full.
+__global__ void k_dedupe(const unsigned long long *keys, int64_t n, unsigned long long *set, uint64_t cap_mask,
+                         unsigned long long *uniq, unsigned long long *n_uniq, int *err)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        unsigned long long key = keys[i];
+        uint64_t h = mix64(key) & cap_mask;
+        bool done = false;
+        for (uint64_t probe = 0; probe <= cap_mask; ++probe) {
+            unsigned long long old = atomicCAS(&set[h], kEmpty64, key);
+            if (old == kEmpty64) {
+                unsigned long long pos = atomicAdd(n_uniq, 1ull);
+                uniq[pos] = key;
+                done = true;
+                break;
+            }
+            if (old == key) {
+                done = true;
+                break;
+            }
+            h = (h + 1) & cap_mask;
+        }
+        if (!done) atomicOr(err, 2);
+    }
+}
+
+// Find the slot of brick (bx, by, bz), inserting it if absent.  Returns
+// UINT32_MAX if the table has no room left.
+__device__ inline uint32_t find_or_insert(Slot *table, uint32_t cap_mask, int32_t bx, int32_t by, int32_t bz,
+                                          unsigned long long *n_bricks)
+{
+    unsigned long long key = brick_key(bx, by, bz);
+    uint32_t h = brick_hash(bx, by, bz) & cap_mask;
+    for (uint32_t probe = 0; probe <= cap_mask; ++probe) {
+        unsigned long long *kp = reinterpret_cast<unsigned long long *>(&table[h].head);
+        unsigned long long old = atomicCAS(kp, kEmpty64, key);
+        if (old == kEmpty64) {
+            atomicAdd(n_bricks, 1ull);
+            return h;
+        }
+        if (old == key) return h;
+        h = (h + 1) & cap_mask;
+    }
+    return 0xFFFFFFFFu;
+}
+
+// OR every voxel of D_level into each brick that covers it.  A voxel v lies in
+// brick floor(v / 4) and, on each axis where v is a multiple of 4, also in the
+// brick below (as its fifth layer).
+__global__ void k_insert_bricks(const unsigned long long *uniq, int64_t n_uniq, int level, int dilate, Slot *table,
+                                uint32_t cap_mask, unsigned long long *n_bricks, int *err)
+{
+    const int jmax = dilate ? 1 : 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_uniq; i += (int64_t)gridDim.x * blockDim.x) {
+        int32_t v0[3];
+        unpack_voxel(uniq[i], v0[0], v0[1], v0[2]);
+        int32_t w[3] = {v0[0] >> level, v0[1] >> level, v0[2] >> level};
+        for (int jx = 0; jx <= jmax; ++jx)
+            for (int jy = 0; jy <= jmax; ++jy)
+                for (int jz = 0; jz <= jmax; ++jz) {
+                    int32_t v[3] = {w[0] - jx, w[1] - jy, w[2] - jz};
+                    int32_t b0[3];
+                    int nb[3];
+                    for (int a = 0; a < 3; ++a) {
+                        b0[a] = v[a] >> 2;
+                        nb[a] = ((v[a] & 3) == 0) ? 2 : 1;
+                    }
+                    for (int ex = 0; ex < nb[0]; ++ex)
+                        for (int ey = 0; ey < nb[1]; ++ey)
+                            for (int ez = 0; ez < nb[2]; ++ez) {
+                                int32_t bx = b0[0] - ex, by = b0[1] - ey, bz = b0[2] - ez;
+                                int dx = v[0] - 4 * bx, dy = v[1] - 4 * by, dz = v[2] - 4 * bz;
+                                int bit = (dz * 5 + dy) * 5 + dx;
+                                uint32_t s = find_or_insert(table, cap_mask, bx, by, bz, n_bricks);
+                                if (s == 0xFFFFFFFFu) {
+                                    atomicOr(err, 4);
+                                    continue;
+                                }
+                                uint32_t *words = reinterpret_cast<uint32_t *>(&table[s].bits);
+                                atomicOr(&words[bit >> 5], 1u << (bit & 31));
+                            }
+                }
+    }
+}
+
+__device__ inline int popc4(uint4 a, uint4 m)
+{
+    return __popc(a.x & m.x) + __popc(a.y & m.y) + __popc(a.z & m.z) + __popc(a.w & m.w);
+}
+
+// Move the bricks of a scratch table into the final one; reduce the brick
+// bounding box and count each voxel once (in its home brick, dx, dy, dz <= 3).
+__global__ void k_compact(const Slot *src, uint64_t src_n, Slot *dst, uint32_t dst_mask, uint4 home,
+                          int *bbox, unsigned long long *n_voxels, int *err)
+{
+    __shared__ int sb[6][kThreads];
+    __shared__ unsigned long long sv[kThreads];
+    int mn[3] = {INT_MAX, INT_MAX, INT_MAX}, mx[3] = {INT_MIN, INT_MIN, INT_MIN};
+    unsigned long long cnt = 0;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < src_n; i += (uint64_t)gridDim.x * blockDim.x) {
+        uint4 hd = src[i].head;
+        if (hd.x == kEmptyLo && hd.y == kEmptyHi) continue;
+        unsigned long long key = ((unsigned long long)hd.y << 32) | hd.x;
+        int32_t b[3] = {(int32_t)((key >> 38) & 0x7FFFF) - kBrickBias, (int32_t)((key >> 19) & 0x7FFFF) - kBrickBias,
+                        (int32_t)(key & 0x7FFFF) - kBrickBias};
+        uint32_t h = brick_hash(b[0], b[1], b[2]) & dst_mask;
+        bool placed = false;
+        for (uint32_t probe = 0; probe <= dst_mask; ++probe) {
+            unsigned long long *kp = reinterpret_cast<unsigned long long *>(&dst[h].head);
+            if (atomicCAS(kp, kEmpty64, key) == kEmpty64) {
+                dst[h].bits = src[i].bits;
+                placed = true;
+                break;
+            }
+            h = (h + 1) & dst_mask;
+        }
+        if (!placed) atomicOr(err, 8);
+        for (int a = 0; a < 3; ++a) {
+            mn[a] = min(mn[a], b[a]);
+            mx[a] = max(mx[a], b[a]);
+        }
+        cnt += (unsigned long long)popc4(src[i].bits, home);
+    }
+    for (int a = 0; a < 3; ++a) {
+        sb[a][threadIdx.x] = mn[a];
+        sb[3 + a][threadIdx.x] = mx[a];
+    }
+    sv[threadIdx.x] = cnt;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            for (int a = 0; a < 3; ++a) {
+                sb[a][threadIdx.x] = min(sb[a][threadIdx.x], sb[a][threadIdx.x + s]);
+                sb[3 + a][threadIdx.x] = max(sb[3 + a][threadIdx.x], sb[3 + a][threadIdx.x + s]);
+            }
+            sv[threadIdx.x] += sv[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        for (int a = 0; a < 3; ++a) {
+            atomicMin(&bbox[a], sb[a][0]);
+            atomicMax(&bbox[3 + a], sb[3 + a][0]);
+        }
+        atomicAdd(n_voxels, sv[0]);
+    }
+}
+
+__global__ void k_dump(const Slot *t, uint64_t n, uint4 home, int32_t *out, uint64_t cap,
+                       unsigned long long *count)
+{
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        uint4 hd = t[i].head;
+        if (hd.x == kEmptyLo && hd.y == kEmptyHi) continue;
+        unsigned long long key = ((unsigned long long)hd.y << 32) | hd.x;
+        int32_t b[3] = {(int32_t)((key >> 38) & 0x7FFFF) - kBrickBias, (int32_t)((key >> 19) & 0x7FFFF) - kBrickBias,
+                        (int32_t)(key & 0x7FFFF) - kBrickBias};
+        uint32_t w[4] = {t[i].bits.x, t[i].bits.y, t[i].bits.z, t[i].bits.w};
+        for (int dz = 0; dz < 4; ++dz)
+            for (int dy = 0; dy < 4; ++dy)
+                for (int dx = 0; dx < 4; ++dx) {
+                    int bit = (dz * 5 + dy) * 5 + dx;
+                    if (!((w[bit >> 5] >> (bit & 31)) & 1u)) continue;
+                    unsigned long long pos = atomicAdd(count, 1ull);
+                    if (pos < cap) {
+                        out[3 * pos + 0] = 4 * b[0] + dx;
+                        out[3 * pos + 1] = 4 * b[1] + dy;
+                        out[3 * pos + 2] = 4 * b[2] + dz;
+                    }
+                }
+    }
+}
+
+__device__ inline bool lookup_bits(const LevelView &lv, int32_t bx, int32_t by, int32_t bz, uint4 &bits)
+{
+    if (bx < lv.bmin[0] || bx > lv.bmax[0] || by < lv.bmin[1] || by > lv.bmax[1] || bz < lv.bmin[2] ||
+        bz > lv.bmax[2])
+        return false;
+    uint32_t klo = brick_key_lo(bx, by, bz), khi = brick_key_hi(bx, by, bz);
+    uint32_t h = brick_hash(bx, by, bz) & lv.cap_mask;
+    for (;;) {
+        uint4 hd = lv.slots[h].head;
+        if (hd.x == klo && hd.y == khi) {
+            bits = lv.slots[h].bits;
+            return true;
+        }
+        if (hd.x == kEmptyLo && hd.y == kEmptyHi) return false;
+        h = (h + 1) & lv.cap_mask;
+    }
+}
+
+// Membership of voxels, read through every brick that covers each voxel; err
+// |= 16 if two covering bricks disagree.
+__global__ void k_contains(LevelView lv, const int32_t *xyz, int64_t n, uint8_t *out, int *err)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        int32_t v[3] = {xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2]};
+        int32_t b0[3];
+        int nb[3];
+        for (int a = 0; a < 3; ++a) {
+            b0[a] = v[a] >> 2;
+            nb[a] = ((v[a] & 3) == 0) ? 2 : 1;
+        }
+        int home = -1;
+        bool mismatch = false;
+        for (int ex = 0; ex < nb[0]; ++ex)
+            for (int ey = 0; ey < nb[1]; ++ey)
+                for (int ez = 0; ez < nb[2]; ++ez) {
+                    int32_t bx = b0[0] - ex, by = b0[1] - ey, bz = b0[2] - ez;
+                    int bit = ((v[2] - 4 * bz) * 5 + (v[1] - 4 * by)) * 5 + (v[0] - 4 * bx);
+                    uint4 bits;
+                    int hit = 0;
+                    if (lookup_bits(lv, bx, by, bz, bits)) {
+                        uint32_t w[4] = {bits.x, bits.y, bits.z, bits.w};
+                        hit = (w[bit >> 5] >> (bit & 31)) & 1u;
+                    }
+                    if (home < 0) home = hit;
+                    else if (hit != home) mismatch = true;
+                }
+        out[i] = (uint8_t)home;
+        if (mismatch) atomicOr(err, 16);
+    }
+}
+
+uint4 home_mask()
+{
+    uint32_t w[4] = {0, 0, 0, 0};
+    for (int dz = 0; dz < 4; ++dz)
+        for (int dy = 0; dy < 4; ++dy)
+            for (int dx = 0; dx < 4; ++dx) {
+                int bit = (dz * 5 + dy) * 5 + dx;
+                w[bit >> 5] |= 1u << (bit & 31);
+            }
+    return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+bool is_pow2_float(float r)
+{
+    int e = 0;
+    float m = std::frexp(r, &e);
+    return m == 0.5f;
+}
+
+struct DevBuf {
+    void *p = nullptr;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf() { reset(); }
+    void reset()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+    }
+    template <class T>
+    T *as() const { return static_cast<T *>(p); }
+};
+
+struct StreamGuard {
+    hipStream_t s = nullptr;
+    bool own = false;
+    ~StreamGuard()
+    {
+        if (own && s) (void)hipStreamDestroy(s);
+    }
+};
+
+}  // namespace
+
+bbs_status alloc_dev(void **p, size_t bytes)
+{
+    hipError_t e = hipMalloc(p, bytes ? bytes : 16);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return fail(BBS_ERR_OOM, std::string("device allocation of ") + std::to_string(bytes) + " bytes failed");
+    }
+    return BBS_OK;
+}
+
+}  // namespace bbs
+
+using namespace bbs;
+
+bbs::MapView bbs_map::view() const
+{
+    MapView v;
+    for (int l = 0; l < kMaxLevels; ++l) {
+        LevelView &lv = v.lv[l];
+        lv.slots = l <= levels ? slots[l] : nullptr;
+        lv.cap_mask = l <= levels ? (uint32_t)(cap[l] - 1) : 0u;
+        for (int a = 0; a < 3; ++a) {
+            lv.bmin[a] = l <= levels ? bmin[l][a] : 1;
+            lv.bmax[a] = l <= levels ? bmax[l][a] : 0;
+        }
+    }
+    return v;
+}
+
+extern "C" void bbs_free_map(bbs_map *map)
+{
+    if (!map) return;
+    for (int l = 0; l < kMaxLevels; ++l)
+        if (map->slots[l]) (void)hipFree(map->slots[l]);
+    delete map;
+}
+
+extern "C" bbs_status bbs_build_map(const float *xyz, int64_t n, int32_t xyz_on_device, float min_res, int32_t levels,
+                                    int32_t dilate_leaf, void *stream, bbs_map **out)
+{
+    if (!out) return fail(BBS_ERR_INVALID_ARG, "bbs_build_map: out is NULL");
+    *out = nullptr;
+    if (!xyz) return fail(BBS_ERR_INVALID_ARG, "bbs_build_map: xyz is NULL");
+    if (n < 1) return fail(BBS_ERR_INVALID_ARG, "bbs_build_map: n must be >= 1");
+    if (n > ((int64_t)1 << 31)) return fail(BBS_ERR_INVALID_ARG, "bbs_build_map: n must be <= 2^31");
+    if (!(min_res > 0.0f) || !std::isfinite(min_res))
+        return fail(BBS_ERR_INVALID_ARG, "bbs_build_map: min_res must be finite and > 0");
+    if (levels < 0 || levels >= kMaxLevels) return fail(BBS_ERR_INVALID_ARG, "bbs_build_map: levels must be in [0, 15]");
+
+    StreamGuard sg;
+    sg.s = static_cast<hipStream_t>(stream);
+    if (!sg.s) {
+        BBS_HIP(hipStreamCreateWithFlags(&sg.s, hipStreamNonBlocking));
+        sg.own = true;
+    }
+    hipStream_t s = sg.s;
+
+    DevBuf dxyz, dkeys, dset, duniq, dcount, derr, dbbox, dvox;
+    const float *pts = xyz;
+    if (!xyz_on_device) {
+        if (alloc_dev(&dxyz.p, (size_t)n * 3 * sizeof(float))) return BBS_ERR_OOM;
+        BBS_HIP(hipMemcpyAsync(dxyz.p, xyz, (size_t)n * 3 * sizeof(float), hipMemcpyHostToDevice, s));
+        pts = dxyz.as<float>();
+    }
+    uint64_t set_cap = next_pow2((uint64_t)n * 2);
+    if (alloc_dev(&dkeys.p, (size_t)n * 8) || alloc_dev(&dset.p, set_cap * 8) || alloc_dev(&duniq.p, (size_t)n * 8) ||
+        alloc_dev(&dcount.p, 64) || alloc_dev(&derr.p, 64) || alloc_dev(&dbbox.p, 64) || alloc_dev(&dvox.p, 64))
+        return BBS_ERR_OOM;
+    BBS_HIP(hipMemsetAsync(dcount.p, 0, 64, s));
+    BBS_HIP(hipMemsetAsync(derr.p, 0, 64, s));
+    bool pow2 = is_pow2_float(min_res);
+    float inv_r = 1.0f / min_res;
+    k_voxelize<<<grid_for(n), kThreads, 0, s>>>(pts, n, min_res, inv_r, pow2 ? 1 : 0, dkeys.as<unsigned long long>(),
+                                                 derr.as<int>());
+    k_fill_u64<<<grid_for((int64_t)set_cap), kThreads, 0, s>>>(dset.as<unsigned long long>(), set_cap, kEmpty64);
+    k_dedupe<<<grid_for(n), kThreads, 0, s>>>(dkeys.as<unsigned long long>(), n, dset.as<unsigned long long>(),
+                                               set_cap - 1, duniq.as<unsigned long long>(),
+                                               dcount.as<unsigned long long>(), derr.as<int>());
+    BBS_HIP(hipGetLastError());
+    unsigned long long n_uniq = 0;
+    int err = 0;
+    BBS_HIP(hipMemcpyAsync(&n_uniq, dcount.p, 8, hipMemcpyDeviceToHost, s));
+    BBS_HIP(hipMemcpyAsync(&err, derr.p, 4, hipMemcpyDeviceToHost, s));
+    BBS_HIP(hipStreamSynchronize(s));
+    if (err & 1)
+        return fail(BBS_ERR_INVALID_ARG,
+                    "bbs_build_map: a map point is not finite or its voxel is outside [-2^20 + 2, 2^20 - 2)");
+    if (err) return fail(BBS_ERR_INTERNAL, "bbs_build_map: voxel set overflow");
+    dkeys.reset();
+    dset.reset();
+    dxyz.reset();
+
+    bbs_map *m = new bbs_map();
+    m->levels = levels;
+    m->r = min_res;
+    m->dilate_leaf = dilate_leaf ? 1 : 0;
+    (void)hipGetDevice(&m->device);
+    const uint4 home = home_mask();
+
+    uint64_t tmp_cap = next_pow2(std::max<uint64_t>(1024, 4 * n_uniq));
+    for (int l = 0; l <= levels; ++l) {
+        int dilate = (l > 0 || dilate_leaf) ? 1 : 0;
+        for (;;) {
+            DevBuf tmp;
+            if (alloc_dev(&tmp.p, tmp_cap * sizeof(Slot))) {
+                bbs_free_map(m);
+                return BBS_ERR_OOM;
+            }
+            BBS_HIP(hipMemsetAsync(dcount.p, 0, 64, s));
+            BBS_HIP(hipMemsetAsync(derr.p, 0, 64, s));
+            k_fill_slots<<<grid_for((int64_t)tmp_cap), kThreads, 0, s>>>(tmp.as<Slot>(), tmp_cap);
+            k_insert_bricks<<<grid_for((int64_t)n_uniq), kThreads, 0, s>>>(
+                duniq.as<unsigned long long>(), (int64_t)n_uniq, l, dilate, tmp.as<Slot>(), (uint32_t)(tmp_cap - 1),
+                dcount.as<unsigned long long>(), derr.as<int>());
+            BBS_HIP(hipGetLastError());
+            unsigned long long nb = 0;
+            BBS_HIP(hipMemcpyAsync(&nb, dcount.p, 8, hipMemcpyDeviceToHost, s));
+            BBS_HIP(hipMemcpyAsync(&err, derr.p, 4, hipMemcpyDeviceToHost, s));
+            BBS_HIP(hipStreamSynchronize(s));
+            if (err || nb * 2 > tmp_cap) {   // too full: grow and rebuild this level
+                if (tmp_cap >= ((uint64_t)1 << 31)) {
+                    bbs_free_map(m);
+                    return fail(BBS_ERR_OOM, "bbs_build_map: brick table would exceed 2^31 slots");
+                }
+                tmp_cap *= 4;
+                continue;
+            }
+            uint64_t cap = next_pow2(std::max<uint64_t>(16, 2 * nb));
+            void *dst = nullptr;
+            if (alloc_dev(&dst, cap * sizeof(Slot))) {
+                bbs_free_map(m);
+                return BBS_ERR_OOM;
+            }
+            m->slots[l] = static_cast<Slot *>(dst);
+            m->cap[l] = cap;
+            m->bricks[l] = (int64_t)nb;
+            int bbox_init[6] = {INT_MAX, INT_MAX, INT_MAX, INT_MIN, INT_MIN, INT_MIN};
+            BBS_HIP(hipMemcpyAsync(dbbox.p, bbox_init, sizeof(bbox_init), hipMemcpyHostToDevice, s));
+            BBS_HIP(hipMemsetAsync(dvox.p, 0, 8, s));
+            k_fill_slots<<<grid_for((int64_t)cap), kThreads, 0, s>>>(m->slots[l], cap);
+            k_compact<<<grid_for((int64_t)tmp_cap, kThreads, 2048), kThreads, 0, s>>>(
+                tmp.as<Slot>(), tmp_cap, m->slots[l], (uint32_t)(cap - 1), home, dbbox.as<int>(),
+                dvox.as<unsigned long long>(), derr.as<int>());
+            BBS_HIP(hipGetLastError());
+            int bbox[6];
+            unsigned long long nv = 0;
+            BBS_HIP(hipMemcpyAsync(bbox, dbbox.p, sizeof(bbox), hipMemcpyDeviceToHost, s));
+            BBS_HIP(hipMemcpyAsync(&nv, dvox.p, 8, hipMemcpyDeviceToHost, s));
+            BBS_HIP(hipMemcpyAsync(&err, derr.p, 4, hipMemcpyDeviceToHost, s));
+            BBS_HIP(hipStreamSynchronize(s));
+            if (err) {
+                bbs_free_map(m);
+                return fail(BBS_ERR_INTERNAL, "bbs_build_map: brick compaction failed");
+            }
+            for (int a = 0; a < 3; ++a) {
+                m->bmin[l][a] = bbox[a];
+                m->bmax[l][a] = bbox[3 + a];
+            }
+            m->voxels[l] = (int64_t)nv;
+            break;
+        }
+    }
+    *out = m;
+    return BBS_OK;
+}
+
+extern "C" bbs_status bbs_map_info(const bbs_map *map, int32_t *levels, float *min_res, int64_t *voxels,
+                                   int64_t *slots, int64_t *bricks)
+{
+    if (!map) return fail(BBS_ERR_INVALID_ARG, "bbs_map_info: map is NULL");
+    if (levels) *levels = map->levels;
+    if (min_res) *min_res = map->r;
+    for (int l = 0; l < kMaxLevels; ++l) {
+        bool on = l <= map->levels;
+        if (voxels) voxels[l] = on ? map->voxels[l] : 0;
+        if (slots) slots[l] = on ? (int64_t)map->cap[l] : 0;
+        if (bricks) bricks[l] = on ? map->bricks[l] : 0;
+    }
+    return BBS_OK;
+}
+
+extern "C" bbs_status bbs_map_dump_level(const bbs_map *map, int32_t level, int32_t *out_xyz, int64_t cap,
+                                         int64_t *count)
+{
+    if (!map) return fail(BBS_ERR_INVALID_ARG, "bbs_map_dump_level: map is NULL");
+    if (level < 0 || level > map->levels) return fail(BBS_ERR_INVALID_ARG, "bbs_map_dump_level: level out of range");
+    if (cap < 0 || (cap > 0 && !out_xyz)) return fail(BBS_ERR_INVALID_ARG, "bbs_map_dump_level: bad output buffer");
+    hipStream_t s = nullptr;
+    BBS_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    StreamGuard sg;
+    sg.s = s;
+    sg.own = true;
+    DevBuf dout, dcnt;
+    if (alloc_dev(&dout.p, (size_t)std::max<int64_t>(cap, 1) * 12) || alloc_dev(&dcnt.p, 8)) return BBS_ERR_OOM;
+    BBS_HIP(hipMemsetAsync(dcnt.p, 0, 8, s));
+    k_dump<<<grid_for((int64_t)map->cap[level]), kThreads, 0, s>>>(map->slots[level], map->cap[level], home_mask(),
+                                                                    dout.as<int32_t>(), (uint64_t)cap,
+                                                                    dcnt.as<unsigned long long>());
+    BBS_HIP(hipGetLastError());
+    unsigned long long c = 0;
+    BBS_HIP(hipMemcpyAsync(&c, dcnt.p, 8, hipMemcpyDeviceToHost, s));
+    BBS_HIP(hipStreamSynchronize(s));
+    int64_t w = std::min<int64_t>((int64_t)c, cap);
+    if (w > 0) BBS_HIP(hipMemcpy(out_xyz, dout.p, (size_t)w * 12, hipMemcpyDeviceToHost));
+    if (count) *count = (int64_t)c;
+    return BBS_OK;
+}
+
+extern "C" bbs_status bbs_map_contains(const bbs_map *map, int32_t level, const int32_t *xyz, int64_t n, uint8_t *out)
+{
+    if (!map) return fail(BBS_ERR_INVALID_ARG, "bbs_map_contains: map is NULL");
+    if (level < 0 || level > map->levels) return fail(BBS_ERR_INVALID_ARG, "bbs_map_contains: level out of range");
+    if (n < 0 || (n > 0 && (!xyz || !out))) return fail(BBS_ERR_INVALID_ARG, "bbs_map_contains: bad buffers");
+    if (n == 0) return BBS_OK;
+    for (int64_t i = 0; i < 3 * n; ++i)
+        if (xyz[i] <= -kVoxelLimit || xyz[i] >= kVoxelLimit)
+            return fail(BBS_ERR_INVALID_ARG, "bbs_map_contains: voxel coordinate outside (-2^20, 2^20)");
+    hipStream_t s = nullptr;
+    BBS_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    StreamGuard sg;
+    sg.s = s;
+    sg.own = true;
+    DevBuf din, dout, derr;
+    if (alloc_dev(&din.p, (size_t)n * 12) || alloc_dev(&dout.p, (size_t)n) || alloc_dev(&derr.p, 4)) return BBS_ERR_OOM;
+    BBS_HIP(hipMemcpyAsync(din.p, xyz, (size_t)n * 12, hipMemcpyHostToDevice, s));
+    BBS_HIP(hipMemsetAsync(derr.p, 0, 4, s));
+    MapView v = map->view();
+    k_contains<<<grid_for(n), kThreads, 0, s>>>(v.lv[level], din.as<int32_t>(), n, dout.as<uint8_t>(), derr.as<int>());
+    BBS_HIP(hipGetLastError());
+    int err = 0;
+    BBS_HIP(hipMemcpyAsync(out, dout.p, (size_t)n, hipMemcpyDeviceToHost, s));
+    BBS_HIP(hipMemcpyAsync(&err, derr.p, 4, hipMemcpyDeviceToHost, s));
+    BBS_HIP(hipStreamSynchronize(s));
+    if (err) return fail(BBS_ERR_INTERNAL, "bbs_map_contains: overlapping bricks disagree");
+    return BBS_OK;
+}

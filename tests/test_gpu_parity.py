@@ -1,0 +1,254 @@
+"""Parity of the HIP library with the CPU oracle, through the C ABI.
+
+Integer results (voxel sets, node scores, leaf indices, node counters) must be
+bit-identical.  Inputs are the seeded synthetic scenes of `synth`.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2310_10023_amd as bbs
+import synth
+
+pytestmark = pytest.mark.gpu
+
+RESULT_KEYS = ("found", "score", "leaf", "nodes_expanded", "nodes_scored", "flushes", "leaves_accepted",
+               "initial_size", "initial_kept")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def room():
+    s = synth.room_scene(0)
+    return s, bbs.Map(s.points, 0.5, 4), oracle.Map(s.points, 0.5, 4)
+
+
+def sorted_rows(a):
+    a = np.asarray(a, np.int32).reshape(-1, 3)
+    return a[np.lexsort((a[:, 2], a[:, 1], a[:, 0]))]
+
+
+# ------------------------------------------------------------------ map (Sec. III-C)
+
+@pytest.mark.parametrize("r,levels,dilate", [(0.5, 4, True), (0.3, 3, True), (1.0, 2, False)])
+def test_map_levels_equal_oracle(r, levels, dilate):
+    say("map parity", r, levels, dilate)
+    s = synth.room_scene(1)
+    g = bbs.Map(s.points, r, levels, dilate_leaf=dilate)
+    o = oracle.Map(s.points, r, levels, dilate_leaf=dilate)
+    info = g.info()
+    for l in range(levels + 1):
+        got = g.dump_level(l)
+        want = sorted_rows(o.level_keys(l))
+        assert info["voxels"][l] == len(want)
+        np.testing.assert_array_equal(got, want)
+
+
+def test_map_membership_probes(room):
+    say("membership")
+    _, g, o = room
+    rng = np.random.default_rng(0)
+    for l in range(5):
+        keys = o.level_keys(l)
+        hits = g.contains(l, keys)
+        assert hits.all()
+        q = rng.integers(keys.min(0) - 3, keys.max(0) + 4, size=(20000, 3)).astype(np.int32)
+        want = np.array([o.contains(l, *v) for v in q.tolist()])
+        np.testing.assert_array_equal(g.contains(l, q), want)
+        assert (~want).sum() > 1000
+
+
+def test_map_from_device_tensor():
+    import torch
+    say("map from device tensor")
+    s = synth.tiny_scene(3, n_map=700)
+    t = torch.from_numpy(s.points).cuda()
+    g = bbs.Map(t, 0.25, 3)
+    o = oracle.Map(s.points, 0.25, 3)
+    for l in range(4):
+        np.testing.assert_array_equal(g.dump_level(l), sorted_rows(o.level_keys(l)))
+
+
+# ------------------------------------------------------------------ score (Eq. eq:3Dupperbound)
+
+def random_nodes(s, rng, n, levels):
+    rows = []
+    for _ in range(n):
+        l = int(rng.integers(0, levels + 1))
+        t = [int(rng.integers((s.lo[i] >> l) - 1, (s.hi[i] >> l) + 2)) for i in range(3)]
+        a = [int(rng.integers(0, s.n(ax, l))) for ax in range(3)]
+        rows.append([l] + t + a)
+    return np.array(rows, np.int32)
+
+
+@pytest.mark.parametrize("k", [1, 37, 256, 2000, 2333])
+def test_scores_equal_oracle_room(room, k):
+    say("scores room k =", k)
+    scene, g, o = room
+    sc = synth.scan_scene(scene, 11 + k, k, z=1.5, z_jitter=0.25, rp_deg=2.0)
+    lo, hi = synth.search_range_room()
+    s = oracle.Search(o, sc.points, lo, hi)
+    nodes = random_nodes(s, np.random.default_rng(k), 3000, 4)
+    want = s.score_nodes(nodes, threads=8)
+    got = bbs.score_nodes(g, sc.points, lo, hi, nodes)
+    np.testing.assert_array_equal(got, want)
+
+
+def test_scores_non_power_of_two_voxel():
+    say("scores r = 0.3")
+    scene = synth.room_scene(2)
+    g = bbs.Map(scene.points, 0.3, 3)
+    o = oracle.Map(scene.points, 0.3, 3)
+    sc = synth.scan_scene(scene, 5, 1500, z=1.5, rp_deg=2.0)
+    lo, hi = synth.search_range_room()
+    s = oracle.Search(o, sc.points, lo, hi)
+    nodes = random_nodes(s, np.random.default_rng(9), 2000, 3)
+    np.testing.assert_array_equal(bbs.score_nodes(g, sc.points, lo, hi, nodes), s.score_nodes(nodes, threads=8))
+
+
+def test_scores_translation_only_grid(room):
+    say("scores translation-only")
+    scene, g, o = room
+    sc = synth.scan_scene(scene, 4, 1000, z=1.5, rp_deg=2.0)
+    lo, hi = synth.search_range_room()
+    s = oracle.Search(o, sc.points, lo, hi, translation_only=True)
+    nodes = random_nodes(s, np.random.default_rng(4), 2000, 4)
+    np.testing.assert_array_equal(bbs.score_nodes(g, sc.points, lo, hi, nodes, translation_only=True),
+                                  s.score_nodes(nodes, threads=8))
+
+
+# ------------------------------------------------------------------ localize (Alg. 2)
+
+def compare(got, want):
+    for key in RESULT_KEYS:
+        assert got[key] == want[key], (key, got[key], want[key])
+    if want["found"]:
+        # pose = r * leaf and the leaf-level angular cell centres, rounded to float32
+        np.testing.assert_array_equal(np.float32(got["pose"]), np.float32(want["pose"]))
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+@pytest.mark.parametrize("batch", [10000, 64])
+def test_localize_room_equals_oracle(room, seed, batch):
+    say("localize room", seed, batch)
+    scene, g, o = room
+    sc = synth.scan_scene(scene, seed, 2000, z=1.5, z_jitter=0.25, rp_deg=2.0)
+    lo, hi = synth.search_range_room()
+    T = synth.threshold_95(2000)
+    want = oracle.Search(o, sc.points, lo, hi).localize(T, batch=batch, threads=8)
+    got = bbs.localize(g, sc.points, lo, hi, T, batch_size=batch)
+    compare(got, want)
+
+
+@pytest.mark.parametrize("batch", [1, 7, 333])
+@pytest.mark.parametrize("translation_only", [False, True])
+def test_localize_tiny_batches_and_modes(batch, translation_only):
+    say("localize tiny", batch, translation_only)
+    scene = synth.tiny_scene(2, n_map=600)
+    g = bbs.Map(scene.points, 0.5, 3)
+    o = oracle.Map(scene.points, 0.5, 3)
+    sc = synth.scan_scene(scene, 2, 300, z=1.0, rp_deg=2.0, n_beams=16, n_az=256, max_range=12.0)
+    rp = math.radians(2.0)
+    lo = np.array([-3, -3, 0.5, -rp, -rp, 0], np.float32)
+    hi = np.array([3, 3, 1.5, rp, rp, 2 * math.pi], np.float32)
+    for T in (0, 150, 280, 301):
+        want = oracle.Search(o, sc.points, lo, hi, translation_only=translation_only).localize(T, batch=batch,
+                                                                                             threads=8)
+        got = bbs.localize(g, sc.points, lo, hi, T, batch_size=batch, translation_only=translation_only)
+        compare(got, want)
+
+
+def test_localize_single_level_and_single_point():
+    say("localize l_max = 0, k = 1")
+    scene = synth.tiny_scene(1, n_map=400)
+    g = bbs.Map(scene.points, 0.5, 0)
+    o = oracle.Map(scene.points, 0.5, 0)
+    lo = np.array([-2, -2, 1, 0, 0, 0], np.float32)
+    hi = np.array([2, 2, 1, 0, 0, 2 * math.pi], np.float32)
+    for k in (1, 50):
+        sc = synth.scan_scene(scene, 7, k, z=1.0, rp_deg=0.5, n_beams=8, n_az=128, max_range=12.0)
+        for T in (0, k):
+            want = oracle.Search(o, sc.points, lo, hi).localize(T, batch=16, threads=4)
+            compare(bbs.localize(g, sc.points, lo, hi, T, batch_size=16), want)
+
+
+def test_localize_device_scan_and_determinism(room):
+    import torch
+    say("localize device scan, twice")
+    scene, g, o = room
+    sc = synth.scan_scene(scene, 5, 2000, z=1.5, z_jitter=0.25, rp_deg=2.0)
+    lo, hi = synth.search_range_room()
+    T = synth.threshold_95(2000)
+    want = oracle.Search(o, sc.points, lo, hi).localize(T, batch=500, threads=8)
+    ws = bbs.Workspace()
+    dev = torch.from_numpy(sc.points).cuda()
+    a = bbs.localize(g, dev, lo, hi, T, batch_size=500, workspace=ws)
+    b = bbs.localize(g, sc.points, lo, hi, T, batch_size=500, workspace=ws)
+    compare(a, want)
+    compare(b, want)
+
+
+def test_localize_errors(room):
+    say("error paths")
+    scene, g, _ = room
+    sc = synth.scan_scene(scene, 0, 500, z=1.5, rp_deg=2.0)
+    lo, hi = synth.search_range_room()
+    bad = sc.points.copy()
+    bad[3, 1] = np.nan
+    with pytest.raises(bbs.BbsError) as e:
+        bbs.localize(g, bad, lo, hi, 400)
+    assert e.value.status == -1
+    with pytest.raises(bbs.BbsError):
+        bbs.localize(g, sc.points, hi, lo, 400)
+    # a queue that cannot hold the initial set
+    ws = bbs.Workspace(max_queue_nodes=16)
+    with pytest.raises(bbs.BbsError) as e:
+        bbs.localize(g, sc.points, lo, hi, 0, workspace=ws)
+    assert e.value.status == -4
+    # the same workspace still works for a search that fits
+    r = bbs.localize(g, sc.points, lo, hi, 501, workspace=ws)
+    assert r["found"] == 0 and r["nodes_expanded"] == 0
+
+
+# ------------------------------------------------------------------ full-size city (sampled parity)
+
+@pytest.fixture(scope="module")
+def city():
+    c = synth.city_scene(1000)
+    say("city map points", len(c.points))
+    return c, bbs.Map(c.points, 1.0, 6), oracle.Map(c.points, 1.0, 6)
+
+
+def test_city_map_and_sampled_scores(city):
+    say("city map + sampled scores")
+    c, g, o = city
+    info = g.info()
+    for l in range(7):
+        assert info["voxels"][l] == o.level_size(l)
+    np.testing.assert_array_equal(g.dump_level(6), sorted_rows(o.level_keys(6)))
+    np.testing.assert_array_equal(g.dump_level(0), sorted_rows(o.level_keys(0)))
+    sc = synth.scan_scene(c, 0, 10000, z=1.8, rp_deg=3.0, n_beams=64, n_az=2048, voxel=0.5)
+    lo, hi = synth.search_range_city()
+    s = oracle.Search(o, sc.points, lo, hi)
+    nodes = random_nodes(s, np.random.default_rng(1), 1500, 6)
+    np.testing.assert_array_equal(bbs.score_nodes(g, sc.points, lo, hi, nodes), s.score_nodes(nodes, threads=16))
+
+
+def test_city_localize_equals_oracle(city):
+    """Full 10k-point city query, plain batched b = 10000, against the oracle."""
+    say("city localize seed 0")
+    c, g, o = city
+    sc = synth.scan_scene(c, 0, 10000, z=1.8, rp_deg=3.0, n_beams=64, n_az=2048, voxel=0.5)
+    lo, hi = synth.search_range_city()
+    T = synth.threshold_95(10000)
+    got = bbs.localize(g, sc.points, lo, hi, T, batch_size=10000)
+    say("gpu", {k: got[k] for k in RESULT_KEYS}, got["phase_ms"])
+    want = oracle.Search(o, sc.points, lo, hi).localize(T, batch=10000, threads=16)
+    compare(got, want)
