@@ -76,6 +76,7 @@ typedef struct {
     double score_kernel_ms;   /* summed duration of the scoring launches (profile = 1) */
     int64_t score_launches;   /* number of scoring launches (profile = 1) */
     int64_t score_pairs;      /* sum over scored nodes of K (node-point membership tests) */
+    int64_t score_groups;     /* scored groups of translational siblings sharing a rotation */
     double phase_ms[4];       /* set-up, initial set, search loop, total (host clock) */
 } bbs_result;
 

@@ -54,7 +54,7 @@ class Result(C.Structure):
                 ("nodes_expanded", C.c_int64), ("nodes_scored", C.c_int64), ("flushes", C.c_int64),
                 ("leaves_accepted", C.c_int64), ("initial_size", C.c_int64), ("initial_kept", C.c_int64),
                 ("score_kernel_ms", C.c_double), ("score_launches", C.c_int64), ("score_pairs", C.c_int64),
-                ("phase_ms", C.c_double * 4)]
+                ("score_groups", C.c_int64), ("phase_ms", C.c_double * 4)]
 
     def as_dict(self):
         return {"found": self.found, "score": self.score, "leaf": list(self.leaf), "pose": list(self.pose),
@@ -62,6 +62,7 @@ class Result(C.Structure):
                 "leaves_accepted": self.leaves_accepted, "initial_size": self.initial_size,
                 "initial_kept": self.initial_kept, "score_kernel_ms": self.score_kernel_ms,
                 "score_launches": self.score_launches, "score_pairs": self.score_pairs,
+                "score_groups": self.score_groups,
                 "phase_ms": list(self.phase_ms)}
 
 

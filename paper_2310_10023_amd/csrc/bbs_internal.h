@@ -26,16 +26,20 @@ constexpr uint32_t kEmptyLo = 0xFFFFFFFFu; // empty slot: key = all ones
 constexpr uint32_t kEmptyHi = 0xFFFFFFFFu;
 constexpr int32_t kTransLimit = 1 << 14;   // |translation cell index| bound (int16 node fields)
 
-// One hash slot: 32 bytes.  head = (key lo, key hi, unused, unused),
+// Build-time hash slot: 32 bytes.  head = (key lo, key hi, unused, unused),
 // bits = occupancy of the brick's 5^3 voxels, bit (dz * 5 + dy) * 5 + dx.
 struct alignas(32) Slot {
     uint4 head;
     uint4 bits;
 };
 
+// A level of the finished map: keys and occupancy masks in separate arrays
+// (structure of arrays), so the key array that every probe walks stays
+// small and cache resident; a mask is read only when its key matches.
 struct LevelView {
-    const Slot *slots;
-    uint32_t cap_mask;   // capacity - 1 (power of two); 0 with slots == nullptr for an empty level
+    const uint2 *keys;   // (key lo, key hi); empty = all ones
+    const uint4 *bits;   // occupancy of the brick in the same slot
+    uint32_t cap_mask;   // capacity - 1 (power of two)
     int32_t bmin[3];     // brick-coordinate bounding box of the level
     int32_t bmax[3];
 };
@@ -120,6 +124,7 @@ struct SearchConst {
     float r;
     float inv_r;
     int32_t r_pow2;                // r is a power of two: p / r == p * (1 / r) exactly
+    int32_t score_items;           // scoring work items to aim for (groups x point splits)
 };
 
 // Error reporting (thread-local message).
@@ -142,7 +147,8 @@ struct bbs_map {
     float r;
     int32_t dilate_leaf;
     int32_t device;
-    bbs::Slot *slots[bbs::kMaxLevels];
+    uint2 *keys[bbs::kMaxLevels];
+    uint4 *bits[bbs::kMaxLevels];
     uint64_t cap[bbs::kMaxLevels];
     int64_t bricks[bbs::kMaxLevels];
     int64_t voxels[bbs::kMaxLevels];

@@ -187,7 +187,7 @@ __device__ inline int popc4(uint4 a, uint4 m)
 
 // Move the bricks of a scratch table into the final one; reduce the brick
 // bounding box and count each voxel once (in its home brick, dx, dy, dz <= 3).
-__global__ void k_compact(const Slot *src, uint64_t src_n, Slot *dst, uint32_t dst_mask, uint4 home,
+__global__ void k_compact(const Slot *src, uint64_t src_n, uint2 *dkeys, uint4 *dbits, uint32_t dst_mask, uint4 home,
                           int *bbox, unsigned long long *n_voxels, int *err)
 {
     __shared__ int sb[6][kThreads];
@@ -203,9 +203,9 @@ __global__ void k_compact(const Slot *src, uint64_t src_n, Slot *dst, uint32_t d
         uint32_t h = brick_hash(b[0], b[1], b[2]) & dst_mask;
         bool placed = false;
         for (uint32_t probe = 0; probe <= dst_mask; ++probe) {
-            unsigned long long *kp = reinterpret_cast<unsigned long long *>(&dst[h].head);
+            unsigned long long *kp = reinterpret_cast<unsigned long long *>(&dkeys[h]);
             if (atomicCAS(kp, kEmpty64, key) == kEmpty64) {
-                dst[h].bits = src[i].bits;
+                dbits[h] = src[i].bits;
                 placed = true;
                 break;
             }
@@ -243,16 +243,24 @@ __global__ void k_compact(const Slot *src, uint64_t src_n, Slot *dst, uint32_t d
     }
 }
 
-__global__ void k_dump(const Slot *t, uint64_t n, uint4 home, int32_t *out, uint64_t cap,
-                       unsigned long long *count)
+__global__ void k_fill_level(uint2 *keys, uint4 *bits, uint64_t n)
 {
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
-        uint4 hd = t[i].head;
-        if (hd.x == kEmptyLo && hd.y == kEmptyHi) continue;
-        unsigned long long key = ((unsigned long long)hd.y << 32) | hd.x;
+        keys[i] = make_uint2(kEmptyLo, kEmptyHi);
+        bits[i] = make_uint4(0u, 0u, 0u, 0u);
+    }
+}
+
+__global__ void k_dump(LevelView lv, uint64_t n, uint4 home, int32_t *out, uint64_t cap, unsigned long long *count)
+{
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        uint2 kk = lv.keys[i];
+        if (kk.x == kEmptyLo && kk.y == kEmptyHi) continue;
+        unsigned long long key = ((unsigned long long)kk.y << 32) | kk.x;
         int32_t b[3] = {(int32_t)((key >> 38) & 0x7FFFF) - kBrickBias, (int32_t)((key >> 19) & 0x7FFFF) - kBrickBias,
                         (int32_t)(key & 0x7FFFF) - kBrickBias};
-        uint32_t w[4] = {t[i].bits.x, t[i].bits.y, t[i].bits.z, t[i].bits.w};
+        uint4 bb = lv.bits[i];
+        uint32_t w[4] = {bb.x, bb.y, bb.z, bb.w};
         for (int dz = 0; dz < 4; ++dz)
             for (int dy = 0; dy < 4; ++dy)
                 for (int dx = 0; dx < 4; ++dx) {
@@ -276,12 +284,12 @@ __device__ inline bool lookup_bits(const LevelView &lv, int32_t bx, int32_t by, 
     uint32_t klo = brick_key_lo(bx, by, bz), khi = brick_key_hi(bx, by, bz);
     uint32_t h = brick_hash(bx, by, bz) & lv.cap_mask;
     for (;;) {
-        uint4 hd = lv.slots[h].head;
-        if (hd.x == klo && hd.y == khi) {
-            bits = lv.slots[h].bits;
+        uint2 kk = lv.keys[h];
+        if (kk.x == klo && kk.y == khi) {
+            bits = lv.bits[h];
             return true;
         }
-        if (hd.x == kEmptyLo && hd.y == kEmptyHi) return false;
+        if (kk.x == kEmptyLo && kk.y == kEmptyHi) return false;
         h = (h + 1) & lv.cap_mask;
     }
 }
@@ -384,7 +392,8 @@ bbs::MapView bbs_map::view() const
     MapView v;
     for (int l = 0; l < kMaxLevels; ++l) {
         LevelView &lv = v.lv[l];
-        lv.slots = l <= levels ? slots[l] : nullptr;
+        lv.keys = l <= levels ? keys[l] : nullptr;
+        lv.bits = l <= levels ? bits[l] : nullptr;
         lv.cap_mask = l <= levels ? (uint32_t)(cap[l] - 1) : 0u;
         for (int a = 0; a < 3; ++a) {
             lv.bmin[a] = l <= levels ? bmin[l][a] : 1;
@@ -397,8 +406,10 @@ bbs::MapView bbs_map::view() const
 extern "C" void bbs_free_map(bbs_map *map)
 {
     if (!map) return;
-    for (int l = 0; l < kMaxLevels; ++l)
-        if (map->slots[l]) (void)hipFree(map->slots[l]);
+    for (int l = 0; l < kMaxLevels; ++l) {
+        if (map->keys[l]) (void)hipFree(map->keys[l]);
+        if (map->bits[l]) (void)hipFree(map->bits[l]);
+    }
     delete map;
 }
 
@@ -493,20 +504,22 @@ extern "C" bbs_status bbs_build_map(const float *xyz, int64_t n, int32_t xyz_on_
                 continue;
             }
             uint64_t cap = next_pow2(std::max<uint64_t>(16, 2 * nb));
-            void *dst = nullptr;
-            if (alloc_dev(&dst, cap * sizeof(Slot))) {
+            void *dk = nullptr, *db = nullptr;
+            if (alloc_dev(&dk, cap * sizeof(uint2)) || alloc_dev(&db, cap * sizeof(uint4))) {
+                if (dk) (void)hipFree(dk);
                 bbs_free_map(m);
                 return BBS_ERR_OOM;
             }
-            m->slots[l] = static_cast<Slot *>(dst);
+            m->keys[l] = static_cast<uint2 *>(dk);
+            m->bits[l] = static_cast<uint4 *>(db);
             m->cap[l] = cap;
             m->bricks[l] = (int64_t)nb;
             int bbox_init[6] = {INT_MAX, INT_MAX, INT_MAX, INT_MIN, INT_MIN, INT_MIN};
             BBS_HIP(hipMemcpyAsync(dbbox.p, bbox_init, sizeof(bbox_init), hipMemcpyHostToDevice, s));
             BBS_HIP(hipMemsetAsync(dvox.p, 0, 8, s));
-            k_fill_slots<<<grid_for((int64_t)cap), kThreads, 0, s>>>(m->slots[l], cap);
+            k_fill_level<<<grid_for((int64_t)cap), kThreads, 0, s>>>(m->keys[l], m->bits[l], cap);
             k_compact<<<grid_for((int64_t)tmp_cap, kThreads, 2048), kThreads, 0, s>>>(
-                tmp.as<Slot>(), tmp_cap, m->slots[l], (uint32_t)(cap - 1), home, dbbox.as<int>(),
+                tmp.as<Slot>(), tmp_cap, m->keys[l], m->bits[l], (uint32_t)(cap - 1), home, dbbox.as<int>(),
                 dvox.as<unsigned long long>(), derr.as<int>());
             BBS_HIP(hipGetLastError());
             int bbox[6];
@@ -560,7 +573,8 @@ extern "C" bbs_status bbs_map_dump_level(const bbs_map *map, int32_t level, int3
     DevBuf dout, dcnt;
     if (alloc_dev(&dout.p, (size_t)std::max<int64_t>(cap, 1) * 12) || alloc_dev(&dcnt.p, 8)) return BBS_ERR_OOM;
     BBS_HIP(hipMemsetAsync(dcnt.p, 0, 8, s));
-    k_dump<<<grid_for((int64_t)map->cap[level]), kThreads, 0, s>>>(map->slots[level], map->cap[level], home_mask(),
+    MapView v = map->view();
+    k_dump<<<grid_for((int64_t)map->cap[level]), kThreads, 0, s>>>(v.lv[level], map->cap[level], home_mask(),
                                                                     dout.as<int32_t>(), (uint64_t)cap,
                                                                     dcnt.as<unsigned long long>());
     BBS_HIP(hipGetLastError());

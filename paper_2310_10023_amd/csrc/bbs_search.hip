@@ -1,15 +1,19 @@
 // Batched best-first branch and bound on the device (Sec. III-D, III-E).
 //
-// One search iteration ("flush" of Alg. 2) is six kernels on one stream:
-//   gather   1 workgroup: pops the queue in (score desc, level asc, FIFO)
-//            order, accepts leaves, and branches accepted inner nodes until
-//            more than b children are pending (or the queue is exhausted);
-//            writes the pending children as rotation groups;
-//   score    the node score of Eq. (eq:3Dupperbound) for every pending node;
-//   push1..3 stable counting sort of the scored children into the bucket
-//            queue (one bucket per (score, level), FIFO inside a bucket).
-// The initial set (every top-level cell) is pushed through the same score and
-// push kernels.  Nothing but a done flag crosses to the host per iteration.
+// One search iteration ("flush" of Alg. 2) is two kernels on one stream:
+//   k_score   the node score of Eq. (eq:3Dupperbound) for every pending node;
+//             the last workgroup to finish a tile of 32 groups also sorts
+//             that tile's kept children by queue bucket (stable ranks);
+//   k_serial  one workgroup: finishes the stable counting sort of the batch
+//             into the bucket queue (one bucket per (score, level), FIFO
+//             inside a bucket), then pops the queue in (score desc, level
+//             asc, FIFO) order, accepts leaves and branches accepted inner
+//             nodes until more than b children are pending (or the queue is
+//             exhausted), writing them as rotation groups.
+// A bucket's FIFO is a chain of 1024-node chunks taken from one pool, so the
+// gather reads a bucket 1024 nodes at a time.  The initial set (every
+// top-level cell) goes through the same kernels.  Nothing but a done flag
+// crosses to the host per iteration.
 #include <algorithm>
 #include <chrono>
 #include <climits>
@@ -23,19 +27,16 @@ namespace bbs {
 namespace {
 
 constexpr int kScoreThreads = 256;
+constexpr int kUnroll = 4;                       // scan points in flight per thread in the scoring loop
 constexpr int kTileGroups = 32;                  // push tile: 32 groups = 256 node slots
 constexpr int kTileSlots = kTileGroups * 8;
-constexpr int kGatherThreads = 256;
-constexpr int kLinkThreads = 1024;
+constexpr int kSerialThreads = 1024;
+constexpr int kChunk = 1024;                     // nodes per queue chunk (= serial block size)
 constexpr int kItersPerSync = 8;
 constexpr int64_t kDefaultQueueNodes = (int64_t)64 << 20;
 
 struct Bucket {
-    int32_t head_run, head_off, tail_run, pad;
-};
-
-struct Run {
-    int32_t start, count, next, pad;
+    int32_t head_chunk, head_off, tail_chunk, tail_fill;   // empty: head_chunk = tail_chunk = -1
 };
 
 struct State {
@@ -43,18 +44,18 @@ struct State {
     int32_t have_match;
     int32_t match[6];
     int32_t done;
-    int32_t error;            // 1: node queue overflow, 2: run table overflow
+    int32_t error;            // 1: node pool overflow
     int32_t top_q;            // no bucket below this index holds nodes
     int32_t n_groups;         // pending groups of the current batch
     int32_t batch;            // 1: the pending batch is to be scored and pushed
     int32_t q_min, q_max;     // bucket range of the kept children of the batch
-    int32_t runs_top, runs_cap;
+    int32_t chunk_top, chunk_cap;
     int32_t pad0;
     int64_t pend_nodes;
     int64_t kept;             // children of the batch with score >= best
     int64_t pushed;           // nodes pushed since the start
     int64_t nodes_expanded, nodes_scored, flushes, leaves_accepted;
-    int64_t arena_top, arena_cap, flush_base;
+    int64_t groups_scored;
 };
 
 inline int grid_for(int64_t n, int threads, int cap)
@@ -144,6 +145,74 @@ __global__ void k_scan_soa(const float *xyz, int32_t K, float *X, float *Y, floa
     if (threadIdx.x == 0) atomicMax(max_sq, (unsigned long long)__double_as_longlong(sm[0]));
 }
 
+// Spatial order of the scan: a counting sort of the points on a 15-bit Morton
+// key (32 cells per axis over [-d_max, d_max]).  Neighbouring lanes of the
+// scoring kernel then probe neighbouring bricks.  The scores are sums over
+// points, so the permutation (and the order inside a cell) changes nothing.
+constexpr int kMortonBits = 5;
+constexpr int kMortonBins = 1 << (3 * kMortonBits);
+
+__device__ inline uint32_t morton_key(float x, float y, float z, float lo, float inv_cell)
+{
+    const int cells = 1 << kMortonBits;
+    int c[3] = {(int)floorf((x - lo) * inv_cell), (int)floorf((y - lo) * inv_cell), (int)floorf((z - lo) * inv_cell)};
+    uint32_t key = 0;
+    for (int b = 0; b < kMortonBits; ++b)
+        for (int a = 0; a < 3; ++a) {
+            int v = min(max(c[a], 0), cells - 1);
+            key |= (uint32_t)((v >> b) & 1) << (3 * b + a);
+        }
+    return key;
+}
+
+__global__ void k_morton_hist(const float *X, const float *Y, const float *Z, int32_t K, float lo, float inv_cell,
+                              uint32_t *keys, int32_t *hist)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < K; i += gridDim.x * blockDim.x) {
+        uint32_t k = morton_key(X[i], Y[i], Z[i], lo, inv_cell);
+        keys[i] = k;
+        atomicAdd(&hist[k], 1);
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_morton_offsets(int32_t *hist)
+{
+    __shared__ int sm[16];
+    const int per = kMortonBins / 1024;
+    int loc[kMortonBins / 1024];
+    int sum = 0;
+    for (int u = 0; u < per; ++u) {
+        loc[u] = hist[threadIdx.x * per + u];
+        sum += loc[u];
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int v = sum;
+    for (int o = 1; o < 64; o <<= 1) {
+        int t = __shfl_up(v, o);
+        if (lane >= o) v += t;
+    }
+    if (lane == 63) sm[wave] = v;
+    __syncthreads();
+    int add = 0;
+    for (int w = 0; w < wave; ++w) add += sm[w];
+    int run = v + add - sum;
+    for (int u = 0; u < per; ++u) {
+        hist[threadIdx.x * per + u] = run;
+        run += loc[u];
+    }
+}
+
+__global__ void k_morton_scatter(const float *X, const float *Y, const float *Z, const uint32_t *keys, int32_t K,
+                                 int32_t *offsets, float *Xs, float *Ys, float *Zs)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < K; i += gridDim.x * blockDim.x) {
+        int pos = atomicAdd(&offsets[keys[i]], 1);
+        Xs[pos] = X[i];
+        Ys[pos] = Y[i];
+        Zs[pos] = Z[i];
+    }
+}
+
 __global__ void k_fill_buckets(Bucket *b, int32_t n)
 {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
@@ -178,78 +247,161 @@ __device__ inline void rotation(const double2 *trig, const SearchConst &C, int l
 // (bx + jx, by + jy, bz + jz) is w + j with w = floor(floor(R s / r) / 2^l) +
 // (bx, by, bz) (float32 transform, fixed evaluation order, no contraction).
 // The brick floor(w / 4) holds all eight candidate voxels, so one probe per
-// point answers the whole group.
+// point answers the whole group.  Each thread keeps kUnroll points (and their
+// probe chains) in flight.  A group's points are split over several
+// workgroups when the batch has few groups; partial counts are added with
+// integer atomics into scores zeroed by the producer of the batch.
+__device__ inline int bucket_of(int score, int level, const SearchConst &C)
+{
+    return (C.K - score) * (C.levels + 1) + level;
+}
+
+// One tile of 32 groups (256 node slots) of a scored batch: the queue bucket
+// of every kept child (score >= best), its rank among the tile's earlier
+// children of the same bucket, and the tile's count per bucket.
+__device__ void tile_pass(int t, const uint4 *groups, int32_t *scores, State *st, const SearchConst &C,
+                          int n_groups, int32_t *q_arr, int32_t *rank_arr, int32_t *hist, int *sq, int *sm)
+{
+    const int s = threadIdx.x;
+    const int g = t * kTileGroups + s / 8, j = s & 7;
+    const int best = st->best;
+    int q = -1;
+    if (g < n_groups) {
+        const uint4 G = groups[g];
+        const uint32_t mask = (G.w >> 8) & 0xFF;
+        if ((mask >> j) & 1u) {
+            const int sc = __hip_atomic_load(&scores[8 * (int64_t)g + j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (sc >= best) q = bucket_of(sc, (int)(G.w & 0xFF), C);
+        }
+    }
+    sq[s] = q;
+    __syncthreads();
+    int rank = 0, cnt = 0;
+    if (q >= 0) {
+        for (int i = 0; i < kTileSlots; ++i) {
+            const int e = (sq[i] == q);
+            cnt += e;
+            rank += e & (i < s);
+        }
+    }
+    q_arr[(int64_t)t * kTileSlots + s] = q;
+    rank_arr[(int64_t)t * kTileSlots + s] = rank;
+    if (q >= 0 && rank == 0) hist[(int64_t)t * C.q_count + q] = cnt;
+    const int qmn = block_min_int<kTileSlots>(q >= 0 ? q : INT_MAX, sm);
+    const int qmx = -block_min_int<kTileSlots>(q >= 0 ? -q : INT_MAX, sm);
+    int tot;
+    (void)block_scan_incl<kTileSlots>(q >= 0 ? 1 : 0, sm, &tot);
+    if (threadIdx.x == 0 && tot > 0) {
+        atomicMin(&st->q_min, qmn);
+        atomicMax(&st->q_max, qmx);
+        atomicAdd((unsigned long long *)&st->kept, (unsigned long long)tot);
+    }
+}
+
 template <bool POW2>
-__global__ __launch_bounds__(kScoreThreads) void k_score(const uint4 *__restrict__ groups, const State *st,
+__global__ __launch_bounds__(kScoreThreads) void k_score(const uint4 *__restrict__ groups, State *st,
                                                           int32_t n_groups_fixed, const float *__restrict__ X,
                                                           const float *__restrict__ Y, const float *__restrict__ Z,
                                                           MapView map, const double2 *__restrict__ trig, SearchConst C,
-                                                          int32_t *__restrict__ scores)
+                                                          int32_t *__restrict__ scores, int32_t *tile_done,
+                                                          int32_t *q_arr, int32_t *rank_arr, int32_t *hist)
 {
     __shared__ int red[kScoreThreads / 64][8];
+    __shared__ int sq[kTileSlots];
+    __shared__ int sm[kScoreThreads / 64];
+    __shared__ int s_last;
     const int n_groups = st ? (st->batch ? st->n_groups : 0) : n_groups_fixed;
+    if (n_groups <= 0) return;
     const int K = C.K;
-    for (int g = blockIdx.x; g < n_groups; g += gridDim.x) {
+    int S = (C.score_items + n_groups - 1) / n_groups;
+    S = max(1, min(S, (K + 1023) / 1024));
+    const int64_t n_items = (int64_t)n_groups * S;
+    for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
+        const int g = (int)(item / S), sp = (int)(item % S);
+        const int k_begin = (int)((int64_t)K * sp / S), k_end = (int)((int64_t)K * (sp + 1) / S);
         const uint4 G = groups[g];
         const int level = (int)(G.w & 0xFF);
         const int bx = lo16s(G.x), by = hi16s(G.x), bz = lo16s(G.y);
         float R[9];
         rotation(trig, C, level, hi16u(G.y), lo16u(G.z), hi16u(G.z), R);
         const LevelView lv = map.lv[level];
-        const Slot *__restrict__ slots = lv.slots;
+        const uint2 *__restrict__ keys = lv.keys;
+        const uint4 *__restrict__ bitsv = lv.bits;
         const uint32_t cap_mask = lv.cap_mask;
         const uint32_t ex = (uint32_t)(lv.bmax[0] - lv.bmin[0]);
         const uint32_t ey = (uint32_t)(lv.bmax[1] - lv.bmin[1]);
         const uint32_t ez = (uint32_t)(lv.bmax[2] - lv.bmin[2]);
         int c0 = 0, c1 = 0, c2 = 0, c3 = 0, c4 = 0, c5 = 0, c6 = 0, c7 = 0;
-        for (int k = threadIdx.x; k < K; k += kScoreThreads) {
-            const float sx = X[k], sy = Y[k], sz = Z[k];
-            float p[3];
+        for (int kb = k_begin + (int)threadIdx.x; kb < k_end; kb += kScoreThreads * kUnroll) {
+            uint32_t h[kUnroll], klo[kUnroll], khi[kUnroll];
+            int i0[kUnroll];
+            int state[kUnroll];   // 0: miss, 1: probing, 2: found
 #pragma unroll
-            for (int row = 0; row < 3; ++row) {
-                float t0 = R[3 * row + 0] * sx;
-                float t1 = R[3 * row + 1] * sy;
-                float t2 = R[3 * row + 2] * sz;
-                p[row] = (t0 + t1) + t2;
-            }
-            int32_t w[3];
+            for (int u = 0; u < kUnroll; ++u) {
+                const int k = kb + u * kScoreThreads;
+                state[u] = 0;
+                h[u] = 0;
+                klo[u] = khi[u] = 0;
+                i0[u] = 0;
+                if (k < k_end) {
+                    const float sx = X[k], sy = Y[k], sz = Z[k];
+                    int32_t w[3];
 #pragma unroll
-            for (int row = 0; row < 3; ++row) {
-                float q = POW2 ? p[row] * C.inv_r : p[row] / C.r;
-                w[row] = ((int32_t)floorf(q) >> level);
-            }
-            const int32_t wx = w[0] + bx, wy = w[1] + by, wz = w[2] + bz;
-            const int32_t Bx = wx >> 2, By = wy >> 2, Bz = wz >> 2;
-            if ((uint32_t)(Bx - lv.bmin[0]) > ex || (uint32_t)(By - lv.bmin[1]) > ey ||
-                (uint32_t)(Bz - lv.bmin[2]) > ez)
-                continue;
-            const uint32_t klo = brick_key_lo(Bx, By, Bz), khi = brick_key_hi(Bx, By, Bz);
-            uint32_t h = brick_hash(Bx, By, Bz) & cap_mask;
-            uint4 bits = make_uint4(0u, 0u, 0u, 0u);
-            for (;;) {
-                const uint4 hd = slots[h].head;
-                const uint4 bb = slots[h].bits;
-                if (hd.x == klo && hd.y == khi) {
-                    bits = bb;
-                    break;
+                    for (int row = 0; row < 3; ++row) {
+                        float t0 = R[3 * row + 0] * sx;
+                        float t1 = R[3 * row + 1] * sy;
+                        float t2 = R[3 * row + 2] * sz;
+                        float p = (t0 + t1) + t2;
+                        float q = POW2 ? p * C.inv_r : p / C.r;
+                        w[row] = ((int32_t)floorf(q) >> level);
+                    }
+                    const int32_t wx = w[0] + bx, wy = w[1] + by, wz = w[2] + bz;
+                    const int32_t Bx = wx >> 2, By = wy >> 2, Bz = wz >> 2;
+                    if ((uint32_t)(Bx - lv.bmin[0]) <= ex && (uint32_t)(By - lv.bmin[1]) <= ey &&
+                        (uint32_t)(Bz - lv.bmin[2]) <= ez) {
+                        state[u] = 1;
+                        klo[u] = brick_key_lo(Bx, By, Bz);
+                        khi[u] = brick_key_hi(Bx, By, Bz);
+                        h[u] = brick_hash(Bx, By, Bz) & cap_mask;
+                        i0[u] = ((wz & 3) * 5 + (wy & 3)) * 5 + (wx & 3);   // 0 .. 93
+                    }
                 }
-                if (hd.x == kEmptyLo && hd.y == kEmptyHi) break;
-                h = (h + 1) & cap_mask;
             }
-            const int i0 = ((wz & 3) * 5 + (wy & 3)) * 5 + (wx & 3);   // 0 .. 93
-            const int word = i0 >> 5;
-            const uint32_t lo = word == 0 ? bits.x : (word == 1 ? bits.y : bits.z);
-            const uint32_t hi = word == 0 ? bits.y : (word == 1 ? bits.z : bits.w);
-            const uint32_t win = __builtin_amdgcn_alignbit(hi, lo, (uint32_t)(i0 & 31));
-            // member j = 4 jx + 2 jy + jz sits at window bit 25 jz + 5 jy + jx
-            c0 += (win >> 0) & 1u;
-            c1 += (win >> 25) & 1u;
-            c2 += (win >> 5) & 1u;
-            c3 += (win >> 30) & 1u;
-            c4 += (win >> 1) & 1u;
-            c5 += (win >> 26) & 1u;
-            c6 += (win >> 6) & 1u;
-            c7 += (win >> 31) & 1u;
+            for (;;) {
+                bool again = false;
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u) {
+                    if (state[u] == 1) {
+                        const uint2 kk = keys[h[u]];
+                        if (kk.x == klo[u] && kk.y == khi[u]) state[u] = 2;
+                        else if (kk.x == kEmptyLo && kk.y == kEmptyHi) state[u] = 0;
+                        else {
+                            h[u] = (h[u] + 1) & cap_mask;
+                            again = true;
+                        }
+                    }
+                }
+                if (!again) break;
+            }
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                if (state[u] == 2) {
+                    const uint4 bits = bitsv[h[u]];
+                    const int word = i0[u] >> 5;
+                    const uint32_t lo = word == 0 ? bits.x : (word == 1 ? bits.y : bits.z);
+                    const uint32_t hi = word == 0 ? bits.y : (word == 1 ? bits.z : bits.w);
+                    const uint32_t win = __builtin_amdgcn_alignbit(hi, lo, (uint32_t)(i0[u] & 31));
+                    // member j = 4 jx + 2 jy + jz sits at window bit 25 jz + 5 jy + jx
+                    c0 += (win >> 0) & 1u;
+                    c1 += (win >> 25) & 1u;
+                    c2 += (win >> 5) & 1u;
+                    c3 += (win >> 30) & 1u;
+                    c4 += (win >> 1) & 1u;
+                    c5 += (win >> 26) & 1u;
+                    c6 += (win >> 6) & 1u;
+                    c7 += (win >> 31) & 1u;
+                }
+            }
         }
         int c[8] = {c0, c1, c2, c3, c4, c5, c6, c7};
 #pragma unroll
@@ -260,9 +412,25 @@ __global__ __launch_bounds__(kScoreThreads) void k_score(const uint4 *__restrict
             for (int j = 0; j < 8; ++j) red[wave][j] = c[j];
         __syncthreads();
         if (threadIdx.x < 8) {
-            int s = 0;
-            for (int wv = 0; wv < kScoreThreads / 64; ++wv) s += red[wv][threadIdx.x];
-            scores[8 * (int64_t)g + threadIdx.x] = s;
+            int sum = 0;
+            for (int wv = 0; wv < kScoreThreads / 64; ++wv) sum += red[wv][threadIdx.x];
+            atomicAdd(&scores[8 * (int64_t)g + threadIdx.x], sum);
+            __threadfence();
+        }
+        __syncthreads();
+        if (!tile_done) continue;
+        // the last workgroup to finish a tile sorts it into queue buckets
+        const int t = g / kTileGroups;
+        if (threadIdx.x == 0) {
+            const int in_tile = min(kTileGroups, n_groups - t * kTileGroups) * S;
+            const int prev = atomicAdd(&tile_done[t], 1);
+            s_last = (prev == in_tile - 1);
+        }
+        __syncthreads();
+        if (s_last) {
+            __threadfence();
+            tile_pass(t, groups, scores, st, C, n_groups, q_arr, rank_arr, hist, sq, sm);
+            if (threadIdx.x == 0) tile_done[t] = 0;
         }
         __syncthreads();
     }
@@ -273,8 +441,8 @@ __global__ __launch_bounds__(kScoreThreads) void k_score(const uint4 *__restrict
 // Top-level cells as the valid children of virtual cells one level above:
 // virtual cell (lexicographic) outer, top-level rotation (lexicographic), then
 // the eight translation children as one group.
-__global__ void k_enum_initial(uint4 *groups, int64_t g0, int32_t count, SearchConst C, int32_t px0, int32_t py0,
-                               int32_t pz0, int32_t npy, int32_t npz, State *st)
+__global__ void k_enum_initial(uint4 *groups, int32_t *scores, int64_t g0, int32_t count, SearchConst C,
+                               int32_t px0, int32_t py0, int32_t pz0, int32_t npy, int32_t npz, State *st)
 {
     const int L = C.levels;
     const int na = C.n[0][L], nb = C.n[1][L], ng = C.n[2][L];
@@ -299,6 +467,7 @@ __global__ void k_enum_initial(uint4 *groups, int64_t g0, int32_t count, SearchC
                     if (ok) mask |= 1u << (4 * jx + 2 * jy + jz);
                 }
         groups[i] = make_uint4(pack16(2 * px, 2 * py), pack16(2 * pz, ia), pack16(ib, ig), (uint32_t)L | (mask << 8));
+        for (int j = 0; j < 8; ++j) scores[8 * (int64_t)i + j] = 0;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         st->n_groups = count;
@@ -311,188 +480,142 @@ __global__ void k_enum_initial(uint4 *groups, int64_t g0, int32_t count, SearchC
 
 // ------------------------------------------------------------------ push (stable counting sort)
 
-__device__ inline int bucket_of(int score, int level, const SearchConst &C)
+// Where bucket q's children of this batch go: first the free slots of its
+// tail chunk, then fresh chunks from the pool (allocated in bucket order).
+__device__ inline void bucket_space(const Bucket &b, int cnt, int &T, int &f, int &space, int &nch)
 {
-    return (C.K - score) * (C.levels + 1) + level;
+    T = b.head_chunk >= 0 ? b.tail_chunk : -1;
+    f = T >= 0 ? b.tail_fill : kChunk;
+    space = kChunk - f;
+    const int need = max(0, cnt - space);
+    nch = (need + kChunk - 1) / kChunk;
 }
 
-// Per tile of 256 node slots: bucket of every kept child, its rank among the
-// tile's earlier children of the same bucket, and the tile's count per bucket.
-__global__ __launch_bounds__(kTileSlots) void k_push_tiles(const uint4 *groups, const int32_t *scores, State *st,
-                                                           SearchConst C, int32_t *q_arr, int32_t *rank_arr,
-                                                           int32_t *hist)
-{
-    __shared__ int sq[kTileSlots];
-    __shared__ int sm[kTileSlots / 64];
-    if (!st->batch) return;
-    const int n_groups = st->n_groups;
-    const int best = st->best;
-    const int n_tiles = (n_groups + kTileGroups - 1) / kTileGroups;
-    for (int t = blockIdx.x; t < n_tiles; t += gridDim.x) {
-        const int s = threadIdx.x;
-        const int g = t * kTileGroups + s / 8, j = s & 7;
-        int q = -1;
-        if (g < n_groups) {
-            uint4 G = groups[g];
-            uint32_t mask = (G.w >> 8) & 0xFF;
-            if ((mask >> j) & 1u) {
-                int sc = scores[8 * (int64_t)g + j];
-                if (sc >= best) q = bucket_of(sc, (int)(G.w & 0xFF), C);
-            }
-        }
-        __syncthreads();
-        sq[s] = q;
-        __syncthreads();
-        int rank = 0, cnt = 0;
-        if (q >= 0) {
-            for (int i = 0; i < kTileSlots; ++i) {
-                int e = (sq[i] == q);
-                cnt += e;
-                rank += e & (i < s);
-            }
-        }
-        q_arr[(int64_t)t * kTileSlots + s] = q;
-        rank_arr[(int64_t)t * kTileSlots + s] = rank;
-        if (q >= 0 && rank == 0) hist[(int64_t)t * C.q_count + q] = cnt;
-        int qmn = block_min_int<kTileSlots>(q >= 0 ? q : INT_MAX, sm);
-        int qmx = -block_min_int<kTileSlots>(q >= 0 ? -q : INT_MAX, sm);
-        int tot;
-        (void)block_scan_incl<kTileSlots>(q >= 0 ? 1 : 0, sm, &tot);
-        if (threadIdx.x == 0 && tot > 0) {
-            atomicMin(&st->q_min, qmn);
-            atomicMax(&st->q_max, qmx);
-            atomicAdd((unsigned long long *)&st->kept, (unsigned long long)tot);
-        }
-    }
-}
+struct PushBufs {
+    int32_t *q_arr, *rank_arr, *hist, *totals, *pT, *pf, *pc0, *chunk_next;
+    uint4 *arena;
+};
 
-// Per bucket of the batch: exclusive prefix of the tile counts (in tile order)
-// and the bucket's total.
-__global__ void k_push_scan(State *st, SearchConst C, int32_t *hist, int32_t *totals)
+// Second half of the stable counting sort, run by the serial workgroup after
+// the scoring kernel's tile passes: per bucket the prefix of the tile counts
+// (tile order = batch order), chunk allocation and chain link, then every
+// kept child is written to its slot and the histogram is cleared.
+__device__ void push_finish(State *st, const SearchConst &C, Bucket *bk, const uint4 *groups, const PushBufs &B,
+                            int *sm)
 {
-    if (!st->batch) return;
-    const int q_min = st->q_min, q_max = st->q_max;
-    if (q_max < q_min) return;
-    const int n_tiles = (st->n_groups + kTileGroups - 1) / kTileGroups;
-    for (int q = q_min + blockIdx.x * blockDim.x + threadIdx.x; q <= q_max; q += gridDim.x * blockDim.x) {
-        int acc = 0;
-        for (int t = 0; t < n_tiles; ++t) {
-            int64_t idx = (int64_t)t * C.q_count + q;
-            int v = hist[idx];
-            if (v) {
-                hist[idx] = acc;
-                acc += v;
-            }
-        }
-        totals[q - q_min] = acc;
-    }
-}
-
-// One workgroup: place each non-empty bucket's run in the node arena (in
-// bucket order) and append it to that bucket's FIFO of runs.
-__global__ __launch_bounds__(kLinkThreads) void k_push_link(State *st, SearchConst C, const int32_t *totals,
-                                                            int32_t *segoff, Bucket *bk, Run *runs)
-{
-    __shared__ int sm[kLinkThreads / 64];
-    if (!st->batch) return;
+    const int tid = threadIdx.x;
     const int q_min = st->q_min, q_max = st->q_max;
     const int64_t kept = st->kept;
-    const int64_t base = st->arena_top;
-    if (q_max < q_min || kept == 0) {
-        if (threadIdx.x == 0) st->flush_base = base;
-        return;
-    }
-    if (base + kept > st->arena_cap) {
-        if (threadIdx.x == 0) {
-            st->error = 1;
-            st->done = 1;
-            st->batch = 0;
-        }
-        return;
-    }
+    const int n_tiles = (st->n_groups + kTileGroups - 1) / kTileGroups;
+    if (q_max < q_min || kept == 0) return;
     const int nq = q_max - q_min + 1;
-    // count runs first so that an overflow leaves the queue untouched
-    int n_runs = 0;
-    for (int c = 0; c < nq; c += kLinkThreads) {
-        int i = c + threadIdx.x;
-        int ne = (i < nq && totals[i] > 0) ? 1 : 0;
-        int tot;
-        (void)block_scan_incl<kLinkThreads>(ne, sm, &tot);
-        n_runs += tot;
-    }
-    const int runs_top = st->runs_top;
-    if ((int64_t)runs_top + n_runs > (int64_t)st->runs_cap) {
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            st->error = 2;
-            st->done = 1;
-            st->batch = 0;
+    // per-bucket prefix over tiles (loads first, in blocks of 16 tiles)
+    for (int qi = tid; qi < nq; qi += kSerialThreads) {
+        const int q = q_min + qi;
+        int acc = 0;
+        for (int t0 = 0; t0 < n_tiles; t0 += 16) {
+            int v[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) v[u] = (t0 + u < n_tiles) ? B.hist[(int64_t)(t0 + u) * C.q_count + q] : 0;
+#pragma unroll
+            for (int u = 0; u < 16; ++u)
+                if (v[u]) {
+                    B.hist[(int64_t)(t0 + u) * C.q_count + q] = acc;
+                    acc += v[u];
+                }
         }
-        return;
-    }
-    int64_t node_off = 0;
-    int run_off = 0;
-    for (int c = 0; c < nq; c += kLinkThreads) {
-        int i = c + threadIdx.x;
-        int tot_n = (i < nq) ? totals[i] : 0;
-        int ne = tot_n > 0 ? 1 : 0;
-        int sum_n, sum_r;
-        int incl_n = block_scan_incl<kLinkThreads>(tot_n, sm, &sum_n);
-        int incl_r = block_scan_incl<kLinkThreads>(ne, sm, &sum_r);
-        if (ne) {
-            int q = q_min + i;
-            int64_t off = node_off + incl_n - tot_n;
-            int r = runs_top + run_off + incl_r - 1;
-            segoff[i] = (int32_t)off;
-            runs[r] = Run{(int32_t)(base + off), tot_n, -1, 0};
-            int tail = bk[q].tail_run;
-            if (tail >= 0) runs[tail].next = r;
-            else {
-                bk[q].head_run = r;
-                bk[q].head_off = 0;
-            }
-            bk[q].tail_run = r;
-        }
-        node_off += sum_n;
-        run_off += sum_r;
+        B.totals[qi] = acc;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        st->flush_base = base;
-        st->arena_top = base + kept;
-        st->runs_top = runs_top + n_runs;
+    // chunks needed, then allocation in bucket order
+    int64_t total_new = 0;
+    for (int c = 0; c < nq; c += kSerialThreads) {
+        const int i = c + tid;
+        int nch = 0;
+        if (i < nq && B.totals[i] > 0) {
+            int T, f, space;
+            bucket_space(bk[q_min + i], B.totals[i], T, f, space, nch);
+        }
+        int tot;
+        (void)block_scan_incl<kSerialThreads>(nch, sm, &tot);
+        total_new += tot;
+    }
+    const int chunk_top = st->chunk_top;
+    if ((int64_t)chunk_top + total_new > (int64_t)st->chunk_cap) {
+        __syncthreads();
+        if (tid == 0) {
+            st->error = 1;
+            st->done = 1;
+        }
+        return;
+    }
+    int64_t run = 0;
+    for (int c = 0; c < nq; c += kSerialThreads) {
+        const int i = c + tid;
+        const int q = q_min + i;
+        const int cnt = i < nq ? B.totals[i] : 0;
+        int T = -1, f = kChunk, space = 0, nch = 0;
+        Bucket b = Bucket{-1, 0, -1, 0};
+        if (cnt > 0) {
+            b = bk[q];
+            bucket_space(b, cnt, T, f, space, nch);
+        }
+        int tot;
+        const int incl = block_scan_incl<kSerialThreads>(nch, sm, &tot);
+        if (cnt > 0) {
+            const int c0 = chunk_top + (int)run + incl - nch;
+            B.pT[i] = T;
+            B.pf[i] = f;
+            B.pc0[i] = c0;
+            if (nch > 0) {
+                if (T >= 0) B.chunk_next[T] = c0;
+                else {
+                    b.head_chunk = c0;
+                    b.head_off = 0;
+                }
+                for (int m = 0; m + 1 < nch; ++m) B.chunk_next[c0 + m] = c0 + m + 1;
+                B.chunk_next[c0 + nch - 1] = -1;
+                b.tail_chunk = c0 + nch - 1;
+                b.tail_fill = (cnt - space) - kChunk * (nch - 1);
+            } else {
+                b.tail_fill = f + cnt;
+            }
+            bk[q] = b;
+        }
+        run += tot;
+    }
+    __syncthreads();
+    // scatter: the child of rank r in its bucket fills the tail chunk first
+    const int n_slots = n_tiles * kTileSlots;
+    for (int i = tid; i < n_slots; i += kSerialThreads) {
+        const int q = B.q_arr[i];
+        if (q < 0) continue;
+        const int t = i / kTileSlots, sl = i % kTileSlots;
+        const int g = t * kTileGroups + sl / 8, j = sl & 7;
+        const uint4 G = groups[g];
+        const int qi = q - q_min;
+        const int r = B.hist[(int64_t)t * C.q_count + q] + B.rank_arr[i];
+        const int T = B.pT[qi], f = B.pf[qi];
+        const int space = T >= 0 ? kChunk - f : 0;
+        int64_t pos;
+        if (r < space) pos = (int64_t)T * kChunk + f + r;
+        else {
+            const int r2 = r - space;
+            pos = (int64_t)(B.pc0[qi] + r2 / kChunk) * kChunk + (r2 % kChunk);
+        }
+        const int jx = (j >> 2) & 1, jy = (j >> 1) & 1, jz = j & 1;
+        const int x = lo16s(G.x) + jx, y = hi16s(G.x) + jy, z = lo16s(G.y) + jz;
+        B.arena[pos] = make_uint4(pack16(x, y), pack16(z, hi16u(G.y)), G.z, G.w & 0xFFu);
+    }
+    __syncthreads();
+    for (int i = tid; i < n_slots; i += kSerialThreads) {
+        const int q = B.q_arr[i];
+        if (q >= 0 && B.rank_arr[i] == 0) B.hist[(int64_t)(i / kTileSlots) * C.q_count + q] = 0;
+    }
+    if (tid == 0) {
+        st->chunk_top = chunk_top + (int)total_new;
         st->pushed += kept;
         st->top_q = min(st->top_q, q_min);
-    }
-}
-
-// Write every kept child to arena[flush_base + bucket offset + earlier tiles'
-// count + rank in tile], then clear the tile's histogram entries.
-__global__ __launch_bounds__(kTileSlots) void k_push_scatter(const uint4 *groups, State *st, SearchConst C,
-                                                             const int32_t *q_arr, const int32_t *rank_arr,
-                                                             const int32_t *segoff, int32_t *hist, uint4 *arena)
-{
-    if (!st->batch) return;
-    const int n_groups = st->n_groups;
-    const int n_tiles = (n_groups + kTileGroups - 1) / kTileGroups;
-    const int q_min = st->q_min;
-    const int64_t base = st->flush_base;
-    for (int t = blockIdx.x; t < n_tiles; t += gridDim.x) {
-        const int s = threadIdx.x;
-        const int q = q_arr[(int64_t)t * kTileSlots + s];
-        const int rank = rank_arr[(int64_t)t * kTileSlots + s];
-        if (q >= 0) {
-            const int g = t * kTileGroups + s / 8, j = s & 7;
-            const uint4 G = groups[g];
-            const int64_t hidx = (int64_t)t * C.q_count + q;
-            const int64_t pos = base + segoff[q - q_min] + hist[hidx] + rank;
-            const int jx = (j >> 2) & 1, jy = (j >> 1) & 1, jz = j & 1;
-            const int x = lo16s(G.x) + jx, y = hi16s(G.x) + jy, z = lo16s(G.y) + jz;
-            arena[pos] = make_uint4(pack16(x, y), pack16(z, hi16u(G.y)), G.z, G.w & 0xFFu);
-        }
-        __syncthreads();
-        if (q >= 0 && rank == 0) hist[(int64_t)t * C.q_count + q] = 0;
-        __syncthreads();
     }
 }
 
@@ -528,14 +651,13 @@ __device__ inline void child_counts(const SearchConst &C, const int32_t t[3], co
 // two flushes nothing is pushed, so pops come in (score desc, level asc,
 // FIFO) order straight off the buckets: a leaf bucket is accepted whole (its
 // lexicographically smallest leaf competes for the match), an inner bucket
-// is consumed node by node until the pending count passes b.  Buckets below
-// the running best are never touched (their nodes would be pruned).
-__global__ __launch_bounds__(kGatherThreads) void k_gather(State *st, Bucket *bk, const Run *runs,
-                                                           const uint4 *arena, SearchConst C, uint4 *groups)
+// is consumed node by node, a chunk at a time, until the pending count
+// passes b.  Buckets below the running best are never touched (their nodes
+// would be pruned).  Writes the pending children as groups and zeroes their
+// score slots.
+__device__ void gather(State *st, Bucket *bk, const int32_t *chunk_next, const uint4 *arena, const SearchConst &C,
+                       uint4 *groups, int32_t *scores, int *sm, int (*smatch)[6], int *s_last)
 {
-    __shared__ int sm[kGatherThreads / 64];
-    __shared__ int smatch[kGatherThreads][6];
-    if (st->done) return;
     const int tid = threadIdx.x;
     const int Lp1 = C.levels + 1;
     int best = st->best;
@@ -551,10 +673,10 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(State *st, Bucket *bk
         if (best > C.K) break;
         const int qlim = min((C.K - best) * Lp1 + C.levels, C.q_count - 1);
         int found = INT_MAX;
-        for (int b0 = q; b0 <= qlim; b0 += kGatherThreads) {
-            int qq = b0 + tid;
-            int cand = (qq <= qlim && bk[qq].head_run >= 0) ? qq : INT_MAX;
-            found = block_min_int<kGatherThreads>(cand, sm);
+        for (int b0 = q; b0 <= qlim; b0 += kSerialThreads) {
+            const int qq = b0 + tid;
+            const int cand = (qq <= qlim && bk[qq].head_chunk >= 0) ? qq : INT_MAX;
+            found = block_min_int<kSerialThreads>(cand, sm);
             if (found != INT_MAX) break;
         }
         if (found == INT_MAX) break;
@@ -562,29 +684,29 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(State *st, Bucket *bk
         const int level = q % Lp1;
         const int score = C.K - q / Lp1;
         const Bucket b = bk[q];
+        int c = b.head_chunk, off = b.head_off;
         if (level == 0) {
             int32_t mine[6] = {INT_MAX, INT_MAX, INT_MAX, INT_MAX, INT_MAX, INT_MAX};
-            int run = b.head_run, off = b.head_off;
-            while (run >= 0) {
-                const Run R = runs[run];
-                const int cnt = R.count - off;
-                for (int i = tid; i < cnt; i += kGatherThreads) {
+            while (c >= 0) {
+                const int end = c == b.tail_chunk ? b.tail_fill : kChunk;
+                const int i = off + tid;
+                if (i < end) {
                     int32_t t[3], ang[3], lv;
-                    node_unpack(arena[R.start + off + i], t, ang, lv);
-                    int32_t cand[6] = {t[0], t[1], t[2], ang[0], ang[1], ang[2]};
+                    node_unpack(arena[(int64_t)c * kChunk + i], t, ang, lv);
+                    const int32_t cand[6] = {t[0], t[1], t[2], ang[0], ang[1], ang[2]};
                     if (leaf_less(cand, mine))
                         for (int k = 0; k < 6; ++k) mine[k] = cand[k];
                 }
-                leaves += cnt;
+                leaves += end - off;
+                c = c == b.tail_chunk ? -1 : chunk_next[c];
                 off = 0;
-                run = R.next;
             }
             __syncthreads();
             for (int k = 0; k < 6; ++k) smatch[tid][k] = mine[k];
             __syncthreads();
-            for (int s = kGatherThreads / 2; s > 0; s >>= 1) {
-                if (tid < s && leaf_less(smatch[tid + s], smatch[tid]))
-                    for (int k = 0; k < 6; ++k) smatch[tid][k] = smatch[tid + s][k];
+            for (int sh = kSerialThreads / 2; sh > 0; sh >>= 1) {
+                if (tid < sh && leaf_less(smatch[tid + sh], smatch[tid]))
+                    for (int k = 0; k < 6; ++k) smatch[tid][k] = smatch[tid + sh][k];
                 __syncthreads();
             }
             if (!have || score > best || leaf_less(smatch[0], match))
@@ -592,76 +714,63 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(State *st, Bucket *bk
             __syncthreads();
             have = 1;
             best = score;
-            if (tid == 0) {
-                bk[q].head_run = -1;
-                bk[q].tail_run = -1;
-            }
+            if (tid == 0) bk[q] = Bucket{-1, 0, -1, 0};
             ++q;
             continue;
         }
-        int run = b.head_run, off = b.head_off;
-        while (run >= 0 && !cut) {
-            const Run R = runs[run];
-            const int avail = R.count - off;
-            int base = 0;
-            for (; base < avail && !cut; base += kGatherThreads) {
-                const int i = base + tid;
-                const bool valid = i < avail;
-                int32_t t[3] = {0, 0, 0}, ang[3] = {0, 0, 0}, lv = level;
-                int rc[3] = {0, 0, 0}, nn = 0, ng = 0;
-                uint32_t tmask = 0;
-                if (valid) {
-                    node_unpack(arena[R.start + off + i], t, ang, lv);
-                    child_counts(C, t, ang, level, rc, tmask, nn, ng);
-                }
-                int tot_n, tot_g;
-                const int incl_n = block_scan_incl<kGatherThreads>(nn, sm, &tot_n);
-                const int incl_g = block_scan_incl<kGatherThreads>(ng, sm, &tot_g);
-                const int over = (valid && pend + incl_n > C.batch) ? tid : INT_MAX;
-                const int cutidx = block_min_int<kGatherThreads>(over, sm);
-                const int consumed = cutidx != INT_MAX ? cutidx + 1 : min(kGatherThreads, avail - base);
-                if (tid < consumed && ng > 0) {
-                    int gi = ngrp + incl_g - ng;
-                    for (int ja = 0; ja < rc[0]; ++ja)
-                        for (int jb = 0; jb < rc[1]; ++jb)
-                            for (int jg = 0; jg < rc[2]; ++jg) {
-                                int ra = C.a[0][level] * ang[0] + ja;
-                                int rb = C.a[1][level] * ang[1] + jb;
-                                int rg = C.a[2][level] * ang[2] + jg;
-                                groups[gi++] = make_uint4(pack16(2 * t[0], 2 * t[1]), pack16(2 * t[2], ra),
-                                                          pack16(rb, rg), (uint32_t)(level - 1) | (tmask << 8));
-                            }
-                }
-                // totals up to and including the last consumed node
-                __syncthreads();
-                __shared__ int s_last_n, s_last_g;
-                if (tid == consumed - 1) {
-                    s_last_n = incl_n;
-                    s_last_g = incl_g;
-                }
-                __syncthreads();
-                pend += s_last_n;
-                ngrp += s_last_g;
-                expanded += consumed;
-                if (cutidx != INT_MAX) {
-                    cut = true;
-                    off += base + consumed;
-                }
+        while (c >= 0) {
+            const int end = c == b.tail_chunk ? b.tail_fill : kChunk;
+            const int avail = end - off;
+            const int i = off + tid;
+            const bool valid = tid < avail;
+            int32_t t[3] = {0, 0, 0}, ang[3] = {0, 0, 0}, lv = level;
+            int rc[3] = {0, 0, 0}, nn = 0, ng = 0;
+            uint32_t tmask = 0;
+            if (valid) {
+                node_unpack(arena[(int64_t)c * kChunk + i], t, ang, lv);
+                child_counts(C, t, ang, level, rc, tmask, nn, ng);
             }
-            if (!cut) {
+            int tot_n, tot_g;
+            const int incl_n = block_scan_incl<kSerialThreads>(nn, sm, &tot_n);
+            const int incl_g = block_scan_incl<kSerialThreads>(ng, sm, &tot_g);
+            const int over = (valid && pend + incl_n > C.batch) ? tid : INT_MAX;
+            const int cutidx = block_min_int<kSerialThreads>(over, sm);
+            const int consumed = cutidx != INT_MAX ? cutidx + 1 : avail;
+            if (tid < consumed && ng > 0) {
+                int gi = ngrp + incl_g - ng;
+                for (int ja = 0; ja < rc[0]; ++ja)
+                    for (int jb = 0; jb < rc[1]; ++jb)
+                        for (int jg = 0; jg < rc[2]; ++jg) {
+                            const int ra = C.a[0][level] * ang[0] + ja;
+                            const int rb = C.a[1][level] * ang[1] + jb;
+                            const int rg = C.a[2][level] * ang[2] + jg;
+                            groups[gi++] = make_uint4(pack16(2 * t[0], 2 * t[1]), pack16(2 * t[2], ra),
+                                                      pack16(rb, rg), (uint32_t)(level - 1) | (tmask << 8));
+                        }
+            }
+            if (tid == consumed - 1) {
+                s_last[0] = incl_n;
+                s_last[1] = incl_g;
+            }
+            __syncthreads();
+            pend += s_last[0];
+            ngrp += s_last[1];
+            expanded += consumed;
+            __syncthreads();
+            off += consumed;
+            if (off == end) {
+                c = c == b.tail_chunk ? -1 : chunk_next[c];
                 off = 0;
-                run = R.next;
-            } else if (off == R.count) {
-                off = 0;
-                run = R.next;
+            }
+            if (cutidx != INT_MAX) {
+                cut = true;
+                break;
             }
         }
         if (tid == 0) {
-            if (run < 0) {
-                bk[q].head_run = -1;
-                bk[q].tail_run = -1;
-            } else {
-                bk[q].head_run = run;
+            if (c < 0) bk[q] = Bucket{-1, 0, -1, 0};
+            else {
+                bk[q].head_chunk = c;
                 bk[q].head_off = off;
             }
         }
@@ -669,6 +778,7 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(State *st, Bucket *bk
         ++q;
     }
     __syncthreads();
+    for (int i = tid; i < 8 * ngrp; i += kSerialThreads) scores[i] = 0;
     if (tid == 0) {
         st->best = best;
         st->have_match = have;
@@ -685,11 +795,30 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(State *st, Bucket *bk
             st->batch = 1;
             st->flushes += 1;
             st->nodes_scored += pend;
+            st->groups_scored += ngrp;
         } else {
             st->batch = 0;
             st->done = 1;
         }
     }
+}
+
+// The serial part of an iteration, one workgroup: push the scored batch,
+// then (unless this is an initial-set chunk with more to come) gather the
+// next one.
+__global__ __launch_bounds__(kSerialThreads) void k_serial(State *st, SearchConst C, Bucket *bk, uint4 *groups,
+                                                           int32_t *scores, PushBufs B, int do_gather)
+{
+    __shared__ int sm[kSerialThreads / 64];
+    __shared__ int smatch[kSerialThreads][6];
+    __shared__ int s_last[2];
+    if (st->done) return;
+    if (st->batch) push_finish(st, C, bk, groups, B, sm);
+    __syncthreads();
+    if (st->done) return;
+    if (threadIdx.x == 0) st->batch = 0;
+    __syncthreads();
+    if (do_gather) gather(st, bk, B.chunk_next, B.arena, C, groups, scores, sm, smatch, s_last);
 }
 
 // ------------------------------------------------------------------ host side
@@ -727,16 +856,16 @@ struct bbs_workspace {
     int64_t queue_nodes = 0;
     uint4 *arena = nullptr;
     int64_t arena_n = 0;
-    Run *runs = nullptr;
-    int64_t runs_n = 0;
+    int32_t *chunk_next = nullptr;
+    int64_t chunk_next_n = 0;
     Bucket *buckets = nullptr;
     int64_t buckets_n = 0;
     int32_t *hist = nullptr;
     int64_t hist_n = 0;
     int32_t *totals = nullptr;
     int64_t totals_n = 0;
-    int32_t *segoff = nullptr;
-    int64_t segoff_n = 0;
+    int32_t *pT = nullptr, *pf = nullptr, *pc0 = nullptr;
+    int64_t pT_n = 0, pf_n = 0, pc0_n = 0;
     uint4 *groups = nullptr;
     int64_t groups_n = 0;
     int32_t *scores = nullptr;
@@ -745,10 +874,18 @@ struct bbs_workspace {
     int64_t q_arr_n = 0;
     int32_t *rank_arr = nullptr;
     int64_t rank_arr_n = 0;
+    int32_t *tile_done = nullptr;
+    int64_t tile_done_n = 0;
     float *scan = nullptr;
     int64_t scan_n = 0;
     float *scan_aos = nullptr;
     int64_t scan_aos_n = 0;
+    float *scan_tmp = nullptr;
+    int64_t scan_tmp_n = 0;
+    uint32_t *mkeys = nullptr;
+    int64_t mkeys_n = 0;
+    int32_t *mhist = nullptr;
+    int64_t mhist_n = 0;
     double2 *trig = nullptr;
     int64_t trig_n = 0;
     State *state = nullptr;
@@ -765,8 +902,9 @@ namespace {
 
 void free_ws(bbs_workspace *w)
 {
-    void *ptrs[] = {w->arena, w->runs, w->buckets, w->hist, w->totals, w->segoff, w->groups, w->scores,
-                    w->q_arr, w->rank_arr, w->scan, w->scan_aos, w->trig, w->state, w->maxsq};
+    void *ptrs[] = {w->arena, w->chunk_next, w->buckets, w->hist, w->totals, w->pT, w->pf, w->pc0, w->groups, w->scores,
+                    w->q_arr, w->rank_arr, w->tile_done, w->scan, w->scan_aos, w->scan_tmp, w->mkeys, w->mhist,
+                    w->trig, w->state, w->maxsq};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (w->host_state) (void)hipHostFree(w->host_state);
@@ -849,7 +987,10 @@ bbs_status setup_search(const bbs_map *m, bbs_workspace *ws, const float *scan, 
             return fail(BBS_ERR_INVALID_ARG, "bbs_localize: search range must be finite with min <= max");
     if (batch < 1 || batch > (1 << 24)) return fail(BBS_ERR_INVALID_ARG, "bbs_localize: batch_size must be in [1, 2^24]");
     S.s = s;
-    if (ensure(ws->scan, ws->scan_n, 3 * k) || ensure(ws->maxsq, ws->maxsq_n, 1)) return BBS_ERR_OOM;
+    if (ensure(ws->scan, ws->scan_n, 3 * k) || ensure(ws->scan_tmp, ws->scan_tmp_n, 3 * k) ||
+        ensure(ws->mkeys, ws->mkeys_n, k) || ensure(ws->mhist, ws->mhist_n, kMortonBins) ||
+        ensure(ws->maxsq, ws->maxsq_n, 1))
+        return BBS_ERR_OOM;
     const float *aos = scan;
     if (!on_device) {
         if (ensure(ws->scan_aos, ws->scan_aos_n, 3 * k)) return BBS_ERR_OOM;
@@ -857,8 +998,8 @@ bbs_status setup_search(const bbs_map *m, bbs_workspace *ws, const float *scan, 
         aos = ws->scan_aos;
     }
     BBS_HIP(hipMemsetAsync(ws->maxsq, 0, 8, s));
-    k_scan_soa<<<grid_for(k, 256, 1024), 256, 0, s>>>(aos, (int32_t)k, ws->scan, ws->scan + k, ws->scan + 2 * k,
-                                                       ws->maxsq);
+    k_scan_soa<<<grid_for(k, 256, 1024), 256, 0, s>>>(aos, (int32_t)k, ws->scan_tmp, ws->scan_tmp + k,
+                                                       ws->scan_tmp + 2 * k, ws->maxsq);
     BBS_HIP(hipGetLastError());
     unsigned long long bits = 0;
     BBS_HIP(hipMemcpyAsync(&bits, ws->maxsq, 8, hipMemcpyDeviceToHost, s));
@@ -869,6 +1010,18 @@ bbs_status setup_search(const bbs_map *m, bbs_workspace *ws, const float *scan, 
     double dmax = std::sqrt(maxsq);
     bbs_status st = make_grid(m, dmax, range, translation_only, S.g);
     if (st) return st;
+    {
+        const float lo = -(float)dmax - 1.0f;
+        const float inv_cell = (float)(1 << kMortonBits) / (2.0f * ((float)dmax + 1.0f));
+        BBS_HIP(hipMemsetAsync(ws->mhist, 0, kMortonBins * sizeof(int32_t), s));
+        const float *tx = ws->scan_tmp, *ty = ws->scan_tmp + k, *tz = ws->scan_tmp + 2 * k;
+        k_morton_hist<<<grid_for(k, 256, 1024), 256, 0, s>>>(tx, ty, tz, (int32_t)k, lo, inv_cell, ws->mkeys,
+                                                              ws->mhist);
+        k_morton_offsets<<<1, 1024, 0, s>>>(ws->mhist);
+        k_morton_scatter<<<grid_for(k, 256, 1024), 256, 0, s>>>(tx, ty, tz, ws->mkeys, (int32_t)k, ws->mhist, ws->scan,
+                                                                 ws->scan + k, ws->scan + 2 * k);
+        BBS_HIP(hipGetLastError());
+    }
     const Grid &g = S.g;
     SearchConst &C = S.C;
     std::memset(&C, 0, sizeof(C));
@@ -897,19 +1050,24 @@ bbs_status setup_search(const bbs_map *m, bbs_workspace *ws, const float *scan, 
     S.pow2 = is_pow2_float(g.r);
     C.inv_r = 1.0f / g.r;
     C.r_pow2 = S.pow2 ? 1 : 0;
+    C.score_items = 2048;
     if (ensure(ws->trig, ws->trig_n, (int64_t)trig.size())) return BBS_ERR_OOM;
     BBS_HIP(hipMemcpyAsync(ws->trig, trig.data(), trig.size() * sizeof(double2), hipMemcpyHostToDevice, s));
     return BBS_OK;
 }
 
-void launch_score(const Setup &S, const bbs_map *m, bbs_workspace *ws, const State *st, int32_t n_fixed, int grid)
+void launch_score(const Setup &S, const bbs_map *m, bbs_workspace *ws, State *st, int32_t n_fixed, int grid,
+                  bool tile_pass)
 {
     const float *X = ws->scan, *Y = ws->scan + S.C.K, *Z = ws->scan + 2 * (int64_t)S.C.K;
     MapView v = m->view();
+    int32_t *td = tile_pass ? ws->tile_done : nullptr;
     if (S.pow2)
-        k_score<true><<<grid, kScoreThreads, 0, S.s>>>(ws->groups, st, n_fixed, X, Y, Z, v, ws->trig, S.C, ws->scores);
+        k_score<true><<<grid, kScoreThreads, 0, S.s>>>(ws->groups, st, n_fixed, X, Y, Z, v, ws->trig, S.C, ws->scores,
+                                                        td, ws->q_arr, ws->rank_arr, ws->hist);
     else
-        k_score<false><<<grid, kScoreThreads, 0, S.s>>>(ws->groups, st, n_fixed, X, Y, Z, v, ws->trig, S.C, ws->scores);
+        k_score<false><<<grid, kScoreThreads, 0, S.s>>>(ws->groups, st, n_fixed, X, Y, Z, v, ws->trig, S.C, ws->scores,
+                                                         td, ws->q_arr, ws->rank_arr, ws->hist);
 }
 
 int64_t max_children(const Grid &g)
@@ -1019,20 +1177,26 @@ extern "C" bbs_status bbs_localize(const bbs_map *map, bbs_workspace *ws, const 
     const int64_t cap_groups = std::max<int64_t>(o.batch_size + mc, 4096);
     const int64_t n_tiles = (cap_groups + kTileGroups - 1) / kTileGroups;
     const int64_t qn = std::max<int32_t>(C.q_count, 1);
-    const int64_t runs_cap = std::max<int64_t>(ws->queue_nodes / 4, 1 << 16);
+    const int64_t chunk_cap = std::max<int64_t>(ws->queue_nodes / kChunk, 16);
     if (ensure(ws->groups, ws->groups_n, cap_groups) || ensure(ws->scores, ws->scores_n, 8 * cap_groups) ||
         ensure(ws->q_arr, ws->q_arr_n, n_tiles * kTileSlots) ||
         ensure(ws->rank_arr, ws->rank_arr_n, n_tiles * kTileSlots) || ensure(ws->totals, ws->totals_n, qn) ||
-        ensure(ws->segoff, ws->segoff_n, qn) || ensure(ws->buckets, ws->buckets_n, qn) ||
-        ensure(ws->arena, ws->arena_n, ws->queue_nodes) || ensure(ws->runs, ws->runs_n, runs_cap) ||
+        ensure(ws->pT, ws->pT_n, qn) || ensure(ws->pf, ws->pf_n, qn) || ensure(ws->pc0, ws->pc0_n, qn) ||
+        ensure(ws->buckets, ws->buckets_n, qn) || ensure(ws->arena, ws->arena_n, chunk_cap * kChunk) ||
+        ensure(ws->chunk_next, ws->chunk_next_n, chunk_cap) ||
         ensure(ws->state, ws->state_n, 1))
         return BBS_ERR_OOM;
+    if (!ws->tile_done || ws->tile_done_n < n_tiles) {
+        if (ensure(ws->tile_done, ws->tile_done_n, n_tiles)) return BBS_ERR_OOM;
+        ws->hist_dirty = true;
+    }
     if (!ws->hist || ws->hist_n < n_tiles * qn) {
         if (ensure(ws->hist, ws->hist_n, n_tiles * qn)) return BBS_ERR_OOM;
         ws->hist_dirty = true;
     }
     if (ws->hist_dirty) {
         BBS_HIP(hipMemsetAsync(ws->hist, 0, (size_t)ws->hist_n * 4, s));
+        BBS_HIP(hipMemsetAsync(ws->tile_done, 0, (size_t)ws->tile_done_n * 4, s));
         ws->hist_dirty = false;
     }
     k_fill_buckets<<<grid_for(qn, 256, 4096), 256, 0, s>>>(ws->buckets, (int32_t)qn);
@@ -1041,8 +1205,7 @@ extern "C" bbs_status bbs_localize(const bbs_map *map, bbs_workspace *ws, const 
     std::memset(&h, 0, sizeof(h));
     h.best = C.threshold;
     h.top_q = 0;
-    h.runs_cap = (int32_t)std::min<int64_t>(runs_cap, INT_MAX);
-    h.arena_cap = ws->queue_nodes;
+    h.chunk_cap = (int32_t)std::min<int64_t>(chunk_cap, INT_MAX);
     h.q_min = INT_MAX;
     h.q_max = -1;
     BBS_HIP(hipMemcpyAsync(ws->state, &h, sizeof(State), hipMemcpyHostToDevice, s));
@@ -1059,34 +1222,39 @@ extern "C" bbs_status bbs_localize(const bbs_map *map, bbs_workspace *ws, const 
         return hipEventRecord(ws->ev[i], s);
     };
     const int score_grid = 4096;
-    const int tile_grid = (int)std::min<int64_t>(n_tiles, 2048);
-    const int scan_grid = 64;
-    auto push = [&]() {
-        k_push_tiles<<<tile_grid, kTileSlots, 0, s>>>(ws->groups, ws->scores, ws->state, C, ws->q_arr, ws->rank_arr,
-                                                       ws->hist);
-        k_push_scan<<<scan_grid, 256, 0, s>>>(ws->state, C, ws->hist, ws->totals);
-        k_push_link<<<1, kLinkThreads, 0, s>>>(ws->state, C, ws->totals, ws->segoff, ws->buckets, ws->runs);
-        k_push_scatter<<<tile_grid, kTileSlots, 0, s>>>(ws->groups, ws->state, C, ws->q_arr, ws->rank_arr, ws->segoff,
-                                                         ws->hist, ws->arena);
+    PushBufs B;
+    B.q_arr = ws->q_arr;
+    B.rank_arr = ws->rank_arr;
+    B.hist = ws->hist;
+    B.totals = ws->totals;
+    B.pT = ws->pT;
+    B.pf = ws->pf;
+    B.pc0 = ws->pc0;
+    B.chunk_next = ws->chunk_next;
+    B.arena = ws->arena;
+    auto serial = [&](int do_gather) {
+        k_serial<<<1, kSerialThreads, 0, s>>>(ws->state, C, ws->buckets, ws->groups, ws->scores, B, do_gather);
     };
     const double t_setup = ms_since(t_start);
 
-    // initial set, in chunks of the group buffer
+    // initial set, in chunks of the group buffer; the last chunk's serial
+    // kernel also gathers the first batch of the search
     int64_t init_chunks = 0;
     for (int64_t g0 = 0; g0 < n_init_groups; g0 += cap_groups) {
         int32_t cnt = (int32_t)std::min<int64_t>(cap_groups, n_init_groups - g0);
-        k_enum_initial<<<grid_for(cnt, 256, 4096), 256, 0, s>>>(ws->groups, g0, cnt, C, P0[0], P0[1], P0[2], PN[1],
-                                                                 PN[2], ws->state);
+        k_enum_initial<<<grid_for(cnt, 256, 4096), 256, 0, s>>>(ws->groups, ws->scores, g0, cnt, C, P0[0], P0[1],
+                                                                 P0[2], PN[1], PN[2], ws->state);
         if (prof) BBS_HIP(record(ev_used++));
-        launch_score(S, map, ws, ws->state, 0, score_grid);
+        launch_score(S, map, ws, ws->state, 0, score_grid, true);
         if (prof) BBS_HIP(record(ev_used++));
-        push();
+        serial(g0 + cnt >= n_init_groups ? 1 : 0);
         ++init_chunks;
     }
     BBS_HIP(hipGetLastError());
     BBS_HIP(hipMemcpyAsync(ws->host_state, ws->state, sizeof(State), hipMemcpyDeviceToHost, s));
     BBS_HIP(hipStreamSynchronize(s));
     const int64_t initial_kept = ws->host_state->pushed;
+    const bool init_done = ws->host_state->done != 0;
     const double t_init = ms_since(t_start);
     if (ws->host_state->error) {
         ws->hist_dirty = true;
@@ -1103,12 +1271,12 @@ extern "C" bbs_status bbs_localize(const bbs_map *map, bbs_workspace *ws, const 
             return fail(BBS_ERR_INTERNAL, "bbs_localize: search did not terminate");
         }
         iters += kItersPerSync;
+        if (init_done) break;
         for (int it = 0; it < kItersPerSync; ++it) {
-            k_gather<<<1, kGatherThreads, 0, s>>>(ws->state, ws->buckets, ws->runs, ws->arena, C, ws->groups);
             if (prof) BBS_HIP(record(ev_used++));
-            launch_score(S, map, ws, ws->state, 0, score_grid);
+            launch_score(S, map, ws, ws->state, 0, score_grid, true);
             if (prof) BBS_HIP(record(ev_used++));
-            push();
+            serial(1);
         }
         BBS_HIP(hipGetLastError());
         BBS_HIP(hipMemcpyAsync(ws->host_state, ws->state, sizeof(State), hipMemcpyDeviceToHost, s));
@@ -1139,6 +1307,7 @@ extern "C" bbs_status bbs_localize(const bbs_map *map, bbs_workspace *ws, const 
     out->initial_size = init_nodes;
     out->initial_kept = initial_kept;
     out->score_pairs = out->nodes_scored * k;
+    out->score_groups = n_init_groups + fs.groups_scored;
     if (prof) {
         // every iteration before the one that found the queue exhausted scored a batch
         int64_t launches = init_chunks + fs.flushes;
@@ -1195,7 +1364,8 @@ extern "C" bbs_status bbs_score_nodes(const bbs_map *map, const float *scan_xyz,
     }
     if (ensure(ws->groups, ws->groups_n, n) || ensure(ws->scores, ws->scores_n, 8 * n)) return BBS_ERR_OOM;
     BBS_HIP(hipMemcpyAsync(ws->groups, groups.data(), (size_t)n * sizeof(uint4), hipMemcpyHostToDevice, s));
-    launch_score(S, map, ws, nullptr, (int32_t)n, (int)std::min<int64_t>(n, 8192));
+    BBS_HIP(hipMemsetAsync(ws->scores, 0, (size_t)n * 8 * sizeof(int32_t), s));
+    launch_score(S, map, ws, nullptr, (int32_t)n, 4096, false);
     BBS_HIP(hipGetLastError());
     std::vector<int32_t> all((size_t)n * 8);
     BBS_HIP(hipMemcpyAsync(all.data(), ws->scores, all.size() * 4, hipMemcpyDeviceToHost, s));

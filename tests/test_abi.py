@@ -58,4 +58,4 @@ def test_struct_layouts():
     assert C.sizeof(bbs.SearchRange) == 48
     assert bbs.Options.stream.offset == 16 and C.sizeof(bbs.Options) == 56
     assert bbs.Result.nodes_expanded.offset == 56
-    assert C.sizeof(bbs.Result) == 56 + 6 * 8 + 8 + 8 + 8 + 4 * 8
+    assert C.sizeof(bbs.Result) == 56 + 6 * 8 + 8 + 8 + 8 + 8 + 4 * 8
