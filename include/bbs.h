@@ -57,9 +57,20 @@ typedef struct {
                                  (Table I "Trans." branching); 0: roto-translational */
     int32_t profile;          /* 1: time every scoring launch with HIP events (fills
                                  score_kernel_ms / score_launches of the result) */
-    int32_t reserved0;
+    int32_t n_seed_dives;     /* with a prior: greedy dives from the first n initial nodes
+                                 (prior order) that reach the threshold seed the incumbent */
     void *stream;             /* hipStream_t to run on; NULL = the library's own stream */
-    int64_t reserved[4];
+    const float *prior;       /* NULL, or 1088 host float logits of the proposal network (64
+                                 yaw bins, then 32 x 32 translation cells of the search box,
+                                 x outer).  Initial nodes are scored and queued in descending
+                                 order of yaw-bin logit + cell logit (ties: enumeration
+                                 order), which orders ties of (score, level); a non-finite
+                                 logit disables the prior */
+    int32_t persistent;       /* 1: run the search loop as one cooperative persistent kernel
+                                 (falls back to per-iteration launches if it cannot launch) */
+    int32_t score_items;      /* scoring work items per batch (groups x point splits); sets the
+                                 points each wave handles; 0 = default (2048) */
+    int64_t reserved[2];
 } bbs_options;
 
 typedef struct {
@@ -78,6 +89,10 @@ typedef struct {
     int64_t score_pairs;      /* sum over scored nodes of K (node-point membership tests) */
     int64_t score_groups;     /* scored groups of translational siblings sharing a rotation */
     double phase_ms[4];       /* set-up, initial set, search loop, total (host clock) */
+    int32_t prior_used;       /* 1: the prior ordered the initial set */
+    int32_t seeded;           /* 1: a seed dive set the incumbent */
+    int32_t seed_score;       /* score of that dive leaf */
+    int32_t persistent_used;  /* 1: the search loop ran as one persistent kernel */
 } bbs_result;
 
 /* Fill *opt with the defaults (b = 10000, roto-translational, no profiling,
@@ -160,6 +175,71 @@ bbs_status bbs_localize(const bbs_map *map, bbs_workspace *ws, const float *scan
  */
 bbs_status bbs_score_nodes(const bbs_map *map, const float *scan_xyz, int64_t k, const bbs_search_range *range,
                            int32_t translation_only, const int32_t *nodes, int64_t n, int32_t *scores);
+
+/* One query of a stream. */
+typedef struct {
+    const float *scan_xyz;    /* k x 3 float32 scan, host or device */
+    int64_t k;
+    int32_t scan_on_device;
+    int32_t score_threshold;
+    bbs_search_range range;
+    double arrival_s;         /* arrival time in seconds after the start of bbs_serve (>= 0) */
+} bbs_query;
+
+/*
+ * Serve a stream of localization queries on one resident map.
+ *   queries, n      queries, sorted by arrival_s (not modified)
+ *   workers         concurrent searches (1..64); each worker has its own
+ *                   workspace and HIP stream, so one query's serial phase
+ *                   overlaps the scoring of others
+ *   opt             options for every query (its stream field is ignored)
+ *   results         n results, in query order (caller-allocated)
+ *   start_s, end_s  n doubles each (caller-allocated, may be NULL): when each
+ *                   query started and finished, seconds after the start
+ * A query starts at the earliest time at which it has arrived and a worker
+ * is free, in arrival order.  The first failing query's status is returned
+ * after every worker has finished; its result has found = 0.
+ */
+bbs_status bbs_serve(const bbs_map *map, const bbs_query *queries, int64_t n, int32_t workers,
+                     const bbs_options *opt, bbs_result *results, double *start_s, double *end_s);
+
+/*
+ * Learned proposal network (an addition to the paper's method; it orders the
+ * initial expansion and seeds the incumbent, never changes a node score).
+ * Input: the scan's bird's-eye polar occupancy, 64 range x 64 azimuth bins,
+ * uint8 counts.  Output: 1088 float logits, 64 over yaw bins then 32 x 32
+ * over translation cells (row-major, x outer).  Weights and activations are
+ * bf16 on BF16 MFMA with float accumulation; master weights float.
+ * Parameters are one flat float array in the order c1w [16,3,3,1], c1b[16],
+ * c2w [32,3,3,16], c2b, c3w [64,3,3,32], c3b, c4w [64,3,3,64], c4b,
+ * f1w [256,1024], f1b, f2w [1088,256], f2b (bbs_net_param_count() values).
+ */
+typedef struct bbs_net bbs_net;
+
+int64_t bbs_net_param_count(void);
+/* Network with room for batches of up to max_batch images; parameters zero
+ * until bbs_net_set_params. */
+bbs_status bbs_net_create(int32_t max_batch, bbs_net **out);
+void bbs_net_free(bbs_net *net);
+/* Set the float master parameters (host array of count values) and reset the
+ * optimiser state. */
+bbs_status bbs_net_set_params(bbs_net *net, const float *params, int64_t count);
+bbs_status bbs_net_get_params(const bbs_net *net, float *params, int64_t count);
+/* Logits of batch images ([batch, 64, 64] uint8, host or device) into a host
+ * array of batch x 1088 floats. */
+bbs_status bbs_net_forward(bbs_net *net, const uint8_t *images, int32_t images_on_device, int32_t batch,
+                           float *logits);
+/* One AdamW step (beta 0.9 / 0.999, eps 1e-8, decoupled weight decay on the
+ * weights) on the mean cross-entropy of both heads.  yaw[i] in [0, 64),
+ * xy[i] in [0, 1024) (host).  lr < 0: compute the gradients only.  loss_out
+ * (host float) and grads_out (host, param_count floats) may be NULL. */
+bbs_status bbs_net_train_step(bbs_net *net, const uint8_t *images, int32_t images_on_device, const int32_t *yaw,
+                              const int32_t *xy, int32_t batch, float lr, float weight_decay, float *loss_out,
+                              float *grads_out);
+/* Bird's-eye polar image of a scan into a host [64, 64] uint8 array: range
+ * bin floor(64 |(x, y)| / d_max) clamped to 63, azimuth bin
+ * floor(64 atan2(y, x) / 2 pi) mod 64, min(255, count) per cell. */
+bbs_status bbs_bev_image(const float *scan_xyz, int64_t k, int32_t scan_on_device, uint8_t *image);
 
 #ifdef __cplusplus
 }

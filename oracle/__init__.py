@@ -39,7 +39,7 @@ class Grid(C.Structure):
                 ("dmax", C.c_double), ("delta", C.c_double * MAX_LEVELS),
                 ("n", (C.c_int32 * MAX_LEVELS) * 3), ("dprime", (C.c_double * MAX_LEVELS) * 3),
                 ("a", (C.c_int32 * MAX_LEVELS) * 3), ("wmin", C.c_double * 3), ("wmax", C.c_double * 3),
-                ("lo", C.c_int32 * 3), ("hi", C.c_int32 * 3)]
+                ("lo", C.c_int32 * 3), ("hi", C.c_int32 * 3), ("tmin", C.c_double * 3), ("tmax", C.c_double * 3)]
 
 
 class Result(C.Structure):
@@ -47,7 +47,8 @@ class Result(C.Structure):
                 ("pose", C.c_double * 6), ("nodes_expanded", C.c_int64), ("nodes_scored", C.c_int64),
                 ("flushes", C.c_int64), ("leaves_accepted", C.c_int64), ("initial_size", C.c_int64),
                 ("initial_kept", C.c_int64), ("bound_checks", C.c_int64), ("bound_violations", C.c_int64),
-                ("violation_excess_sum", C.c_double)]
+                ("violation_excess_sum", C.c_double), ("prior_used", C.c_int32), ("seeded", C.c_int32),
+                ("seed_score", C.c_int32), ("pad", C.c_int32)]
 
     def as_dict(self):
         return {"found": self.found, "score": self.score, "leaf": list(self.leaf),
@@ -56,7 +57,8 @@ class Result(C.Structure):
                 "leaves_accepted": self.leaves_accepted, "initial_size": self.initial_size,
                 "initial_kept": self.initial_kept, "bound_checks": self.bound_checks,
                 "bound_violations": self.bound_violations,
-                "violation_excess_sum": self.violation_excess_sum}
+                "violation_excess_sum": self.violation_excess_sum, "prior_used": self.prior_used,
+                "seeded": self.seeded, "seed_score": self.seed_score}
 
 
 _lib = None
@@ -84,7 +86,7 @@ def lib():
         L.orc_score.argtypes = [P, P, I64, C.POINTER(Grid), I32, I32, I32, I32, I32, I32, I32]
         L.orc_score.restype = I32
         L.orc_score_nodes.argtypes = [P, P, I64, C.POINTER(Grid), P, I64, P, I32]
-        L.orc_localize.argtypes = [P, P, I64, C.POINTER(Grid), I32, I64, I32, I64, C.POINTER(Result), P, I64]
+        L.orc_localize.argtypes = [P, P, I64, C.POINTER(Grid), I32, I64, I32, I64, C.POINTER(Result), P, I64, P, I32]
         L.orc_localize.restype = C.c_int
         L.orc_bruteforce.argtypes = [P, P, I64, C.POINTER(Grid), I32, I32, C.POINTER(Result)]
         L.orc_bruteforce.restype = C.c_int
@@ -212,12 +214,17 @@ class Search:
         return out[:n]
 
     def localize(self, threshold: int, batch: int = 10000, threads: int = 1, max_scored: int = 0,
-                 trace_cap: int = 0) -> dict:
+                 trace_cap: int = 0, prior=None, n_seed_dives: int = 0) -> dict:
+        """Alg. 2.  prior: optional 1088 float logits (64 yaw bins, then 32 x 32
+        translation cells) that order the initial set; n_seed_dives greedy
+        dives from the best-prior initial nodes seed the incumbent."""
         res = Result()
         tr = np.zeros(max(trace_cap, 1), dtype=np.int64)
+        pr = None if prior is None else np.ascontiguousarray(prior, dtype=np.float32).reshape(1088)
         rc = lib().orc_localize(self.map.handle, self.scan.ctypes.data, self.k, C.byref(self.grid), int(threshold),
                                 int(batch), int(threads), int(max_scored), C.byref(res),
-                                tr.ctypes.data if trace_cap else None, int(trace_cap))
+                                tr.ctypes.data if trace_cap else None, int(trace_cap),
+                                pr.ctypes.data if pr is not None else None, int(n_seed_dives))
         if rc != 0:
             raise OracleError(f"orc_localize failed ({rc})")
         d = res.as_dict()

@@ -201,6 +201,7 @@ typedef struct {
     int32_t a[3][ORC_MAX_LEVELS];          /* divisions a from level l to l - 1 (l >= 1) */
     double wmin[3], wmax[3];               /* angular ranges */
     int32_t lo[3], hi[3];                  /* leaf translation index range per axis */
+    double tmin[3], tmax[3];               /* translation ranges [m] */
 } orc_grid;
 
 /*
@@ -263,6 +264,8 @@ int orc_setup(const float *scan, int64_t k, const float rmin[6], const float rma
             g->a[ax][l] = (g->n[ax][l - 1] + g->n[ax][l] - 1) / g->n[ax][l];
     }
     for (int ax = 0; ax < 3; ++ax) {
+        g->tmin[ax] = rmin[ax];
+        g->tmax[ax] = rmax[ax];
         double lo = ceil((double)rmin[ax] / (double)r);
         double hi = floor((double)rmax[ax] / (double)r);
         if (lo > hi) return ORC_ERR_ARG;
@@ -454,6 +457,8 @@ typedef struct {
     int64_t initial_size, initial_kept;
     int64_t bound_checks, bound_violations;  /* children scored / children above parent */
     double violation_excess_sum;             /* sum of (child - parent) / parent */
+    int32_t prior_used, seeded;              /* the prior ordered the initial set; a dive set the incumbent */
+    int32_t seed_score, pad;
 } orc_result;
 
 /*
@@ -506,6 +511,74 @@ static void decode_pose(const orc_grid *g, const int32_t leaf[6], double pose[6]
     for (int ax = 0; ax < 3; ++ax) pose[3 + ax] = cell_angle(g, ax, leaf[3 + ax], 0);
 }
 
+/* ------------------------------------------------------------------ learned prior (not in the paper)
+ *
+ * The prior is 1088 logits: 64 over yaw bins, then 32 x 32 over translation
+ * cells of the search box (x outer).  A top-level node's key is the logit of
+ * the yaw bin holding its yaw cell centre plus the logit of the translation
+ * cell holding its translation-cell centre.  It orders ties in the queue and
+ * picks where greedy seed dives start; it never changes a score.
+ */
+#define ORC_YAW_BINS 64
+#define ORC_XY_CELLS 32
+
+static double prior_key(const orc_grid *g, const float *prior, const orc_node *c)
+{
+    const double two_pi = 2.0 * 3.14159265358979323846;
+    double th = cell_angle(g, 2, c->ang[2], c->level);
+    double tm = th - two_pi * floor(th / two_pi);
+    int yb = (int)floor(tm / (two_pi / ORC_YAW_BINS));
+    if (yb < 0) yb = 0;
+    if (yb >= ORC_YAW_BINS) yb = ORC_YAW_BINS - 1;
+    int cell[2];
+    for (int ax = 0; ax < 2; ++ax) {
+        double rl = ldexp((double)g->r, c->level);
+        double x = rl * ((double)c->t[ax] + 0.5);
+        double lo = g->tmin[ax], hi = g->tmax[ax];
+        int ci = hi > lo ? (int)floor(ORC_XY_CELLS * (x - lo) / (hi - lo)) : 0;
+        if (ci < 0) ci = 0;
+        if (ci >= ORC_XY_CELLS) ci = ORC_XY_CELLS - 1;
+        cell[ax] = ci;
+    }
+    return (double)prior[yb] + (double)prior[ORC_YAW_BINS + cell[0] * ORC_XY_CELLS + cell[1]];
+}
+
+typedef struct {
+    double key;
+    int64_t index;
+} keyed;
+
+static int cmp_keyed(const void *a, const void *b)
+{
+    const keyed *x = (const keyed *)a, *y = (const keyed *)b;
+    if (x->key != y->key) return x->key > y->key ? -1 : 1;
+    return (x->index > y->index) - (x->index < y->index);
+}
+
+/* Greedy dive from c to a leaf: score every child, go to the highest-scoring
+ * one (ties: the first in branching order). */
+static int dive(const orc_map *m, const float *scan, int64_t k, const orc_grid *g, orc_node c, int32_t threads,
+                orc_result *res, orc_node *leaf)
+{
+    node_vec ch = {0};
+    int rc = ORC_OK;
+    while (c.level > 0) {
+        ch.n = 0;
+        if ((rc = branch(g, &c, &ch))) break;
+        res->nodes_expanded++;
+        if (ch.n == 0) { rc = 1; break; }
+        score_vec(m, scan, k, g, &ch, threads);
+        res->nodes_scored += ch.n;
+        int64_t bi = 0;
+        for (int64_t i = 1; i < ch.n; ++i)
+            if (ch.v[i].score > ch.v[bi].score) bi = i;
+        c = ch.v[bi];
+    }
+    free(ch.v);
+    *leaf = c;
+    return rc;
+}
+
 /*
  * Batched best-first branch and bound, Alg. 2.
  *  - best_score starts at score_threshold; initial nodes below it are removed
@@ -527,7 +600,7 @@ static void decode_pose(const orc_grid *g, const int32_t leaf[6], double pose[6]
  */
 int orc_localize(const orc_map *m, const float *scan, int64_t k, const orc_grid *g, int32_t threshold,
                  int64_t batch, int32_t threads, int64_t max_scored, orc_result *res,
-                 int64_t *trace_flush, int64_t trace_cap)
+                 int64_t *trace_flush, int64_t trace_cap, const float *prior, int32_t n_dives)
 {
     memset(res, 0, sizeof(*res));
     if (!m || !scan || k < 1 || batch < 1 || g->levels != m->levels) return ORC_ERR_ARG;
@@ -564,6 +637,25 @@ int orc_localize(const orc_map *m, const float *scan, int64_t k, const orc_grid 
                                         if (!node_valid(g, L, top.t, top.ang)) continue;
                                         if ((rc = vec_push(&pending, &top))) goto done;
                                     }
+    if (prior) {
+        int finite = 1;
+        for (int i = 0; i < ORC_YAW_BINS + ORC_XY_CELLS * ORC_XY_CELLS; ++i) finite = finite && isfinite(prior[i]);
+        if (finite) {
+            keyed *kv = (keyed *)malloc((size_t)(pending.n ? pending.n : 1) * sizeof(keyed));
+            orc_node *cp = (orc_node *)malloc((size_t)(pending.n ? pending.n : 1) * sizeof(orc_node));
+            if (!kv || !cp) { free(kv); free(cp); rc = ORC_ERR_OOM; goto done; }
+            for (int64_t i = 0; i < pending.n; ++i) {
+                kv[i].key = prior_key(g, prior, &pending.v[i]);
+                kv[i].index = i;
+                cp[i] = pending.v[i];
+            }
+            qsort(kv, (size_t)pending.n, sizeof(keyed), cmp_keyed);
+            for (int64_t i = 0; i < pending.n; ++i) pending.v[i] = cp[kv[i].index];
+            free(kv);
+            free(cp);
+            res->prior_used = 1;
+        }
+    }
     score_vec(m, scan, k, g, &pending, threads);
     res->initial_size = pending.n;
     res->nodes_scored = pending.n;
@@ -572,6 +664,21 @@ int orc_localize(const orc_map *m, const float *scan, int64_t k, const orc_grid 
         pending.v[i].seq = seq++;
         if ((rc = heap_push(&heap, &pending.v[i]))) goto done;
         res->initial_kept++;
+    }
+    if (res->prior_used && n_dives > 0) {
+        int started = 0;
+        for (int64_t i = 0; i < pending.n && started < n_dives; ++i) {
+            if (pending.v[i].score < threshold) continue;
+            ++started;
+            orc_node leaf;
+            if (dive(m, scan, k, g, pending.v[i], threads, res, &leaf) != ORC_OK) continue;
+            if (leaf.score < best) continue;
+            if (!have_match || leaf.score > best || leaf_lex_less(&leaf, &match)) match = leaf;
+            have_match = 1;
+            best = leaf.score;
+            res->seeded = 1;
+            res->seed_score = leaf.score;
+        }
     }
     pending.n = 0;
 

@@ -14,8 +14,8 @@ import os
 
 import numpy as np
 
-__all__ = ["LibraryMissing", "BbsError", "Map", "Workspace", "localize", "score_nodes", "lib", "library_path",
-           "EXPORTED_SYMBOLS"]
+__all__ = ["LibraryMissing", "BbsError", "Map", "Workspace", "localize", "score_nodes", "serve", "lib",
+           "library_path", "EXPORTED_SYMBOLS"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "_lib", "libbbs.so")
@@ -24,7 +24,8 @@ MAX_LEVELS = 16
 EXPORTED_SYMBOLS = (
     "bbs_default_options", "bbs_abi_version", "bbs_last_error", "bbs_build_map", "bbs_free_map", "bbs_map_info",
     "bbs_map_dump_level", "bbs_map_contains", "bbs_workspace_create", "bbs_workspace_free", "bbs_localize",
-    "bbs_score_nodes",
+    "bbs_score_nodes", "bbs_serve", "bbs_net_param_count", "bbs_net_create", "bbs_net_free", "bbs_net_set_params",
+    "bbs_net_get_params", "bbs_net_forward", "bbs_net_train_step", "bbs_bev_image",
 )
 
 STATUS = {0: "OK", -1: "INVALID_ARG", -2: "OOM", -3: "DEVICE", -4: "QUEUE_OVERFLOW", -5: "INTERNAL"}
@@ -46,7 +47,8 @@ class SearchRange(C.Structure):
 
 class Options(C.Structure):
     _fields_ = [("batch_size", C.c_int32), ("translation_only", C.c_int32), ("profile", C.c_int32),
-                ("reserved0", C.c_int32), ("stream", C.c_void_p), ("reserved", C.c_int64 * 4)]
+                ("n_seed_dives", C.c_int32), ("stream", C.c_void_p), ("prior", C.c_void_p),
+                ("persistent", C.c_int32), ("score_items", C.c_int32), ("reserved", C.c_int64 * 2)]
 
 
 class Result(C.Structure):
@@ -54,7 +56,8 @@ class Result(C.Structure):
                 ("nodes_expanded", C.c_int64), ("nodes_scored", C.c_int64), ("flushes", C.c_int64),
                 ("leaves_accepted", C.c_int64), ("initial_size", C.c_int64), ("initial_kept", C.c_int64),
                 ("score_kernel_ms", C.c_double), ("score_launches", C.c_int64), ("score_pairs", C.c_int64),
-                ("score_groups", C.c_int64), ("phase_ms", C.c_double * 4)]
+                ("score_groups", C.c_int64), ("phase_ms", C.c_double * 4), ("prior_used", C.c_int32),
+                ("seeded", C.c_int32), ("seed_score", C.c_int32), ("persistent_used", C.c_int32)]
 
     def as_dict(self):
         return {"found": self.found, "score": self.score, "leaf": list(self.leaf), "pose": list(self.pose),
@@ -63,7 +66,13 @@ class Result(C.Structure):
                 "initial_kept": self.initial_kept, "score_kernel_ms": self.score_kernel_ms,
                 "score_launches": self.score_launches, "score_pairs": self.score_pairs,
                 "score_groups": self.score_groups,
-                "phase_ms": list(self.phase_ms)}
+                "phase_ms": list(self.phase_ms), "prior_used": self.prior_used, "seeded": self.seeded,
+                "seed_score": self.seed_score, "persistent_used": self.persistent_used}
+
+
+class Query(C.Structure):
+    _fields_ = [("scan_xyz", C.c_void_p), ("k", C.c_int64), ("scan_on_device", C.c_int32),
+                ("score_threshold", C.c_int32), ("range", SearchRange), ("arrival_s", C.c_double)]
 
 
 _lib = None
@@ -101,6 +110,8 @@ def lib():
         L.bbs_localize.restype = C.c_int
         L.bbs_score_nodes.argtypes = [P, P, I64, C.POINTER(SearchRange), I32, P, I64, P]
         L.bbs_score_nodes.restype = C.c_int
+        L.bbs_serve.argtypes = [P, C.POINTER(Query), I64, I32, C.POINTER(Options), C.POINTER(Result), P, P]
+        L.bbs_serve.restype = C.c_int
         _lib = L
     return _lib
 
@@ -231,22 +242,31 @@ class Workspace:
 
 def localize(bmap: Map, scan, rmin, rmax, score_threshold: int, *, batch_size: int = 10000,
              translation_only: bool = False, profile: bool = False, workspace: Workspace | None = None,
-             stream=None) -> dict:
+             stream=None, prior=None, n_seed_dives: int = 0, persistent: bool = False,
+             score_items: int = 0) -> dict:
     """Global localization of one scan (Alg. 2 on the GPU).  Returns the result
-    fields as a dict (found, score, leaf, pose, node counters, timings)."""
+    fields as a dict (found, score, leaf, pose, node counters, timings).
+    prior: optional 1088 logits of the proposal network."""
     ptr, k, dev, keep = _points(scan, "scan")
     opt = Options()
     lib().bbs_default_options(C.byref(opt))
     opt.batch_size = int(batch_size)
     opt.translation_only = int(translation_only)
     opt.profile = int(profile)
+    opt.n_seed_dives = int(n_seed_dives)
+    opt.persistent = int(persistent)
+    opt.score_items = int(score_items)
+    pr = None
+    if prior is not None:
+        pr = np.ascontiguousarray(prior, dtype=np.float32).reshape(1088)
+        opt.prior = pr.ctypes.data
     st = _stream(stream)
     opt.stream = st
     rng = _range(rmin, rmax)
     res = Result()
     _check(lib().bbs_localize(bmap.handle, workspace.handle if workspace else None, ptr, k, dev, C.byref(rng),
                               int(score_threshold), C.byref(opt), C.byref(res)))
-    del keep
+    del keep, pr
     return res.as_dict()
 
 
@@ -260,3 +280,33 @@ def score_nodes(bmap: Map, scan, rmin, rmax, nodes, translation_only: bool = Fal
     _check(lib().bbs_score_nodes(bmap.handle, s.ctypes.data, len(s), C.byref(rng), int(translation_only),
                                  nd.ctypes.data, len(nd), out.ctypes.data))
     return out
+
+
+def serve(bmap: Map, scans, ranges, thresholds, arrivals, *, workers: int = 4, batch_size: int = 10000,
+          translation_only: bool = False) -> tuple[list, "np.ndarray", "np.ndarray"]:
+    """Serve a stream of queries (sorted by arrival time, seconds from the
+    start) with `workers` concurrent searches.  Returns (results, start_s,
+    end_s)."""
+    n = len(scans)
+    qs = (Query * max(n, 1))()
+    keep = []
+    for i in range(n):
+        ptr, k, dev, kp = _points(scans[i], "scan")
+        keep.append(kp)
+        qs[i].scan_xyz = ptr
+        qs[i].k = k
+        qs[i].scan_on_device = dev
+        qs[i].score_threshold = int(thresholds[i])
+        qs[i].range = _range(*ranges[i])
+        qs[i].arrival_s = float(arrivals[i])
+    opt = Options()
+    lib().bbs_default_options(C.byref(opt))
+    opt.batch_size = int(batch_size)
+    opt.translation_only = int(translation_only)
+    res = (Result * max(n, 1))()
+    t_start = np.zeros(max(n, 1), np.float64)
+    t_end = np.zeros(max(n, 1), np.float64)
+    _check(lib().bbs_serve(bmap.handle, qs, n, int(workers), C.byref(opt), res, t_start.ctypes.data,
+                           t_end.ctypes.data))
+    del keep
+    return [res[i].as_dict() for i in range(n)], t_start[:n], t_end[:n]

@@ -13,7 +13,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIBDIR, "libbbs.so")
-SOURCES = ["bbs_api.cpp", "bbs_map.hip", "bbs_search.hip"]
+SOURCES = ["bbs_api.cpp", "bbs_serve.cpp", "bbs_map.hip", "bbs_search.hip", "bbs_net.hip"]
 ARCH = os.environ.get("BBS_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [
@@ -35,14 +35,14 @@ def build(verbose: bool = False) -> str:
         cmd = [hipcc, *FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-c",
                os.path.join(CSRC, src), "-o", obj]
         if src.endswith(".cpp"):
-            cmd = [hipcc, "-O2", "-std=c++17", "-fPIC", "-Wall", "-I", os.path.join(ROOT, "include"), "-I", CSRC,
-                   "-c", os.path.join(CSRC, src), "-o", obj]
+            cmd = [hipcc, "-O2", "-std=c++17", "-fPIC", "-Wall", "-pthread", "-I", os.path.join(ROOT, "include"),
+                   "-I", CSRC, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)
         objs.append(obj)
     tmp = LIB + ".tmp"
-    cmd = [hipcc, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]
+    cmd = [hipcc, "-shared", "-fPIC", "-pthread", f"--offload-arch={ARCH}", *objs, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

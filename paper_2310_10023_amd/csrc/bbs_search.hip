@@ -56,6 +56,14 @@ struct State {
     int64_t pushed;           // nodes pushed since the start
     int64_t nodes_expanded, nodes_scored, flushes, leaves_accepted;
     int64_t groups_scored;
+    int64_t dive_scored;      // children scored by seed dives
+    int32_t seeded, seed_score;
+};
+
+// One greedy seed dive: its current node and the groups of its children.
+struct Dive {
+    uint4 node;
+    int32_t active, g0, ng, score;
 };
 
 inline int grid_for(int64_t n, int threads, int cap)
@@ -251,6 +259,13 @@ __device__ inline void rotation(const double2 *trig, const SearchConst &C, int l
 // probe chains) in flight.  A group's points are split over several
 // workgroups when the batch has few groups; partial counts are added with
 // integer atomics into scores zeroed by the producer of the batch.
+// Batch header fields written by another workgroup of the same launch are
+// read with device-scope loads (no stale first-level cache line).
+__device__ inline int32_t ld_agent(const int32_t *p)
+{
+    return __hip_atomic_load(const_cast<int32_t *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __device__ inline int bucket_of(int score, int level, const SearchConst &C)
 {
     return (C.K - score) * (C.levels + 1) + level;
@@ -264,7 +279,7 @@ __device__ void tile_pass(int t, const uint4 *groups, int32_t *scores, State *st
 {
     const int s = threadIdx.x;
     const int g = t * kTileGroups + s / 8, j = s & 7;
-    const int best = st->best;
+    const int best = ld_agent(&st->best);
     int q = -1;
     if (g < n_groups) {
         const uint4 G = groups[g];
@@ -298,19 +313,35 @@ __device__ void tile_pass(int t, const uint4 *groups, int32_t *scores, State *st
     }
 }
 
+struct ScoreSmem {
+    int red[kScoreThreads / 64][8];
+    int sq[kTileSlots];
+    int sm[kScoreThreads / 64];
+    int s_last;
+};
+
+struct ScoreArgs {
+    const uint4 *groups;
+    int32_t n_groups_fixed;    // used when st is NULL
+    const float *X, *Y, *Z;
+    const double2 *trig;
+    int32_t *scores;
+    int32_t *tile_done;        // NULL: no tile pass
+    int32_t *q_arr, *rank_arr, *hist;
+};
+
 template <bool POW2>
-__global__ __launch_bounds__(kScoreThreads) void k_score(const uint4 *__restrict__ groups, State *st,
-                                                          int32_t n_groups_fixed, const float *__restrict__ X,
-                                                          const float *__restrict__ Y, const float *__restrict__ Z,
-                                                          MapView map, const double2 *__restrict__ trig, SearchConst C,
-                                                          int32_t *__restrict__ scores, int32_t *tile_done,
-                                                          int32_t *q_arr, int32_t *rank_arr, int32_t *hist)
+__device__ void score_items(State *st, const ScoreArgs &A, const MapView &map, const SearchConst &C, ScoreSmem &sh)
 {
-    __shared__ int red[kScoreThreads / 64][8];
-    __shared__ int sq[kTileSlots];
-    __shared__ int sm[kScoreThreads / 64];
-    __shared__ int s_last;
-    const int n_groups = st ? (st->batch ? st->n_groups : 0) : n_groups_fixed;
+    const uint4 *__restrict__ groups = A.groups;
+    const float *__restrict__ X = A.X;
+    const float *__restrict__ Y = A.Y;
+    const float *__restrict__ Z = A.Z;
+    const double2 *__restrict__ trig = A.trig;
+    int32_t *__restrict__ scores = A.scores;
+    int32_t *tile_done = A.tile_done;
+    auto &red = sh.red;
+    const int n_groups = st ? (ld_agent(&st->batch) ? ld_agent(&st->n_groups) : 0) : A.n_groups_fixed;
     if (n_groups <= 0) return;
     const int K = C.K;
     int S = (C.score_items + n_groups - 1) / n_groups;
@@ -424,16 +455,23 @@ __global__ __launch_bounds__(kScoreThreads) void k_score(const uint4 *__restrict
         if (threadIdx.x == 0) {
             const int in_tile = min(kTileGroups, n_groups - t * kTileGroups) * S;
             const int prev = atomicAdd(&tile_done[t], 1);
-            s_last = (prev == in_tile - 1);
+            sh.s_last = (prev == in_tile - 1);
         }
         __syncthreads();
-        if (s_last) {
+        if (sh.s_last) {
             __threadfence();
-            tile_pass(t, groups, scores, st, C, n_groups, q_arr, rank_arr, hist, sq, sm);
-            if (threadIdx.x == 0) tile_done[t] = 0;
+            tile_pass(t, groups, scores, st, C, n_groups, A.q_arr, A.rank_arr, A.hist, sh.sq, sh.sm);
+            if (threadIdx.x == 0) __hip_atomic_store(&tile_done[t], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         __syncthreads();
     }
+}
+
+template <bool POW2>
+__global__ __launch_bounds__(kScoreThreads) void k_score(State *st, ScoreArgs A, MapView map, SearchConst C)
+{
+    __shared__ ScoreSmem sh;
+    score_items<POW2>(st, A, map, C, sh);
 }
 
 // ------------------------------------------------------------------ initial set
@@ -500,6 +538,7 @@ struct PushBufs {
 // the scoring kernel's tile passes: per bucket the prefix of the tile counts
 // (tile order = batch order), chunk allocation and chain link, then every
 // kept child is written to its slot and the histogram is cleared.
+template <int NT>
 __device__ void push_finish(State *st, const SearchConst &C, Bucket *bk, const uint4 *groups, const PushBufs &B,
                             int *sm)
 {
@@ -510,7 +549,7 @@ __device__ void push_finish(State *st, const SearchConst &C, Bucket *bk, const u
     if (q_max < q_min || kept == 0) return;
     const int nq = q_max - q_min + 1;
     // per-bucket prefix over tiles (loads first, in blocks of 16 tiles)
-    for (int qi = tid; qi < nq; qi += kSerialThreads) {
+    for (int qi = tid; qi < nq; qi += NT) {
         const int q = q_min + qi;
         int acc = 0;
         for (int t0 = 0; t0 < n_tiles; t0 += 16) {
@@ -529,7 +568,7 @@ __device__ void push_finish(State *st, const SearchConst &C, Bucket *bk, const u
     __syncthreads();
     // chunks needed, then allocation in bucket order
     int64_t total_new = 0;
-    for (int c = 0; c < nq; c += kSerialThreads) {
+    for (int c = 0; c < nq; c += NT) {
         const int i = c + tid;
         int nch = 0;
         if (i < nq && B.totals[i] > 0) {
@@ -537,7 +576,7 @@ __device__ void push_finish(State *st, const SearchConst &C, Bucket *bk, const u
             bucket_space(bk[q_min + i], B.totals[i], T, f, space, nch);
         }
         int tot;
-        (void)block_scan_incl<kSerialThreads>(nch, sm, &tot);
+        (void)block_scan_incl<NT>(nch, sm, &tot);
         total_new += tot;
     }
     const int chunk_top = st->chunk_top;
@@ -550,7 +589,7 @@ __device__ void push_finish(State *st, const SearchConst &C, Bucket *bk, const u
         return;
     }
     int64_t run = 0;
-    for (int c = 0; c < nq; c += kSerialThreads) {
+    for (int c = 0; c < nq; c += NT) {
         const int i = c + tid;
         const int q = q_min + i;
         const int cnt = i < nq ? B.totals[i] : 0;
@@ -561,7 +600,7 @@ __device__ void push_finish(State *st, const SearchConst &C, Bucket *bk, const u
             bucket_space(b, cnt, T, f, space, nch);
         }
         int tot;
-        const int incl = block_scan_incl<kSerialThreads>(nch, sm, &tot);
+        const int incl = block_scan_incl<NT>(nch, sm, &tot);
         if (cnt > 0) {
             const int c0 = chunk_top + (int)run + incl - nch;
             B.pT[i] = T;
@@ -587,7 +626,7 @@ __device__ void push_finish(State *st, const SearchConst &C, Bucket *bk, const u
     __syncthreads();
     // scatter: the child of rank r in its bucket fills the tail chunk first
     const int n_slots = n_tiles * kTileSlots;
-    for (int i = tid; i < n_slots; i += kSerialThreads) {
+    for (int i = tid; i < n_slots; i += NT) {
         const int q = B.q_arr[i];
         if (q < 0) continue;
         const int t = i / kTileSlots, sl = i % kTileSlots;
@@ -608,7 +647,7 @@ __device__ void push_finish(State *st, const SearchConst &C, Bucket *bk, const u
         B.arena[pos] = make_uint4(pack16(x, y), pack16(z, hi16u(G.y)), G.z, G.w & 0xFFu);
     }
     __syncthreads();
-    for (int i = tid; i < n_slots; i += kSerialThreads) {
+    for (int i = tid; i < n_slots; i += NT) {
         const int q = B.q_arr[i];
         if (q >= 0 && B.rank_arr[i] == 0) B.hist[(int64_t)(i / kTileSlots) * C.q_count + q] = 0;
     }
@@ -655,6 +694,7 @@ __device__ inline void child_counts(const SearchConst &C, const int32_t t[3], co
 // passes b.  Buckets below the running best are never touched (their nodes
 // would be pruned).  Writes the pending children as groups and zeroes their
 // score slots.
+template <int NT>
 __device__ void gather(State *st, Bucket *bk, const int32_t *chunk_next, const uint4 *arena, const SearchConst &C,
                        uint4 *groups, int32_t *scores, int *sm, int (*smatch)[6], int *s_last)
 {
@@ -673,10 +713,10 @@ __device__ void gather(State *st, Bucket *bk, const int32_t *chunk_next, const u
         if (best > C.K) break;
         const int qlim = min((C.K - best) * Lp1 + C.levels, C.q_count - 1);
         int found = INT_MAX;
-        for (int b0 = q; b0 <= qlim; b0 += kSerialThreads) {
+        for (int b0 = q; b0 <= qlim; b0 += NT) {
             const int qq = b0 + tid;
             const int cand = (qq <= qlim && bk[qq].head_chunk >= 0) ? qq : INT_MAX;
-            found = block_min_int<kSerialThreads>(cand, sm);
+            found = block_min_int<NT>(cand, sm);
             if (found != INT_MAX) break;
         }
         if (found == INT_MAX) break;
@@ -689,8 +729,7 @@ __device__ void gather(State *st, Bucket *bk, const int32_t *chunk_next, const u
             int32_t mine[6] = {INT_MAX, INT_MAX, INT_MAX, INT_MAX, INT_MAX, INT_MAX};
             while (c >= 0) {
                 const int end = c == b.tail_chunk ? b.tail_fill : kChunk;
-                const int i = off + tid;
-                if (i < end) {
+                for (int i = off + tid; i < end; i += NT) {
                     int32_t t[3], ang[3], lv;
                     node_unpack(arena[(int64_t)c * kChunk + i], t, ang, lv);
                     const int32_t cand[6] = {t[0], t[1], t[2], ang[0], ang[1], ang[2]};
@@ -704,7 +743,7 @@ __device__ void gather(State *st, Bucket *bk, const int32_t *chunk_next, const u
             __syncthreads();
             for (int k = 0; k < 6; ++k) smatch[tid][k] = mine[k];
             __syncthreads();
-            for (int sh = kSerialThreads / 2; sh > 0; sh >>= 1) {
+            for (int sh = NT / 2; sh > 0; sh >>= 1) {
                 if (tid < sh && leaf_less(smatch[tid + sh], smatch[tid]))
                     for (int k = 0; k < 6; ++k) smatch[tid][k] = smatch[tid + sh][k];
                 __syncthreads();
@@ -720,7 +759,7 @@ __device__ void gather(State *st, Bucket *bk, const int32_t *chunk_next, const u
         }
         while (c >= 0) {
             const int end = c == b.tail_chunk ? b.tail_fill : kChunk;
-            const int avail = end - off;
+            const int avail = min(end - off, NT);
             const int i = off + tid;
             const bool valid = tid < avail;
             int32_t t[3] = {0, 0, 0}, ang[3] = {0, 0, 0}, lv = level;
@@ -731,10 +770,10 @@ __device__ void gather(State *st, Bucket *bk, const int32_t *chunk_next, const u
                 child_counts(C, t, ang, level, rc, tmask, nn, ng);
             }
             int tot_n, tot_g;
-            const int incl_n = block_scan_incl<kSerialThreads>(nn, sm, &tot_n);
-            const int incl_g = block_scan_incl<kSerialThreads>(ng, sm, &tot_g);
+            const int incl_n = block_scan_incl<NT>(nn, sm, &tot_n);
+            const int incl_g = block_scan_incl<NT>(ng, sm, &tot_g);
             const int over = (valid && pend + incl_n > C.batch) ? tid : INT_MAX;
-            const int cutidx = block_min_int<kSerialThreads>(over, sm);
+            const int cutidx = block_min_int<NT>(over, sm);
             const int consumed = cutidx != INT_MAX ? cutidx + 1 : avail;
             if (tid < consumed && ng > 0) {
                 int gi = ngrp + incl_g - ng;
@@ -778,7 +817,7 @@ __device__ void gather(State *st, Bucket *bk, const int32_t *chunk_next, const u
         ++q;
     }
     __syncthreads();
-    for (int i = tid; i < 8 * ngrp; i += kSerialThreads) scores[i] = 0;
+    for (int i = tid; i < 8 * ngrp; i += NT) scores[i] = 0;
     if (tid == 0) {
         st->best = best;
         st->have_match = have;
@@ -806,19 +845,191 @@ __device__ void gather(State *st, Bucket *bk, const int32_t *chunk_next, const u
 // The serial part of an iteration, one workgroup: push the scored batch,
 // then (unless this is an initial-set chunk with more to come) gather the
 // next one.
+template <int NT>
+struct SerialSmem {
+    int sm[NT / 64];
+    int smatch[NT][6];
+    int s_last[2];
+};
+
+template <int NT>
+__device__ void serial_body(State *st, const SearchConst &C, Bucket *bk, uint4 *groups, int32_t *scores,
+                            const PushBufs &B, int do_gather, SerialSmem<NT> &sh)
+{
+    if (ld_agent(&st->done)) return;
+    if (ld_agent(&st->batch)) push_finish<NT>(st, C, bk, groups, B, sh.sm);
+    __syncthreads();
+    if (ld_agent(&st->done)) return;
+    if (threadIdx.x == 0) st->batch = 0;
+    __syncthreads();
+    if (do_gather) gather<NT>(st, bk, B.chunk_next, B.arena, C, groups, scores, sh.sm, sh.smatch, sh.s_last);
+}
+
 __global__ __launch_bounds__(kSerialThreads) void k_serial(State *st, SearchConst C, Bucket *bk, uint4 *groups,
                                                            int32_t *scores, PushBufs B, int do_gather)
 {
-    __shared__ int sm[kSerialThreads / 64];
-    __shared__ int smatch[kSerialThreads][6];
-    __shared__ int s_last[2];
-    if (st->done) return;
-    if (st->batch) push_finish(st, C, bk, groups, B, sm);
+    __shared__ SerialSmem<kSerialThreads> sh;
+    serial_body<kSerialThreads>(st, C, bk, groups, scores, B, do_gather, sh);
+}
+
+// ------------------------------------------------------------------ persistent search loop
+
+constexpr int kPersistThreads = 256;
+constexpr unsigned kSpinLimit = 1u << 26;
+
+// Grid-wide barrier for a cooperative launch: arrive on bar[0], wait for the
+// generation in bar[1] to move.  The wait is bounded: on timeout the error
+// flag gets bit 4 and every workgroup leaves the loop.  Device-scope fences
+// on both sides publish the workgroups' writes to each other.
+__device__ bool grid_sync(unsigned *bar, int32_t *err, int *s_ok)
+{
     __syncthreads();
-    if (st->done) return;
-    if (threadIdx.x == 0) st->batch = 0;
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const unsigned gen = __hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        int ok = 1;
+        if (atomicAdd(&bar[0], 1u) == gridDim.x - 1) {
+            __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __threadfence();
+            atomicAdd(&bar[1], 1u);
+        } else {
+            unsigned spins = 0;
+            while (__hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+                __builtin_amdgcn_s_sleep(1);
+                if (++spins > kSpinLimit) {
+                    atomicOr(err, 4);
+                    ok = 0;
+                    break;
+                }
+            }
+        }
+        __threadfence();
+        *s_ok = ok && !(ld_agent(err) & 4);
+    }
     __syncthreads();
-    if (do_gather) gather(st, bk, B.chunk_next, B.arena, C, groups, scores, sm, smatch, s_last);
+    return *s_ok != 0;
+}
+
+// The whole search loop in one cooperative launch: every workgroup scores
+// the pending batch, then workgroup 0 pushes it and gathers the next one.
+template <bool POW2>
+__global__ __launch_bounds__(kPersistThreads) void k_persistent(State *st, ScoreArgs A, MapView map, SearchConst C,
+                                                                Bucket *bk, uint4 *groups, int32_t *scores,
+                                                                PushBufs B, unsigned *bar, int32_t max_iters)
+{
+    __shared__ ScoreSmem ssh;
+    __shared__ SerialSmem<kPersistThreads> sh;
+    __shared__ int s_ok;
+    for (int it = 0; it < max_iters; ++it) {
+        if (ld_agent(&st->done)) break;
+        score_items<POW2>(st, A, map, C, ssh);
+        if (!grid_sync(bar, &st->error, &s_ok)) break;
+        if (blockIdx.x == 0) serial_body<kPersistThreads>(st, C, bk, groups, scores, B, 1, sh);
+        if (!grid_sync(bar, &st->error, &s_ok)) break;
+    }
+}
+
+// ------------------------------------------------------------------ learned prior: batches and seed dives
+
+// A batch already written to `groups` (initial nodes in prior order): zero
+// its scores and reset the push bookkeeping.
+__global__ void k_begin_batch(State *st, int32_t *scores, int32_t n_groups)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < 8 * n_groups; i += gridDim.x * blockDim.x) scores[i] = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->n_groups = n_groups;
+        st->batch = 1;
+        st->q_min = INT_MAX;
+        st->q_max = -1;
+        st->kept = 0;
+    }
+}
+
+// Children of every live dive as groups (branching order), one after the
+// other; a dive whose node has no child stops.  `ds` is the batch header the
+// scoring kernel reads.
+__global__ void k_dive_expand(Dive *d, int M, SearchConst C, uint4 *groups, int32_t *scores, State *st, State *ds)
+{
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    int g = 0;
+    for (int i = 0; i < M; ++i) {
+        if (!d[i].active) continue;
+        int32_t t[3], ang[3], level;
+        node_unpack(d[i].node, t, ang, level);
+        if (level == 0) continue;
+        int rc[3], nn, ng;
+        uint32_t tmask;
+        child_counts(C, t, ang, level, rc, tmask, nn, ng);
+        st->nodes_expanded += 1;
+        d[i].g0 = g;
+        d[i].ng = ng;
+        if (ng == 0) {
+            d[i].active = 0;
+            continue;
+        }
+        for (int ja = 0; ja < rc[0]; ++ja)
+            for (int jb = 0; jb < rc[1]; ++jb)
+                for (int jg = 0; jg < rc[2]; ++jg) {
+                    const int ra = C.a[0][level] * ang[0] + ja;
+                    const int rb = C.a[1][level] * ang[1] + jb;
+                    const int rg = C.a[2][level] * ang[2] + jg;
+                    for (int j = 0; j < 8; ++j) scores[8 * g + j] = 0;
+                    groups[g++] = make_uint4(pack16(2 * t[0], 2 * t[1]), pack16(2 * t[2], ra), pack16(rb, rg),
+                                             (uint32_t)(level - 1) | (tmask << 8));
+                }
+    }
+    ds->batch = 1;
+    ds->n_groups = g;
+}
+
+// Each live dive moves to its highest-scoring child (ties: the first in
+// branching order).
+__global__ void k_dive_pick(Dive *d, int M, const uint4 *groups, const int32_t *scores, State *st)
+{
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    for (int i = 0; i < M; ++i) {
+        if (!d[i].active) continue;
+        int best = -1;
+        uint4 node = d[i].node;
+        for (int gi = d[i].g0; gi < d[i].g0 + d[i].ng; ++gi) {
+            const uint4 G = groups[gi];
+            const uint32_t mask = (G.w >> 8) & 0xFF;
+            for (int j = 0; j < 8; ++j) {
+                if (!((mask >> j) & 1u)) continue;
+                const int sc = scores[8 * gi + j];
+                st->dive_scored += 1;
+                if (sc > best) {
+                    best = sc;
+                    const int jx = (j >> 2) & 1, jy = (j >> 1) & 1, jz = j & 1;
+                    node = make_uint4(pack16(lo16s(G.x) + jx, hi16s(G.x) + jy), pack16(lo16s(G.y) + jz, hi16u(G.y)),
+                                      G.z, G.w & 0xFFu);
+                }
+            }
+        }
+        d[i].node = node;
+        d[i].score = best;
+    }
+}
+
+// The best dive leaf (highest score, then lexicographically smallest) seeds
+// the incumbent if it reaches the running best.
+__global__ void k_dive_seed(const Dive *d, int M, State *st)
+{
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    for (int i = 0; i < M; ++i) {
+        if (!d[i].active) continue;
+        int32_t t[3], ang[3], level;
+        node_unpack(d[i].node, t, ang, level);
+        if (level != 0 || d[i].score < st->best) continue;
+        const int32_t leaf[6] = {t[0], t[1], t[2], ang[0], ang[1], ang[2]};
+        if (!st->have_match || d[i].score > st->best || leaf_less(leaf, st->match)) {
+            for (int k = 0; k < 6; ++k) st->match[k] = leaf[k];
+        }
+        st->have_match = 1;
+        st->best = d[i].score;
+        st->seeded = 1;
+        st->seed_score = d[i].score;
+    }
 }
 
 // ------------------------------------------------------------------ host side
@@ -892,6 +1103,12 @@ struct bbs_workspace {
     int64_t state_n = 0;
     unsigned long long *maxsq = nullptr;
     int64_t maxsq_n = 0;
+    Dive *dives = nullptr;
+    int64_t dives_n = 0;
+    unsigned *bar = nullptr;
+    int64_t bar_n = 0;
+    State *dstate = nullptr;
+    int64_t dstate_n = 0;
     State *host_state = nullptr;   // pinned
     std::vector<hipEvent_t> ev;
     bool hist_dirty = true;
@@ -904,7 +1121,7 @@ void free_ws(bbs_workspace *w)
 {
     void *ptrs[] = {w->arena, w->chunk_next, w->buckets, w->hist, w->totals, w->pT, w->pf, w->pc0, w->groups, w->scores,
                     w->q_arr, w->rank_arr, w->tile_done, w->scan, w->scan_aos, w->scan_tmp, w->mkeys, w->mhist,
-                    w->trig, w->state, w->maxsq};
+                    w->trig, w->state, w->maxsq, w->dives, w->dstate, w->bar};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (w->host_state) (void)hipHostFree(w->host_state);
@@ -1056,18 +1273,30 @@ bbs_status setup_search(const bbs_map *m, bbs_workspace *ws, const float *scan, 
     return BBS_OK;
 }
 
+ScoreArgs score_args(const Setup &S, bbs_workspace *ws, int32_t n_fixed, bool tile_pass)
+{
+    ScoreArgs A;
+    A.groups = ws->groups;
+    A.n_groups_fixed = n_fixed;
+    A.X = ws->scan;
+    A.Y = ws->scan + S.C.K;
+    A.Z = ws->scan + 2 * (int64_t)S.C.K;
+    A.trig = ws->trig;
+    A.scores = ws->scores;
+    A.tile_done = tile_pass ? ws->tile_done : nullptr;
+    A.q_arr = ws->q_arr;
+    A.rank_arr = ws->rank_arr;
+    A.hist = ws->hist;
+    return A;
+}
+
 void launch_score(const Setup &S, const bbs_map *m, bbs_workspace *ws, State *st, int32_t n_fixed, int grid,
                   bool tile_pass)
 {
-    const float *X = ws->scan, *Y = ws->scan + S.C.K, *Z = ws->scan + 2 * (int64_t)S.C.K;
-    MapView v = m->view();
-    int32_t *td = tile_pass ? ws->tile_done : nullptr;
-    if (S.pow2)
-        k_score<true><<<grid, kScoreThreads, 0, S.s>>>(ws->groups, st, n_fixed, X, Y, Z, v, ws->trig, S.C, ws->scores,
-                                                        td, ws->q_arr, ws->rank_arr, ws->hist);
-    else
-        k_score<false><<<grid, kScoreThreads, 0, S.s>>>(ws->groups, st, n_fixed, X, Y, Z, v, ws->trig, S.C, ws->scores,
-                                                         td, ws->q_arr, ws->rank_arr, ws->hist);
+    const ScoreArgs A = score_args(S, ws, n_fixed, tile_pass);
+    const MapView v = m->view();
+    if (S.pow2) k_score<true><<<grid, kScoreThreads, 0, S.s>>>(st, A, v, S.C);
+    else k_score<false><<<grid, kScoreThreads, 0, S.s>>>(st, A, v, S.C);
 }
 
 int64_t max_children(const Grid &g)
@@ -1075,6 +1304,57 @@ int64_t max_children(const Grid &g)
     int64_t mc = 8;
     for (int l = 1; l <= g.levels; ++l) mc = std::max<int64_t>(mc, 8LL * g.a[0][l] * g.a[1][l] * g.a[2][l]);
     return mc;
+}
+
+// Initial nodes in descending prior key (yaw-bin logit + cell logit, summed in
+// double), ties in enumeration order, as one-node groups.
+std::vector<uint4> prior_order(const Grid &g, const bbs_search_range *range, const float *prior)
+{
+    const int L = g.levels;
+    const double two_pi = 2.0 * 3.14159265358979323846;
+    struct Item {
+        double key;
+        uint4 grp;
+    };
+    std::vector<Item> items;
+    const int32_t P0[3] = {g.lo[0] >> (L + 1), g.lo[1] >> (L + 1), g.lo[2] >> (L + 1)};
+    const int32_t P1[3] = {g.hi[0] >> (L + 1), g.hi[1] >> (L + 1), g.hi[2] >> (L + 1)};
+    for (int32_t px = P0[0]; px <= P1[0]; ++px)
+        for (int32_t py = P0[1]; py <= P1[1]; ++py)
+            for (int32_t pz = P0[2]; pz <= P1[2]; ++pz)
+                for (int32_t ia = 0; ia < g.n[0][L]; ++ia)
+                    for (int32_t ib = 0; ib < g.n[1][L]; ++ib)
+                        for (int32_t ig = 0; ig < g.n[2][L]; ++ig) {
+                            const double th = cell_angle(g, 2, ig, L);
+                            const double tm = th - two_pi * std::floor(th / two_pi);
+                            int yb = (int)std::floor(tm / (two_pi / 64));
+                            yb = std::min(std::max(yb, 0), 63);
+                            for (int j = 0; j < 8; ++j) {
+                                const int jx = (j >> 2) & 1, jy = (j >> 1) & 1, jz = j & 1;
+                                const int32_t t[3] = {2 * px + jx, 2 * py + jy, 2 * pz + jz};
+                                bool ok = true;
+                                for (int a = 0; a < 3; ++a) ok = ok && t[a] >= (g.lo[a] >> L) && t[a] <= (g.hi[a] >> L);
+                                if (!ok) continue;
+                                int cell[2];
+                                for (int a = 0; a < 2; ++a) {
+                                    const double rl = std::ldexp((double)g.r, L);
+                                    const double x = rl * ((double)t[a] + 0.5);
+                                    const double lo = range->min[a], hi = range->max[a];
+                                    int c = hi > lo ? (int)std::floor(32 * (x - lo) / (hi - lo)) : 0;
+                                    cell[a] = std::min(std::max(c, 0), 31);
+                                }
+                                const double key = (double)prior[yb] + (double)prior[64 + cell[0] * 32 + cell[1]];
+                                const int bj = 4 * (t[0] & 1) + 2 * (t[1] & 1) + (t[2] & 1);
+                                const uint4 grp = make_uint4(pack16(t[0] - (t[0] & 1), t[1] - (t[1] & 1)),
+                                                             pack16(t[2] - (t[2] & 1), ia), pack16(ib, ig),
+                                                             (uint32_t)L | ((1u << bj) << 8));
+                                items.push_back(Item{key, grp});
+                            }
+                        }
+    std::stable_sort(items.begin(), items.end(), [](const Item &a, const Item &b) { return a.key > b.key; });
+    std::vector<uint4> out(items.size());
+    for (size_t i = 0; i < items.size(); ++i) out[i] = items[i].grp;
+    return out;
 }
 
 }  // namespace
@@ -1155,6 +1435,9 @@ extern "C" bbs_status bbs_localize(const bbs_map *map, bbs_workspace *ws, const 
     bbs_status st = setup_search(map, ws, scan_xyz, k, scan_on_device, range, o.translation_only, score_threshold,
                                  o.batch_size, s, S);
     if (st) return st;
+    if (o.score_items < 0 || o.score_items > (1 << 20))
+        return fail(BBS_ERR_INVALID_ARG, "bbs_localize: score_items must be in [0, 2^20]");
+    if (o.score_items > 0) S.C.score_items = o.score_items;
     const Grid &g = S.g;
     const SearchConst &C = S.C;
     const int L = g.levels;
@@ -1237,18 +1520,69 @@ extern "C" bbs_status bbs_localize(const bbs_map *map, bbs_workspace *ws, const 
     };
     const double t_setup = ms_since(t_start);
 
+    // prior (learned proposal): usable only if every logit is finite
+    bool use_prior = o.prior != nullptr;
+    for (int i = 0; use_prior && i < 1088; ++i) use_prior = std::isfinite(o.prior[i]);
+    // at most 64 dives, and never more children than the group buffer holds
+    const int n_dives = use_prior ? (int)std::max<int64_t>(0, std::min<int64_t>({(int64_t)o.n_seed_dives, 64,
+                                                                                 cap_groups / std::max<int64_t>(1, mc / 8)}))
+                                  : 0;
+    std::vector<uint4> ordered;
+    if (use_prior) ordered = prior_order(g, range, o.prior);
+    std::vector<uint4> cand;          // dive start nodes: first initial nodes (prior order) reaching the threshold
+    std::vector<int32_t> cand_score;
+
     // initial set, in chunks of the group buffer; the last chunk's serial
-    // kernel also gathers the first batch of the search
+    // kernel also gathers the first batch of the search (unless dives come first)
     int64_t init_chunks = 0;
-    for (int64_t g0 = 0; g0 < n_init_groups; g0 += cap_groups) {
-        int32_t cnt = (int32_t)std::min<int64_t>(cap_groups, n_init_groups - g0);
-        k_enum_initial<<<grid_for(cnt, 256, 4096), 256, 0, s>>>(ws->groups, ws->scores, g0, cnt, C, P0[0], P0[1],
-                                                                 P0[2], PN[1], PN[2], ws->state);
+    const int64_t n_groups_init = use_prior ? (int64_t)ordered.size() : n_init_groups;
+    for (int64_t g0 = 0; g0 < n_groups_init; g0 += cap_groups) {
+        const int32_t cnt = (int32_t)std::min<int64_t>(cap_groups, n_groups_init - g0);
+        const bool last = g0 + cnt >= n_groups_init;
+        if (use_prior) {
+            BBS_HIP(hipMemcpyAsync(ws->groups, ordered.data() + g0, (size_t)cnt * sizeof(uint4), hipMemcpyHostToDevice,
+                                   s));
+            k_begin_batch<<<grid_for(8 * (int64_t)cnt, 256, 1024), 256, 0, s>>>(ws->state, ws->scores, cnt);
+        } else {
+            k_enum_initial<<<grid_for(cnt, 256, 4096), 256, 0, s>>>(ws->groups, ws->scores, g0, cnt, C, P0[0], P0[1],
+                                                                     P0[2], PN[1], PN[2], ws->state);
+        }
         if (prof) BBS_HIP(record(ev_used++));
         launch_score(S, map, ws, ws->state, 0, score_grid, true);
         if (prof) BBS_HIP(record(ev_used++));
-        serial(g0 + cnt >= n_init_groups ? 1 : 0);
+        if (n_dives > 0 && (int)cand.size() < n_dives) {
+            std::vector<int32_t> sc((size_t)cnt * 8);
+            BBS_HIP(hipMemcpyAsync(sc.data(), ws->scores, sc.size() * 4, hipMemcpyDeviceToHost, s));
+            BBS_HIP(hipStreamSynchronize(s));
+            for (int32_t i = 0; i < cnt && (int)cand.size() < n_dives; ++i) {
+                const uint4 G = ordered[(size_t)(g0 + i)];
+                const uint32_t mask = (G.w >> 8) & 0xFF;
+                const int j = __builtin_ctz(mask);
+                const int32_t v = sc[(size_t)i * 8 + j];
+                if (v < C.threshold) continue;
+                const int jx = (j >> 2) & 1, jy = (j >> 1) & 1, jz = j & 1;
+                cand.push_back(make_uint4(pack16(lo16s(G.x) + jx, hi16s(G.x) + jy), pack16(lo16s(G.y) + jz, hi16u(G.y)),
+                                          G.z, G.w & 0xFFu));
+                cand_score.push_back(v);
+            }
+        }
+        serial(last && cand.empty() ? 1 : 0);
         ++init_chunks;
+    }
+    if (!cand.empty()) {
+        const int M = (int)cand.size();
+        std::vector<Dive> d((size_t)M);
+        for (int i = 0; i < M; ++i) d[i] = Dive{cand[i], 1, 0, 0, cand_score[i]};
+        if (ensure(ws->dives, ws->dives_n, M) || ensure(ws->dstate, ws->dstate_n, 1)) return BBS_ERR_OOM;
+        BBS_HIP(hipMemcpyAsync(ws->dives, d.data(), (size_t)M * sizeof(Dive), hipMemcpyHostToDevice, s));
+        BBS_HIP(hipMemsetAsync(ws->dstate, 0, sizeof(State), s));
+        for (int step = 0; step < L; ++step) {
+            k_dive_expand<<<1, 64, 0, s>>>(ws->dives, M, C, ws->groups, ws->scores, ws->state, ws->dstate);
+            launch_score(S, map, ws, ws->dstate, 0, score_grid, false);
+            k_dive_pick<<<1, 64, 0, s>>>(ws->dives, M, ws->groups, ws->scores, ws->state);
+        }
+        k_dive_seed<<<1, 64, 0, s>>>(ws->dives, M, ws->state);
+        serial(1);
     }
     BBS_HIP(hipGetLastError());
     BBS_HIP(hipMemcpyAsync(ws->host_state, ws->state, sizeof(State), hipMemcpyDeviceToHost, s));
@@ -1261,11 +1595,49 @@ extern "C" bbs_status bbs_localize(const bbs_map *map, bbs_workspace *ws, const 
         return fail(BBS_ERR_QUEUE_OVERFLOW, "bbs_localize: node queue capacity exceeded by the initial set");
     }
 
+    // persistent search loop: one cooperative launch runs every iteration
+    bool persistent_used = false;
+    if (o.persistent && !init_done) {
+        if (ensure(ws->bar, ws->bar_n, 2)) return BBS_ERR_OOM;
+        BBS_HIP(hipMemsetAsync(ws->bar, 0, 2 * sizeof(unsigned), s));
+        int dev = 0, cus = 0, per_cu = 0;
+        BBS_HIP(hipGetDevice(&dev));
+        BBS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        const void *fn = S.pow2 ? reinterpret_cast<const void *>(&k_persistent<true>)
+                                : reinterpret_cast<const void *>(&k_persistent<false>);
+        hipError_t oe = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kPersistThreads, 0);
+        if (oe == hipSuccess && per_cu > 0) {
+            ScoreArgs A = score_args(S, ws, 0, true);
+            MapView v = map->view();
+            SearchConst Cv = C;
+            State *stp = ws->state;
+            Bucket *bkp = ws->buckets;
+            uint4 *gp = ws->groups;
+            int32_t *sp = ws->scores;
+            unsigned *barp = ws->bar;
+            int32_t max_it = 1 << 24;
+            void *args[] = {&stp, &A, &v, &Cv, &bkp, &gp, &sp, &B, &barp, &max_it};
+            const int grid = cus * std::min(per_cu, 4);
+            oe = hipLaunchCooperativeKernel(fn, dim3(grid), dim3(kPersistThreads), args, 0, s);
+            if (oe == hipSuccess) persistent_used = true;
+        }
+        if (!persistent_used) (void)hipGetLastError();
+        else {
+            BBS_HIP(hipMemcpyAsync(ws->host_state, ws->state, sizeof(State), hipMemcpyDeviceToHost, s));
+            BBS_HIP(hipStreamSynchronize(s));
+            if (ws->host_state->error & 4) {
+                ws->hist_dirty = true;
+                return fail(BBS_ERR_INTERNAL, "bbs_localize: persistent kernel barrier timed out");
+            }
+        }
+    }
+
     // search loop; every iteration before the last pops at least one node, so
     // the cap only guards against a broken queue
     const int64_t max_iters = (int64_t)1 << 26;
     int64_t iters = 0;
     for (;;) {
+        if (persistent_used) break;
         if (iters >= max_iters) {
             ws->hist_dirty = true;
             return fail(BBS_ERR_INTERNAL, "bbs_localize: search did not terminate");
@@ -1301,7 +1673,11 @@ extern "C" bbs_status bbs_localize(const bbs_map *map, bbs_workspace *ws, const 
         }
     }
     out->nodes_expanded = fs.nodes_expanded;
-    out->nodes_scored = init_nodes + fs.nodes_scored;
+    out->nodes_scored = init_nodes + fs.nodes_scored + fs.dive_scored;
+    out->prior_used = use_prior ? 1 : 0;
+    out->persistent_used = persistent_used ? 1 : 0;
+    out->seeded = fs.seeded;
+    out->seed_score = fs.seeded ? fs.seed_score : 0;
     out->flushes = fs.flushes;
     out->leaves_accepted = fs.leaves_accepted;
     out->initial_size = init_nodes;
@@ -1310,7 +1686,7 @@ extern "C" bbs_status bbs_localize(const bbs_map *map, bbs_workspace *ws, const 
     out->score_groups = n_init_groups + fs.groups_scored;
     if (prof) {
         // every iteration before the one that found the queue exhausted scored a batch
-        int64_t launches = init_chunks + fs.flushes;
+        int64_t launches = init_chunks + (persistent_used ? 0 : fs.flushes);
         double total = 0.0;
         for (int64_t i = 0; i < launches && 2 * i + 1 < ev_used; ++i) {
             float ms = 0.0f;

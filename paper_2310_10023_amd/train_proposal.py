@@ -1,0 +1,151 @@
+"""Train the learned proposal network on (scan, plain-BnB optimum) pairs.
+
+    python -m paper_2310_10023_amd.train_proposal --maps 40 --scans 50 --out weights.npz
+
+For every seeded training city (seeds 0.. maps-1; the benchmark city 1000 is
+held out) scans are ray-cast from random street poses, localized by the
+plain batched branch and bound on the GPU (bbs_serve), and the optimum leaf
+gives the labels: the yaw bin of its yaw and the 32 x 32 cell of its
+translation in the search box.  The bird's-eye polar image of the scan and the
+training steps run in libbbs (BF16 MFMA kernels, AdamW).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import multiprocessing as mp
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import synth  # noqa: E402
+
+import paper_2310_10023_amd as bbs  # noqa: E402
+from paper_2310_10023_amd import proposal  # noqa: E402
+
+CONV_CH = (1, 16, 32, 64, 64)
+
+
+def he_init(seed: int) -> np.ndarray:
+    """He-normal weights, zero biases, flattened in the library's parameter order."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for i in range(4):
+        cin, cout = CONV_CH[i], CONV_CH[i + 1]
+        parts.append(rng.normal(size=cout * 9 * cin) * math.sqrt(2.0 / (9 * cin)))
+        parts.append(np.zeros(cout))
+    parts.append(rng.normal(size=256 * 1024) * math.sqrt(2.0 / 1024))
+    parts.append(np.zeros(256))
+    parts.append(rng.normal(size=1088 * 256) * math.sqrt(2.0 / 256))
+    parts.append(np.zeros(1088))
+    flat = np.concatenate(parts).astype(np.float32)
+    assert flat.size == proposal.param_count()
+    return flat
+
+
+_SCENE = None
+
+
+def _init_worker(boxes, ground, extent, streets):
+    global _SCENE
+    _SCENE = synth.Scene(points=np.zeros((0, 3), np.float32), boxes=boxes, ground=ground, walls_box=None,
+                         extent=extent, streets=streets)
+
+
+def _scan_worker(args):
+    seed, k = args
+    sc = synth.scan_scene(_SCENE, seed, k, z=1.8, rp_deg=3.0, n_beams=64, n_az=2048, voxel=0.5)
+    return sc.points, sc.pose
+
+
+def make_dataset(map_seeds, scans_per_map, k=10000, workers=8, bnb_workers=4, log=print):
+    lo, hi = synth.search_range_city()
+    T = synth.threshold_95(k)
+    images, yaws, cells, meta = [], [], [], []
+    for ms in map_seeds:
+        t0 = time.time()
+        city = synth.city_scene(ms)
+        gmap = bbs.Map(city.points, 1.0, 6)
+        with mp.get_context("fork").Pool(workers, initializer=_init_worker,
+                                         initargs=(city.boxes, city.ground, city.extent, city.streets)) as pool:
+            scans = pool.map(_scan_worker, [(10_000 * ms + i, k) for i in range(scans_per_map)])
+        pts = [s[0] for s in scans]
+        res, _, _ = bbs.serve(gmap, pts, [(lo, hi)] * len(pts), [T] * len(pts), [0.0] * len(pts),
+                              workers=bnb_workers)
+        kept = 0
+        for (p, pose), r in zip(scans, res):
+            if not r["found"]:
+                continue
+            images.append(proposal.bev_image(p))
+            yaws.append(proposal.yaw_bin(r["pose"][5]))
+            cells.append(proposal.xy_cell(r["pose"][0], r["pose"][1], lo, hi))
+            meta.append((ms, float(np.hypot(*(np.array(r["pose"][:2]) - pose[:2])))))
+            kept += 1
+        gmap.close()
+        log(f"[data] map {ms}: {kept}/{len(pts)} localized in {time.time() - t0:.1f} s")
+    return np.stack(images), np.array(yaws, np.int32), np.array(cells, np.int32), meta
+
+
+def train(images, yaw, xy, epochs=40, batch=128, lr=2e-3, weight_decay=1e-4, seed=0, log=print):
+    rng = np.random.default_rng(seed)
+    net = proposal.Net(max_batch=batch, params=he_init(seed))
+    n = len(images)
+    steps = 0
+    for ep in range(epochs):
+        perm = rng.permutation(n)
+        # yaw augmentation: rotating the scan by whole azimuth bins shifts the image
+        # columns and the yaw label together (the label is the map-frame yaw of the
+        # sensor, the image is in the sensor frame: a sensor-frame rotation by s bins
+        # is a yaw change of -s bins)
+        tot, cnt = 0.0, 0
+        for b0 in range(0, n - batch + 1, batch):
+            idx = perm[b0:b0 + batch]
+            shift = rng.integers(0, 64, size=len(idx))
+            img = np.stack([np.roll(images[i], s, axis=1) for i, s in zip(idx, shift)])
+            y = (yaw[idx] - shift) % 64
+            cur_lr = lr * 0.5 * (1 + math.cos(math.pi * steps / max(1, epochs * (n // batch))))
+            loss, _ = net.train_step(img, y, xy[idx], lr=cur_lr, weight_decay=weight_decay)
+            tot += loss
+            cnt += 1
+            steps += 1
+        log(f"[train] epoch {ep}: loss {tot / max(cnt, 1):.3f}")
+    return net.get_params()
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--maps", type=int, default=40)
+    ap.add_argument("--scans", type=int, default=50)
+    ap.add_argument("--epochs", type=int, default=40)
+    ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--data", default=None, help="cache of the generated pairs (.npz)")
+    args = ap.parse_args()
+    import torch
+    torch.cuda.set_device(0)
+    t0 = time.time()
+    if args.data and os.path.exists(args.data):
+        d = np.load(args.data)
+        images, yaw, xy = d["images"], d["yaw"], d["xy"]
+    else:
+        images, yaw, xy, _ = make_dataset(range(args.maps), args.scans, workers=args.workers,
+                                          log=lambda m: print(m, flush=True))
+        if args.data:
+            np.savez_compressed(args.data, images=images, yaw=yaw, xy=xy)
+    print(f"[data] {len(images)} pairs in {time.time() - t0:.1f} s", flush=True)
+    params = train(images, yaw, xy, epochs=args.epochs, log=lambda m: print(m, flush=True))
+    np.savez_compressed(args.out, params=params,
+                        info=json.dumps({"pairs": int(len(images)), "maps": args.maps, "scans_per_map": args.scans,
+                                         "epochs": args.epochs}))
+    print(f"[train] wrote {args.out} after {time.time() - t0:.1f} s", flush=True)
+
+
+if __name__ == "__main__":
+    main()

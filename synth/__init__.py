@@ -249,23 +249,51 @@ def _ray_cast(scene: Scene, origin: np.ndarray, dirs: np.ndarray, max_range: flo
                 ok = (t > 1e-6) & (p[:, 2] >= 0) & (p[:, 2] <= z1) & (p[:, o] >= [x0, y0][o]) & \
                      (p[:, o] <= [x1, y1][o])
                 best = np.where(ok, np.minimum(best, t), best)
-    # boxes (slab test), only those that can be reached
+    # boxes (slab test), only those that can be reached; rays are bucketed by
+    # azimuth sector and tested against the boxes whose angular extent (seen
+    # from the origin, with a margin) overlaps the sector.  A ray can only hit
+    # a box whose footprint its horizontal direction crosses, so the culling
+    # changes no hit.
     if len(scene.boxes):
         b = scene.boxes
         cx = np.clip(origin[0], b[:, 0], b[:, 3])
         cy = np.clip(origin[1], b[:, 1], b[:, 4])
         near = np.hypot(cx - origin[0], cy - origin[1]) <= max_range
         b = b[near]
-        chunk = max(1, int(2e7 // max(1, len(b))))
-        for s in range(0, n, chunk):
-            iv = inv[s:s + chunk]
-            t1 = (b[None, :, 0:3] - origin[None, None, :]) * iv[:, None, :]
-            t2 = (b[None, :, 3:6] - origin[None, None, :]) * iv[:, None, :]
-            tmin = np.nanmax(np.minimum(t1, t2), axis=2)
-            tmax = np.nanmin(np.maximum(t1, t2), axis=2)
-            hit = (tmax >= tmin) & (tmax > 1e-6)
-            tt = np.where(hit, np.where(tmin > 1e-6, tmin, np.inf), np.inf)
-            best[s:s + chunk] = np.minimum(best[s:s + chunk], tt.min(axis=1) if tt.shape[1] else np.inf)
+        n_sec = 256
+        phi = np.arctan2(d[:, 1], d[:, 0])
+        sec = np.floor((phi + np.pi) / (2 * np.pi) * n_sec).astype(np.int64) % n_sec
+        corners = np.stack([np.stack([b[:, 0], b[:, 1]], 1), np.stack([b[:, 3], b[:, 1]], 1),
+                            np.stack([b[:, 0], b[:, 4]], 1), np.stack([b[:, 3], b[:, 4]], 1)], 1)
+        rel = corners - origin[None, None, :2]
+        mid = rel.mean(axis=1)
+        phc = np.arctan2(mid[:, 1], mid[:, 0])
+        ang = np.arctan2(rel[:, :, 1], rel[:, :, 0]) - phc[:, None]
+        ang = (ang + np.pi) % (2 * np.pi) - np.pi
+        inside = (origin[0] >= b[:, 0]) & (origin[0] <= b[:, 3]) & (origin[1] >= b[:, 1]) & (origin[1] <= b[:, 4])
+        half = np.where(inside, np.pi, np.abs(ang).max(axis=1)) + 4 * np.pi / n_sec
+        order = np.argsort(sec, kind="stable")
+        bounds = np.searchsorted(sec[order], np.arange(n_sec + 1))
+        for k in range(n_sec):
+            rays = order[bounds[k]:bounds[k + 1]]
+            if len(rays) == 0:
+                continue
+            psi = -np.pi + (k + 0.5) * 2 * np.pi / n_sec
+            dd = np.abs((psi - phc + np.pi) % (2 * np.pi) - np.pi)
+            cand = b[dd <= half]
+            if len(cand) == 0:
+                continue
+            chunk = max(1, int(2e7 // len(cand)))
+            for s0 in range(0, len(rays), chunk):
+                rr = rays[s0:s0 + chunk]
+                iv = inv[rr]
+                t1 = (cand[None, :, 0:3] - origin[None, None, :]) * iv[:, None, :]
+                t2 = (cand[None, :, 3:6] - origin[None, None, :]) * iv[:, None, :]
+                tmin = np.nanmax(np.minimum(t1, t2), axis=2)
+                tmax = np.nanmin(np.maximum(t1, t2), axis=2)
+                hit = (tmax >= tmin) & (tmax > 1e-6)
+                tt = np.where(hit, np.where(tmin > 1e-6, tmin, np.inf), np.inf)
+                best[rr] = np.minimum(best[rr], tt.min(axis=1))
     best[best > max_range] = np.inf
     return best
 

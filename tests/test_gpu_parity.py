@@ -195,6 +195,32 @@ def test_localize_device_scan_and_determinism(room):
     compare(b, want)
 
 
+@pytest.mark.parametrize("batch", [64, 10000])
+def test_localize_persistent_equals_oracle(room, batch):
+    """The persistent cooperative kernel runs the same schedule."""
+    say("localize persistent", batch)
+    scene, g, o = room
+    lo, hi = synth.search_range_room()
+    T = synth.threshold_95(2000)
+    for seed in (0, 3):
+        sc = synth.scan_scene(scene, seed, 2000, z=1.5, z_jitter=0.25, rp_deg=2.0)
+        want = oracle.Search(o, sc.points, lo, hi).localize(T, batch=batch, threads=8)
+        got = bbs.localize(g, sc.points, lo, hi, T, batch_size=batch, persistent=True)
+        compare(got, want)
+        assert got["persistent_used"] == 1
+
+
+@pytest.mark.parametrize("items", [1, 300, 20000])
+def test_localize_score_tiling_does_not_change_results(room, items):
+    say("score_items", items)
+    scene, g, o = room
+    lo, hi = synth.search_range_room()
+    sc = synth.scan_scene(scene, 8, 2500, z=1.5, z_jitter=0.25, rp_deg=2.0)
+    T = synth.threshold_95(2500)
+    want = oracle.Search(o, sc.points, lo, hi).localize(T, batch=3000, threads=8)
+    compare(bbs.localize(g, sc.points, lo, hi, T, batch_size=3000, score_items=items), want)
+
+
 def test_localize_errors(room):
     say("error paths")
     scene, g, _ = room
@@ -215,6 +241,48 @@ def test_localize_errors(room):
     # the same workspace still works for a search that fits
     r = bbs.localize(g, sc.points, lo, hi, 501, workspace=ws)
     assert r["found"] == 0 and r["nodes_expanded"] == 0
+
+
+@pytest.mark.parametrize("translation_only", [False, True])
+@pytest.mark.parametrize("dives", [0, 3])
+def test_localize_with_prior_equals_oracle(room, translation_only, dives):
+    """Prior-ordered initial set and seed dives: same schedule as the oracle."""
+    say("localize prior", translation_only, dives)
+    scene, g, o = room
+    sc = synth.scan_scene(scene, 21, 1200, z=1.5, z_jitter=0.25, rp_deg=2.0)
+    lo, hi = synth.search_range_room()
+    if translation_only:
+        lo = lo.copy()
+        hi = hi.copy()
+        lo[:2], hi[:2] = sc.pose[:2] - 2.0, sc.pose[:2] + 2.0
+    T = synth.threshold_95(1200)
+    prior = np.random.default_rng(3).normal(size=1088).astype(np.float32) * 2
+    want = oracle.Search(o, sc.points, lo, hi, translation_only=translation_only).localize(
+        T, batch=500, threads=8, prior=prior, n_seed_dives=dives)
+    got = bbs.localize(g, sc.points, lo, hi, T, batch_size=500, translation_only=translation_only, prior=prior,
+                       n_seed_dives=dives)
+    compare(got, want)
+    assert got["prior_used"] == want["prior_used"] == 1
+    assert (got["seeded"], got["seed_score"]) == (want["seeded"], want["seed_score"])
+
+
+def test_serve_matches_single_queries(room):
+    """Concurrent workers on separate streams give the oracle's results."""
+    say("serve")
+    scene, g, o = room
+    lo, hi = synth.search_range_room()
+    scans, want = [], []
+    for seed in range(6):
+        sc = synth.scan_scene(scene, 40 + seed, 1500 + 97 * seed, z=1.5, z_jitter=0.25, rp_deg=2.0)
+        scans.append(sc.points)
+        want.append(oracle.Search(o, sc.points, lo, hi).localize(synth.threshold_95(len(sc.points)), batch=2000,
+                                                                  threads=8))
+    arrivals = np.cumsum(np.random.default_rng(0).exponential(0.002, size=6))
+    res, t0, t1 = bbs.serve(g, scans, [(lo, hi)] * 6, [synth.threshold_95(len(s)) for s in scans], arrivals,
+                            workers=3, batch_size=2000)
+    for got, w in zip(res, want):
+        compare(got, w)
+    assert np.all(t1 >= t0) and np.all(t0 >= arrivals - 1e-6)
 
 
 # ------------------------------------------------------------------ full-size city (sampled parity)
@@ -250,5 +318,8 @@ def test_city_localize_equals_oracle(city):
     T = synth.threshold_95(10000)
     got = bbs.localize(g, sc.points, lo, hi, T, batch_size=10000)
     say("gpu", {k: got[k] for k in RESULT_KEYS}, got["phase_ms"])
+    pers = bbs.localize(g, sc.points, lo, hi, T, batch_size=10000, persistent=True)
+    say("gpu persistent", pers["phase_ms"], pers["persistent_used"])
     want = oracle.Search(o, sc.points, lo, hi).localize(T, batch=10000, threads=16)
     compare(got, want)
+    compare(pers, want)

@@ -199,3 +199,45 @@ def test_room_success_criterion(seed):
     R_true = synth.rotation_zyx(*sc.pose[3:])
     err_r = math.acos(max(-1.0, min(1.0, (np.trace(R_est.T @ R_true) - 1) / 2)))
     assert err_t < 2.0 and err_r < 0.05, (err_t, err_r)
+
+
+# ------------------------------------------------------------------ learned prior (ordering and seed dives)
+
+@pytest.mark.parametrize("dives", [0, 1, 4])
+@pytest.mark.parametrize("seed", [0, 2])
+def test_prior_keeps_translation_only_result_exact(seed, dives):
+    """Ordering ties by a prior and seeding the incumbent by greedy dives leave
+    the translation-only optimum unchanged (pruning stays strict)."""
+    s = tiny_case(seed, rp_deg=2.0, z_w=0.5)
+    T = int(0.6 * s.k)
+    bf = s.bruteforce(T, threads=8)
+    prior = np.random.default_rng(seed).normal(size=1088).astype(np.float32) * 3
+    r = s.localize(T, batch=64, threads=8, prior=prior, n_seed_dives=dives)
+    assert r["prior_used"] == 1
+    assert (r["found"], r["score"], r["leaf"]) == (bf["found"], bf["score"], bf["leaf"])
+    if r["seeded"]:
+        assert r["seed_score"] <= r["score"]
+
+
+def test_flat_prior_changes_nothing_and_nan_prior_is_ignored():
+    s = tiny_case(1, translation_only=False, rp_deg=2.0)
+    T = int(0.7 * s.k)
+    plain = s.localize(T, batch=100, threads=8)
+    flat = s.localize(T, batch=100, threads=8, prior=np.zeros(1088, np.float32))
+    nan = np.zeros(1088, np.float32)
+    nan[5] = np.nan
+    ign = s.localize(T, batch=100, threads=8, prior=nan, n_seed_dives=4)
+    assert flat["prior_used"] == 1 and ign["prior_used"] == 0 and ign["seeded"] == 0
+    for key in ("found", "score", "leaf", "nodes_expanded", "nodes_scored", "flushes"):
+        assert flat[key] == plain[key] and ign[key] == plain[key], key
+
+
+def test_seed_dive_counts_and_incumbent():
+    s = tiny_case(3, translation_only=True, rp_deg=2.0, z_w=0.5)
+    T = int(0.5 * s.k)
+    prior = np.random.default_rng(5).normal(size=1088).astype(np.float32)
+    a = s.localize(T, batch=64, threads=8, prior=prior, n_seed_dives=0)
+    b = s.localize(T, batch=64, threads=8, prior=prior, n_seed_dives=2)
+    assert b["seeded"] == 1 and T <= b["seed_score"] <= b["score"] == a["score"]
+    # a dive expands one node per level and scores all of that node's children
+    assert b["nodes_expanded"] >= 3 and b["nodes_scored"] > b["initial_size"]
