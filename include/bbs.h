@@ -70,7 +70,10 @@ typedef struct {
                                  (falls back to per-iteration launches if it cannot launch) */
     int32_t score_items;      /* scoring work items per batch (groups x point splits); sets the
                                  points each wave handles; 0 = default (2048) */
-    int64_t reserved[2];
+    int32_t graph;            /* 1: capture 8 search iterations in a hipGraph once per search
+                                 and replay it (ignored with persistent or profile) */
+    int32_t reserved1;
+    int64_t reserved[1];
 } bbs_options;
 
 typedef struct {
@@ -240,6 +243,28 @@ bbs_status bbs_net_train_step(bbs_net *net, const uint8_t *images, int32_t image
  * bin floor(64 |(x, y)| / d_max) clamped to 63, azimuth bin
  * floor(64 atan2(y, x) / 2 pi) mod 64, min(255, count) per cell. */
 bbs_status bbs_bev_image(const float *scan_xyz, int64_t k, int32_t scan_on_device, uint8_t *image);
+
+/* One measured configuration of bbs_autotune. */
+typedef struct {
+    int32_t batch_size;
+    int32_t score_items;
+    double ms;                /* wall time of the sample queries, summed */
+} bbs_tune_entry;
+
+/*
+ * Pick the node-batch size b and the scoring tile size (points per wave, via
+ * score_items) that localize the sample queries fastest: each candidate pair
+ * runs every query once after one warm-up query, on one workspace.
+ *   batch_sizes, n_b       candidate b values (each in [1, 2^24])
+ *   score_items, n_items   candidate score_items values (each in [1, 2^20])
+ *   base                   other options (its batch_size and score_items are replaced)
+ *   best                   fastest pair (caller-allocated)
+ *   all                    NULL or n_b * n_items entries, b outer
+ * Note: b changes the search schedule (node counts) but not its rules.
+ */
+bbs_status bbs_autotune(const bbs_map *map, const bbs_query *queries, int64_t n, const int32_t *batch_sizes,
+                        int32_t n_b, const int32_t *score_items, int32_t n_items, const bbs_options *base,
+                        bbs_tune_entry *best, bbs_tune_entry *all);
 
 #ifdef __cplusplus
 }

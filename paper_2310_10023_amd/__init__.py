@@ -25,7 +25,7 @@ EXPORTED_SYMBOLS = (
     "bbs_default_options", "bbs_abi_version", "bbs_last_error", "bbs_build_map", "bbs_free_map", "bbs_map_info",
     "bbs_map_dump_level", "bbs_map_contains", "bbs_workspace_create", "bbs_workspace_free", "bbs_localize",
     "bbs_score_nodes", "bbs_serve", "bbs_net_param_count", "bbs_net_create", "bbs_net_free", "bbs_net_set_params",
-    "bbs_net_get_params", "bbs_net_forward", "bbs_net_train_step", "bbs_bev_image",
+    "bbs_net_get_params", "bbs_net_forward", "bbs_net_train_step", "bbs_bev_image", "bbs_autotune",
 )
 
 STATUS = {0: "OK", -1: "INVALID_ARG", -2: "OOM", -3: "DEVICE", -4: "QUEUE_OVERFLOW", -5: "INTERNAL"}
@@ -48,7 +48,8 @@ class SearchRange(C.Structure):
 class Options(C.Structure):
     _fields_ = [("batch_size", C.c_int32), ("translation_only", C.c_int32), ("profile", C.c_int32),
                 ("n_seed_dives", C.c_int32), ("stream", C.c_void_p), ("prior", C.c_void_p),
-                ("persistent", C.c_int32), ("score_items", C.c_int32), ("reserved", C.c_int64 * 2)]
+                ("persistent", C.c_int32), ("score_items", C.c_int32), ("graph", C.c_int32),
+                ("reserved1", C.c_int32), ("reserved", C.c_int64 * 1)]
 
 
 class Result(C.Structure):
@@ -68,6 +69,10 @@ class Result(C.Structure):
                 "score_groups": self.score_groups,
                 "phase_ms": list(self.phase_ms), "prior_used": self.prior_used, "seeded": self.seeded,
                 "seed_score": self.seed_score, "persistent_used": self.persistent_used}
+
+
+class TuneEntry(C.Structure):
+    _fields_ = [("batch_size", C.c_int32), ("score_items", C.c_int32), ("ms", C.c_double)]
 
 
 class Query(C.Structure):
@@ -112,6 +117,9 @@ def lib():
         L.bbs_score_nodes.restype = C.c_int
         L.bbs_serve.argtypes = [P, C.POINTER(Query), I64, I32, C.POINTER(Options), C.POINTER(Result), P, P]
         L.bbs_serve.restype = C.c_int
+        L.bbs_autotune.argtypes = [P, C.POINTER(Query), I64, P, I32, P, I32, C.POINTER(Options),
+                                   C.POINTER(TuneEntry), P]
+        L.bbs_autotune.restype = C.c_int
         _lib = L
     return _lib
 
@@ -243,7 +251,7 @@ class Workspace:
 def localize(bmap: Map, scan, rmin, rmax, score_threshold: int, *, batch_size: int = 10000,
              translation_only: bool = False, profile: bool = False, workspace: Workspace | None = None,
              stream=None, prior=None, n_seed_dives: int = 0, persistent: bool = False,
-             score_items: int = 0) -> dict:
+             score_items: int = 0, graph: bool = False) -> dict:
     """Global localization of one scan (Alg. 2 on the GPU).  Returns the result
     fields as a dict (found, score, leaf, pose, node counters, timings).
     prior: optional 1088 logits of the proposal network."""
@@ -256,6 +264,7 @@ def localize(bmap: Map, scan, rmin, rmax, score_threshold: int, *, batch_size: i
     opt.n_seed_dives = int(n_seed_dives)
     opt.persistent = int(persistent)
     opt.score_items = int(score_items)
+    opt.graph = int(graph)
     pr = None
     if prior is not None:
         pr = np.ascontiguousarray(prior, dtype=np.float32).reshape(1088)
@@ -282,11 +291,7 @@ def score_nodes(bmap: Map, scan, rmin, rmax, nodes, translation_only: bool = Fal
     return out
 
 
-def serve(bmap: Map, scans, ranges, thresholds, arrivals, *, workers: int = 4, batch_size: int = 10000,
-          translation_only: bool = False) -> tuple[list, "np.ndarray", "np.ndarray"]:
-    """Serve a stream of queries (sorted by arrival time, seconds from the
-    start) with `workers` concurrent searches.  Returns (results, start_s,
-    end_s)."""
+def _queries(scans, ranges, thresholds, arrivals):
     n = len(scans)
     qs = (Query * max(n, 1))()
     keep = []
@@ -299,6 +304,40 @@ def serve(bmap: Map, scans, ranges, thresholds, arrivals, *, workers: int = 4, b
         qs[i].score_threshold = int(thresholds[i])
         qs[i].range = _range(*ranges[i])
         qs[i].arrival_s = float(arrivals[i])
+    return qs, keep
+
+
+def autotune(bmap: Map, scans, rmin, rmax, thresholds, batch_sizes, score_items, *, persistent: bool = False,
+             prior=None, n_seed_dives: int = 0):
+    """Fastest (batch_size, score_items) on the sample scans; returns
+    (best dict, list of all measured entries)."""
+    qs, keep = _queries(scans, [(rmin, rmax)] * len(scans), thresholds, [0.0] * len(scans))
+    bs = np.ascontiguousarray(batch_sizes, np.int32)
+    it = np.ascontiguousarray(score_items, np.int32)
+    opt = Options()
+    lib().bbs_default_options(C.byref(opt))
+    opt.persistent = int(persistent)
+    pr = None
+    if prior is not None:
+        pr = np.ascontiguousarray(prior, np.float32).reshape(1088)
+        opt.prior = pr.ctypes.data
+        opt.n_seed_dives = int(n_seed_dives)
+    best = TuneEntry()
+    allv = (TuneEntry * (len(bs) * len(it)))()
+    _check(lib().bbs_autotune(bmap.handle, qs, len(scans), bs.ctypes.data, len(bs), it.ctypes.data, len(it),
+                              C.byref(opt), C.byref(best), allv))
+    del keep, pr
+    conv = lambda e: {"batch_size": e.batch_size, "score_items": e.score_items, "ms": e.ms}
+    return conv(best), [conv(e) for e in allv]
+
+
+def serve(bmap: Map, scans, ranges, thresholds, arrivals, *, workers: int = 4, batch_size: int = 10000,
+          translation_only: bool = False) -> tuple[list, "np.ndarray", "np.ndarray"]:
+    """Serve a stream of queries (sorted by arrival time, seconds from the
+    start) with `workers` concurrent searches.  Returns (results, start_s,
+    end_s)."""
+    n = len(scans)
+    qs, keep = _queries(scans, ranges, thresholds, arrivals)
     opt = Options()
     lib().bbs_default_options(C.byref(opt))
     opt.batch_size = int(batch_size)

@@ -1632,12 +1632,50 @@ extern "C" bbs_status bbs_localize(const bbs_map *map, bbs_workspace *ws, const 
         }
     }
 
+    // graph path: the kItersPerSync iterations are captured once and replayed
+    bool graph_used = false;
+    if (o.graph && !prof && !persistent_used && !init_done) {
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        hipError_t ge = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+        if (ge == hipSuccess) {
+            for (int it = 0; it < kItersPerSync; ++it) {
+                launch_score(S, map, ws, ws->state, 0, score_grid, true);
+                serial(1);
+            }
+            ge = hipStreamEndCapture(s, &graph);
+        }
+        if (ge == hipSuccess) ge = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (ge == hipSuccess) {
+            graph_used = true;
+            for (int64_t rounds = 0;; ++rounds) {
+                if (rounds * kItersPerSync >= ((int64_t)1 << 26)) {
+                    ge = hipErrorUnknown;
+                    break;
+                }
+                ge = hipGraphLaunch(exec, s);
+                if (ge == hipSuccess) ge = hipMemcpyAsync(ws->host_state, ws->state, sizeof(State), hipMemcpyDeviceToHost, s);
+                if (ge == hipSuccess) ge = hipStreamSynchronize(s);
+                if (ge != hipSuccess || ws->host_state->done || ws->host_state->error) break;
+            }
+        }
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (ge != hipSuccess) {
+            if (graph_used) {
+                ws->hist_dirty = true;
+                return hip_fail(ge, "bbs_localize: graph replay");
+            }
+            (void)hipGetLastError();   // capture not available on this stream: plain launches
+        }
+    }
+
     // search loop; every iteration before the last pops at least one node, so
     // the cap only guards against a broken queue
     const int64_t max_iters = (int64_t)1 << 26;
     int64_t iters = 0;
     for (;;) {
-        if (persistent_used) break;
+        if (persistent_used || graph_used) break;
         if (iters >= max_iters) {
             ws->hist_dirty = true;
             return fail(BBS_ERR_INTERNAL, "bbs_localize: search did not terminate");

@@ -94,3 +94,45 @@ extern "C" bbs_status bbs_serve(const bbs_map *map, const bbs_query *queries, in
     }
     return BBS_OK;
 }
+
+extern "C" bbs_status bbs_autotune(const bbs_map *map, const bbs_query *queries, int64_t n, const int32_t *batch_sizes,
+                                   int32_t n_b, const int32_t *score_items, int32_t n_items, const bbs_options *base,
+                                   bbs_tune_entry *best, bbs_tune_entry *all)
+{
+    using bbs::fail;
+    if (!map || !queries || n < 1 || !batch_sizes || n_b < 1 || !score_items || n_items < 1 || !best)
+        return fail(BBS_ERR_INVALID_ARG, "bbs_autotune: bad arguments");
+    for (int i = 0; i < n_b; ++i)
+        if (batch_sizes[i] < 1 || batch_sizes[i] > (1 << 24))
+            return fail(BBS_ERR_INVALID_ARG, "bbs_autotune: batch size out of range");
+    for (int i = 0; i < n_items; ++i)
+        if (score_items[i] < 1 || score_items[i] > (1 << 20))
+            return fail(BBS_ERR_INVALID_ARG, "bbs_autotune: score_items out of range");
+    bbs_options o;
+    bbs_default_options(&o);
+    if (base) o = *base;
+    o.profile = 0;
+    bbs_workspace *ws = nullptr;
+    bbs_status st = bbs_workspace_create(0, &ws);
+    if (st) return st;
+    bbs_result r;
+    best->ms = -1.0;
+    for (int ib = 0; ib < n_b && st == BBS_OK; ++ib)
+        for (int ii = 0; ii < n_items && st == BBS_OK; ++ii) {
+            o.batch_size = batch_sizes[ib];
+            o.score_items = score_items[ii];
+            const bbs_query &w = queries[0];
+            st = bbs_localize(map, ws, w.scan_xyz, w.k, w.scan_on_device, &w.range, w.score_threshold, &o, &r);
+            const auto t0 = std::chrono::steady_clock::now();
+            for (int64_t q = 0; q < n && st == BBS_OK; ++q) {
+                const bbs_query &Q = queries[q];
+                st = bbs_localize(map, ws, Q.scan_xyz, Q.k, Q.scan_on_device, &Q.range, Q.score_threshold, &o, &r);
+            }
+            const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+            if (st) break;
+            if (all) all[ib * n_items + ii] = bbs_tune_entry{o.batch_size, o.score_items, ms};
+            if (best->ms < 0.0 || ms < best->ms) *best = bbs_tune_entry{o.batch_size, o.score_items, ms};
+        }
+    bbs_workspace_free(ws);
+    return st;
+}

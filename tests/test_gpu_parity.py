@@ -210,6 +210,28 @@ def test_localize_persistent_equals_oracle(room, batch):
         assert got["persistent_used"] == 1
 
 
+def test_localize_graph_equals_oracle(room):
+    """Graph-captured iterations, replayed several times per search."""
+    say("localize graph")
+    scene, g, o = room
+    lo, hi = synth.search_range_room()
+    T = synth.threshold_95(2000)
+    for seed in (1, 2):
+        sc = synth.scan_scene(scene, seed, 2000, z=1.5, z_jitter=0.25, rp_deg=2.0)
+        want = oracle.Search(o, sc.points, lo, hi).localize(T, batch=64, threads=8)
+        compare(bbs.localize(g, sc.points, lo, hi, T, batch_size=64, graph=True), want)
+
+
+def test_autotune_returns_a_measured_pair(room):
+    say("autotune")
+    scene, g, _ = room
+    lo, hi = synth.search_range_room()
+    scans = [synth.scan_scene(scene, 60 + i, 2000, z=1.5, rp_deg=2.0).points for i in range(2)]
+    best, allv = bbs.autotune(g, scans, lo, hi, [synth.threshold_95(2000)] * 2, [1000, 10000], [512, 4096])
+    assert len(allv) == 4 and all(e["ms"] > 0 for e in allv)
+    assert best["ms"] == min(e["ms"] for e in allv)
+
+
 @pytest.mark.parametrize("items", [1, 300, 20000])
 def test_localize_score_tiling_does_not_change_results(room, items):
     say("score_items", items)
