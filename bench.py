@@ -86,7 +86,7 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 plain device copies of MIB MiB (to scale HBM byte counters) and exit")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-order comparison")
-    ap.add_argument("--dives", type=int, default=4, help="seed dives of the learned-order search")
+    ap.add_argument("--beam", type=int, default=8, help="seed beam width of the learned-order search")
     ap.add_argument("--stream", action="store_true",
                     help="run the 256-query stream workload instead (throughput, p50/p99 latency)")
     ap.add_argument("--stream-queries", type=int, default=256)
@@ -193,6 +193,10 @@ def main():
             "nodes_scored_total": nodes,
             "found": f"{found}/{len(seeds)}",
             "map_build_ms": map_ms,
+            "score_kernel_ms_mean": kern_ms / len(seeds),
+            "serial_push_ms_mean": sum(r["serial_ms"][0] for r in results) / len(seeds),
+            "serial_gather_ms_mean": sum(r["serial_ms"][1] for r in results) / len(seeds),
+            "iterations_mean": launches / len(seeds),
         },
         "roofline": {
             "bound": "hbm",
@@ -225,7 +229,7 @@ def main():
 
 def learned_order(gmap, dev, seeds, plain, lo, hi, T, args):
     """The same queries with the proposal network's prior (prior-ordered initial
-    set and seed dives).  Timed per query: BEV image + network forward +
+    set and seed beam).  Timed per query: BEV image + network forward +
     localization."""
     import numpy as np
     import torch
@@ -243,7 +247,7 @@ def learned_order(gmap, dev, seeds, plain, lo, hi, T, args):
         logits = net.forward(proposal.bev_image(dev[s])[None])[0]
         prior_ms += (time.perf_counter() - ta) * 1e3
         out.append(bbs.localize(gmap, dev[s], lo, hi, T, batch_size=args.batch, workspace=ws, prior=logits,
-                                n_seed_dives=args.dives))
+                                seed_beam=args.beam))
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     same = sum(a["found"] == b["found"] and a["leaf"] == b["leaf"] and a["score"] == b["score"]
@@ -259,7 +263,7 @@ def learned_order(gmap, dev, seeds, plain, lo, hi, T, args):
         "same_result_as_plain": f"{same}/{len(seeds)}",
         "score_at_least_plain": f"{ge}/{len(seeds)}",
         "seeded": sum(r["seeded"] for r in out),
-        "dives": args.dives,
+        "beam": args.beam,
     }
     return {"summary": summary, "results": out}
 

@@ -57,15 +57,22 @@ typedef struct {
                                  (Table I "Trans." branching); 0: roto-translational */
     int32_t profile;          /* 1: time every scoring launch with HIP events (fills
                                  score_kernel_ms / score_launches of the result) */
-    int32_t n_seed_dives;     /* with a prior: greedy dives from the first n initial nodes
-                                 (prior order) that reach the threshold seed the incumbent */
+    int32_t seed_beam;        /* with a prior: width W of the seed beam.  Starting from the W best
+                                 initial nodes reaching the threshold, every beam node is
+                                 branched, all children scored, and the W best children
+                                 reaching the threshold form the next beam, down to the
+                                 leaves; "best" is score desc, prior key desc, position asc.
+                                 The best beam leaf seeds the incumbent.  Clamped to 64 and
+                                 to 2048 / (most children of one node); 0: no beam */
     void *stream;             /* hipStream_t to run on; NULL = the library's own stream */
     const float *prior;       /* NULL, or 1088 host float logits of the proposal network (64
                                  yaw bins, then 32 x 32 translation cells of the search box,
-                                 x outer).  Initial nodes are scored and queued in descending
-                                 order of yaw-bin logit + cell logit (ties: enumeration
-                                 order), which orders ties of (score, level); a non-finite
-                                 logit disables the prior */
+                                 x outer).  The key of a node is the best yaw-bin logit over
+                                 the leaf yaws below it plus the best cell logit over the
+                                 leaf translations below it (summed in double).  Initial
+                                 nodes are scored and queued in descending key (ties:
+                                 enumeration order), which orders ties of (score, level); a
+                                 non-finite logit disables the prior */
     int32_t persistent;       /* 1: run the search loop as one cooperative persistent kernel
                                  (falls back to per-iteration launches if it cannot launch) */
     int32_t score_items;      /* scoring work items per batch (groups x point splits); sets the
@@ -93,9 +100,13 @@ typedef struct {
     int64_t score_groups;     /* scored groups of translational siblings sharing a rotation */
     double phase_ms[4];       /* set-up, initial set, search loop, total (host clock) */
     int32_t prior_used;       /* 1: the prior ordered the initial set */
-    int32_t seeded;           /* 1: a seed dive set the incumbent */
-    int32_t seed_score;       /* score of that dive leaf */
+    int32_t seeded;           /* 1: the seed beam set the incumbent */
+    int32_t seed_score;       /* score of that beam leaf */
     int32_t persistent_used;  /* 1: the search loop ran as one persistent kernel */
+    int32_t seed_beam_used;   /* beam width after clamping (0: no beam ran) */
+    int32_t reserved_r;
+    double serial_ms[2];      /* device time of the serial queue work: push, then gather
+                                 (summed over iterations, from the 100 MHz device clock) */
 } bbs_result;
 
 /* Fill *opt with the defaults (b = 10000, roto-translational, no profiling,

@@ -94,6 +94,8 @@ def lib():
         L.orc_all_leaf_scores.restype = I64
         L.orc_children.argtypes = [C.POINTER(Grid), P, P, I64]
         L.orc_children.restype = I64
+        L.orc_prior_key.argtypes = [C.POINTER(Grid), P, P]
+        L.orc_prior_key.restype = C.c_double
         L.orc_sizeof_grid.restype = I64
         L.orc_sizeof_result.restype = I64
         assert L.orc_sizeof_grid() == C.sizeof(Grid), "oracle Grid layout mismatch"
@@ -213,18 +215,26 @@ class Search:
         n = lib().orc_children(C.byref(self.grid), node.ctypes.data, out.ctypes.data, cap)
         return out[:n]
 
+    def prior_key(self, prior, node) -> float:
+        """Ordering key of a node (level, x, y, z, roll, pitch, yaw) under a
+        1088-logit prior: best yaw-bin logit plus best cell logit over the
+        leaves below the node."""
+        pr = np.ascontiguousarray(prior, dtype=np.float32).reshape(1088)
+        nd = _i32(node).reshape(7)
+        return float(lib().orc_prior_key(C.byref(self.grid), pr.ctypes.data, nd.ctypes.data))
+
     def localize(self, threshold: int, batch: int = 10000, threads: int = 1, max_scored: int = 0,
-                 trace_cap: int = 0, prior=None, n_seed_dives: int = 0) -> dict:
+                 trace_cap: int = 0, prior=None, seed_beam: int = 0) -> dict:
         """Alg. 2.  prior: optional 1088 float logits (64 yaw bins, then 32 x 32
-        translation cells) that order the initial set; n_seed_dives greedy
-        dives from the best-prior initial nodes seed the incumbent."""
+        translation cells) that order the initial set; a seed beam of width
+        `seed_beam` ranked by (score, prior key) may seed the incumbent."""
         res = Result()
         tr = np.zeros(max(trace_cap, 1), dtype=np.int64)
         pr = None if prior is None else np.ascontiguousarray(prior, dtype=np.float32).reshape(1088)
         rc = lib().orc_localize(self.map.handle, self.scan.ctypes.data, self.k, C.byref(self.grid), int(threshold),
                                 int(batch), int(threads), int(max_scored), C.byref(res),
                                 tr.ctypes.data if trace_cap else None, int(trace_cap),
-                                pr.ctypes.data if pr is not None else None, int(n_seed_dives))
+                                pr.ctypes.data if pr is not None else None, int(seed_beam))
         if rc != 0:
             raise OracleError(f"orc_localize failed ({rc})")
         d = res.as_dict()

@@ -457,7 +457,7 @@ typedef struct {
     int64_t initial_size, initial_kept;
     int64_t bound_checks, bound_violations;  /* children scored / children above parent */
     double violation_excess_sum;             /* sum of (child - parent) / parent */
-    int32_t prior_used, seeded;              /* the prior ordered the initial set; a dive set the incumbent */
+    int32_t prior_used, seeded;              /* the prior ordered the initial set; the seed beam set the incumbent */
     int32_t seed_score, pad;
 } orc_result;
 
@@ -514,33 +514,83 @@ static void decode_pose(const orc_grid *g, const int32_t leaf[6], double pose[6]
 /* ------------------------------------------------------------------ learned prior (not in the paper)
  *
  * The prior is 1088 logits: 64 over yaw bins, then 32 x 32 over translation
- * cells of the search box (x outer).  A top-level node's key is the logit of
- * the yaw bin holding its yaw cell centre plus the logit of the translation
- * cell holding its translation-cell centre.  It orders ties in the queue and
- * picks where greedy seed dives start; it never changes a score.
+ * cells of the search box (x outer).  A yaw bin is [2 pi b / 64, 2 pi (b+1) / 64)
+ * after reducing the angle mod 2 pi; a translation cell splits each of the
+ * x and y search intervals into 32 equal parts.
+ *
+ * The key of a node is the best yaw-bin logit over the leaf yaws below it
+ * plus the best cell logit over the leaf translations below it.  The leaves
+ * below a level-l node are the cells [c 2^l, (c+1) 2^l - 1] of each
+ * translation axis (within the search range) and the yaw cells
+ * [c P, (c+1) P - 1] with P the product of the yaw divisions a of levels
+ * 1..l (within the level-0 cell count).  A key only orders nodes; it never
+ * changes a score.
  */
 #define ORC_YAW_BINS 64
 #define ORC_XY_CELLS 32
 
-static double prior_key(const orc_grid *g, const float *prior, const orc_node *c)
+static int yaw_bin_of(double th)
 {
     const double two_pi = 2.0 * 3.14159265358979323846;
-    double th = cell_angle(g, 2, c->ang[2], c->level);
     double tm = th - two_pi * floor(th / two_pi);
     int yb = (int)floor(tm / (two_pi / ORC_YAW_BINS));
     if (yb < 0) yb = 0;
     if (yb >= ORC_YAW_BINS) yb = ORC_YAW_BINS - 1;
-    int cell[2];
-    for (int ax = 0; ax < 2; ++ax) {
-        double rl = ldexp((double)g->r, c->level);
-        double x = rl * ((double)c->t[ax] + 0.5);
-        double lo = g->tmin[ax], hi = g->tmax[ax];
-        int ci = hi > lo ? (int)floor(ORC_XY_CELLS * (x - lo) / (hi - lo)) : 0;
-        if (ci < 0) ci = 0;
-        if (ci >= ORC_XY_CELLS) ci = ORC_XY_CELLS - 1;
-        cell[ax] = ci;
+    return yb;
+}
+
+static int xy_cell_of(const orc_grid *g, int ax, int32_t i)
+{
+    double x = (double)g->r * (double)i;
+    double lo = g->tmin[ax], hi = g->tmax[ax];
+    int ci = hi > lo ? (int)floor(ORC_XY_CELLS * (x - lo) / (hi - lo)) : 0;
+    if (ci < 0) ci = 0;
+    if (ci >= ORC_XY_CELLS) ci = ORC_XY_CELLS - 1;
+    return ci;
+}
+
+static double prior_key(const orc_grid *g, const float *prior, const orc_node *c)
+{
+    const int l = c->level;
+    int64_t span = 1;
+    for (int m = 1; m <= l; ++m) span *= g->a[2][m];
+    int64_t y0 = (int64_t)c->ang[2] * span, y1 = ((int64_t)c->ang[2] + 1) * span - 1;
+    if (y1 > g->n[2][0] - 1) y1 = g->n[2][0] - 1;
+    double ky = -INFINITY;
+    for (int64_t i = y0; i <= y1; ++i) {
+        double v = prior[yaw_bin_of(cell_angle(g, 2, (int32_t)i, 0))];
+        if (v > ky) ky = v;
     }
-    return (double)prior[yb] + (double)prior[ORC_YAW_BINS + cell[0] * ORC_XY_CELLS + cell[1]];
+    uint32_t cells[2] = {0, 0};       /* bit c: some leaf below the node lies in cell c of this axis */
+    for (int ax = 0; ax < 2; ++ax) {
+        int64_t i0 = (int64_t)c->t[ax] << l, i1 = (((int64_t)c->t[ax] + 1) << l) - 1;
+        if (i0 < g->lo[ax]) i0 = g->lo[ax];
+        if (i1 > g->hi[ax]) i1 = g->hi[ax];
+        for (int64_t i = i0; i <= i1; ++i) cells[ax] |= 1u << xy_cell_of(g, ax, (int32_t)i);
+    }
+    double kxy = -INFINITY;
+    for (int cx = 0; cx < ORC_XY_CELLS; ++cx) {
+        if (!((cells[0] >> cx) & 1u)) continue;
+        for (int cy = 0; cy < ORC_XY_CELLS; ++cy) {
+            if (!((cells[1] >> cy) & 1u)) continue;
+            double v = prior[ORC_YAW_BINS + cx * ORC_XY_CELLS + cy];
+            if (v > kxy) kxy = v;
+        }
+    }
+    return ky + kxy;
+}
+
+/* node = (level, x, y, z, i_roll, i_pitch, i_yaw) */
+double orc_prior_key(const orc_grid *g, const float *prior, const int32_t *node)
+{
+    orc_node c;
+    memset(&c, 0, sizeof(c));
+    c.level = node[0];
+    for (int ax = 0; ax < 3; ++ax) {
+        c.t[ax] = node[1 + ax];
+        c.ang[ax] = node[4 + ax];
+    }
+    return prior_key(g, prior, &c);
 }
 
 typedef struct {
@@ -555,27 +605,84 @@ static int cmp_keyed(const void *a, const void *b)
     return (x->index > y->index) - (x->index < y->index);
 }
 
-/* Greedy dive from c to a leaf: score every child, go to the highest-scoring
- * one (ties: the first in branching order). */
-static int dive(const orc_map *m, const float *scan, int64_t k, const orc_grid *g, orc_node c, int32_t threads,
-                orc_result *res, orc_node *leaf)
+/* beam candidates rank by score (desc), prior key (desc), position (asc) */
+typedef struct {
+    orc_node n;
+    double key;
+    int64_t pos;
+} beam_item;
+
+static int cmp_beam(const void *a, const void *b)
 {
-    node_vec ch = {0};
+    const beam_item *x = (const beam_item *)a, *y = (const beam_item *)b;
+    if (x->n.score != y->n.score) return x->n.score > y->n.score ? -1 : 1;
+    if (x->key != y->key) return x->key > y->key ? -1 : 1;
+    return (x->pos > y->pos) - (x->pos < y->pos);
+}
+
+/*
+ * Seed beam: starting from the `width` best initial nodes (scored, at or
+ * above the threshold; position = place in the prior order), branch every
+ * beam node, score all children, and keep the `width` best children at or
+ * above the threshold (position = place among the children, beam order then
+ * branching order), down to the leaves.  The best beam leaf (highest score,
+ * then lexicographically smallest) is returned.  Every branched beam node
+ * counts as expanded and every child as scored.
+ */
+static int seed_beam(const orc_map *m, const float *scan, int64_t k, const orc_grid *g, const float *prior,
+                     int32_t threshold, int32_t width, const node_vec *init, int32_t threads, orc_result *res,
+                     orc_node *leaf, int *found)
+{
+    *found = 0;
     int rc = ORC_OK;
-    while (c.level > 0) {
+    node_vec ch = {0};
+    beam_item *items = (beam_item *)malloc((size_t)(init->n ? init->n : 1) * sizeof(beam_item));
+    if (!items) return ORC_ERR_OOM;
+    int64_t n_items = 0, cap_items = init->n ? init->n : 1;
+    for (int64_t i = 0; i < init->n; ++i) {
+        if (init->v[i].score < threshold) continue;
+        items[n_items].n = init->v[i];
+        items[n_items].key = prior_key(g, prior, &init->v[i]);
+        items[n_items].pos = i;
+        ++n_items;
+    }
+    qsort(items, (size_t)n_items, sizeof(beam_item), cmp_beam);
+    if (n_items > width) n_items = width;
+    while (n_items > 0 && items[0].n.level > 0) {
         ch.n = 0;
-        if ((rc = branch(g, &c, &ch))) break;
-        res->nodes_expanded++;
-        if (ch.n == 0) { rc = 1; break; }
+        for (int64_t i = 0; i < n_items; ++i) {
+            if ((rc = branch(g, &items[i].n, &ch))) goto out;
+            res->nodes_expanded++;
+        }
         score_vec(m, scan, k, g, &ch, threads);
         res->nodes_scored += ch.n;
-        int64_t bi = 0;
-        for (int64_t i = 1; i < ch.n; ++i)
-            if (ch.v[i].score > ch.v[bi].score) bi = i;
-        c = ch.v[bi];
+        if (ch.n > cap_items) {
+            beam_item *t = (beam_item *)realloc(items, (size_t)ch.n * sizeof(beam_item));
+            if (!t) { rc = ORC_ERR_OOM; goto out; }
+            items = t;
+            cap_items = ch.n;
+        }
+        n_items = 0;
+        for (int64_t i = 0; i < ch.n; ++i) {
+            if (ch.v[i].score < threshold) continue;
+            items[n_items].n = ch.v[i];
+            items[n_items].key = prior_key(g, prior, &ch.v[i]);
+            items[n_items].pos = i;
+            ++n_items;
+        }
+        qsort(items, (size_t)n_items, sizeof(beam_item), cmp_beam);
+        if (n_items > width) n_items = width;
     }
+    for (int64_t i = 0; i < n_items; ++i) {
+        const orc_node *c = &items[i].n;
+        if (!*found || c->score > leaf->score || (c->score == leaf->score && leaf_lex_less(c, leaf))) {
+            *leaf = *c;
+            *found = 1;
+        }
+    }
+out:
+    free(items);
     free(ch.v);
-    *leaf = c;
     return rc;
 }
 
@@ -595,12 +702,15 @@ static int dive(const orc_map *m, const float *scan, int64_t k, const orc_grid *
  * for its order: the top-level cells are enumerated as the valid children of
  * virtual cells one level above, visited in lexicographic order, each
  * expanded like a branch (rotations outer, translations inner).
- * max_pops bounds the number of queue pops (0 = no bound); a bounded run
+ * max_scored bounds the number of scored nodes (0 = no bound); a bounded run
  * returns found = -1 when it stops early.
+ * With a finite prior (not in the paper) the initial set is scored and queued
+ * in descending prior key (ties in enumeration order), and a seed beam of
+ * width beam_width may set the incumbent before the loop starts.
  */
 int orc_localize(const orc_map *m, const float *scan, int64_t k, const orc_grid *g, int32_t threshold,
                  int64_t batch, int32_t threads, int64_t max_scored, orc_result *res,
-                 int64_t *trace_flush, int64_t trace_cap, const float *prior, int32_t n_dives)
+                 int64_t *trace_flush, int64_t trace_cap, const float *prior, int32_t beam_width)
 {
     memset(res, 0, sizeof(*res));
     if (!m || !scan || k < 1 || batch < 1 || g->levels != m->levels) return ORC_ERR_ARG;
@@ -665,15 +775,13 @@ int orc_localize(const orc_map *m, const float *scan, int64_t k, const orc_grid 
         if ((rc = heap_push(&heap, &pending.v[i]))) goto done;
         res->initial_kept++;
     }
-    if (res->prior_used && n_dives > 0) {
-        int started = 0;
-        for (int64_t i = 0; i < pending.n && started < n_dives; ++i) {
-            if (pending.v[i].score < threshold) continue;
-            ++started;
-            orc_node leaf;
-            if (dive(m, scan, k, g, pending.v[i], threads, res, &leaf) != ORC_OK) continue;
-            if (leaf.score < best) continue;
-            if (!have_match || leaf.score > best || leaf_lex_less(&leaf, &match)) match = leaf;
+    if (res->prior_used && beam_width > 0) {
+        orc_node leaf;
+        int got = 0;
+        if ((rc = seed_beam(m, scan, k, g, prior, threshold, beam_width, &pending, threads, res, &leaf, &got)))
+            goto done;
+        if (got && leaf.score >= best) {
+            match = leaf;
             have_match = 1;
             best = leaf.score;
             res->seeded = 1;

@@ -47,7 +47,7 @@ class SearchRange(C.Structure):
 
 class Options(C.Structure):
     _fields_ = [("batch_size", C.c_int32), ("translation_only", C.c_int32), ("profile", C.c_int32),
-                ("n_seed_dives", C.c_int32), ("stream", C.c_void_p), ("prior", C.c_void_p),
+                ("seed_beam", C.c_int32), ("stream", C.c_void_p), ("prior", C.c_void_p),
                 ("persistent", C.c_int32), ("score_items", C.c_int32), ("graph", C.c_int32),
                 ("reserved1", C.c_int32), ("reserved", C.c_int64 * 1)]
 
@@ -58,7 +58,8 @@ class Result(C.Structure):
                 ("leaves_accepted", C.c_int64), ("initial_size", C.c_int64), ("initial_kept", C.c_int64),
                 ("score_kernel_ms", C.c_double), ("score_launches", C.c_int64), ("score_pairs", C.c_int64),
                 ("score_groups", C.c_int64), ("phase_ms", C.c_double * 4), ("prior_used", C.c_int32),
-                ("seeded", C.c_int32), ("seed_score", C.c_int32), ("persistent_used", C.c_int32)]
+                ("seeded", C.c_int32), ("seed_score", C.c_int32), ("persistent_used", C.c_int32),
+                ("seed_beam_used", C.c_int32), ("reserved_r", C.c_int32), ("serial_ms", C.c_double * 2)]
 
     def as_dict(self):
         return {"found": self.found, "score": self.score, "leaf": list(self.leaf), "pose": list(self.pose),
@@ -68,7 +69,8 @@ class Result(C.Structure):
                 "score_launches": self.score_launches, "score_pairs": self.score_pairs,
                 "score_groups": self.score_groups,
                 "phase_ms": list(self.phase_ms), "prior_used": self.prior_used, "seeded": self.seeded,
-                "seed_score": self.seed_score, "persistent_used": self.persistent_used}
+                "seed_score": self.seed_score, "persistent_used": self.persistent_used,
+                "seed_beam_used": self.seed_beam_used, "serial_ms": list(self.serial_ms)}
 
 
 class TuneEntry(C.Structure):
@@ -250,7 +252,7 @@ class Workspace:
 
 def localize(bmap: Map, scan, rmin, rmax, score_threshold: int, *, batch_size: int = 10000,
              translation_only: bool = False, profile: bool = False, workspace: Workspace | None = None,
-             stream=None, prior=None, n_seed_dives: int = 0, persistent: bool = False,
+             stream=None, prior=None, seed_beam: int = 0, persistent: bool = False,
              score_items: int = 0, graph: bool = False) -> dict:
     """Global localization of one scan (Alg. 2 on the GPU).  Returns the result
     fields as a dict (found, score, leaf, pose, node counters, timings).
@@ -261,7 +263,7 @@ def localize(bmap: Map, scan, rmin, rmax, score_threshold: int, *, batch_size: i
     opt.batch_size = int(batch_size)
     opt.translation_only = int(translation_only)
     opt.profile = int(profile)
-    opt.n_seed_dives = int(n_seed_dives)
+    opt.seed_beam = int(seed_beam)
     opt.persistent = int(persistent)
     opt.score_items = int(score_items)
     opt.graph = int(graph)
@@ -308,7 +310,7 @@ def _queries(scans, ranges, thresholds, arrivals):
 
 
 def autotune(bmap: Map, scans, rmin, rmax, thresholds, batch_sizes, score_items, *, persistent: bool = False,
-             prior=None, n_seed_dives: int = 0):
+             prior=None, seed_beam: int = 0):
     """Fastest (batch_size, score_items) on the sample scans; returns
     (best dict, list of all measured entries)."""
     qs, keep = _queries(scans, [(rmin, rmax)] * len(scans), thresholds, [0.0] * len(scans))
@@ -321,7 +323,7 @@ def autotune(bmap: Map, scans, rmin, rmax, thresholds, batch_sizes, score_items,
     if prior is not None:
         pr = np.ascontiguousarray(prior, np.float32).reshape(1088)
         opt.prior = pr.ctypes.data
-        opt.n_seed_dives = int(n_seed_dives)
+        opt.seed_beam = int(seed_beam)
     best = TuneEntry()
     allv = (TuneEntry * (len(bs) * len(it)))()
     _check(lib().bbs_autotune(bmap.handle, qs, len(scans), bs.ctypes.data, len(bs), it.ctypes.data, len(it),

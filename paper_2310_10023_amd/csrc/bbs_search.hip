@@ -56,15 +56,94 @@ struct State {
     int64_t pushed;           // nodes pushed since the start
     int64_t nodes_expanded, nodes_scored, flushes, leaves_accepted;
     int64_t groups_scored;
-    int64_t dive_scored;      // children scored by seed dives
+    int64_t dive_scored;      // children scored by the seed beam
     int32_t seeded, seed_score;
+    int64_t t_push, t_gather; // device real-time ticks (100 MHz) spent in the serial push and gather
 };
 
-// One greedy seed dive: its current node and the groups of its children.
-struct Dive {
-    uint4 node;
-    int32_t active, g0, ng, score;
+// ---- learned prior: seed beam (not in the paper)
+constexpr int kMaxBeam = 64;
+constexpr int kBeamThreads = 1024;
+constexpr int kBeamSlots = 2048;                 // children (8 slots per group) one beam step may score
+
+struct BeamNode {
+    uint4 node;               // packed node (translation, angle indices, level)
+    int32_t score, pad;
+    double key;               // prior key
 };
+
+struct BeamBuf {
+    int32_t count, pad[3];
+    BeamNode nodes[kMaxBeam];
+};
+
+// What the prior key needs of the search grid: the leaf yaw grid, the yaw
+// divisions per level, the leaf translation grid and the search box.
+struct PriorConst {
+    double wmin_yaw, dprime_yaw0;     // leaf yaw cell i has angle wmin + dprime (i + 1/2)
+    double r;                         // leaf translation cell i sits at r i
+    double tmin[2], tmax[2];          // x and y search intervals
+    int32_t n_yaw0;
+    int32_t lo[2], hi[2];             // leaf translation cells in the search range
+    int32_t a_yaw[kMaxLevels];        // yaw divisions from level l to l - 1
+};
+
+// Yaw bin of an angle: 64 bins over [0, 2 pi) after reduction mod 2 pi.
+__host__ __device__ inline int prior_yaw_bin(double th)
+{
+    const double two_pi = 2.0 * 3.14159265358979323846;
+    const double tm = th - two_pi * floor(th / two_pi);
+    int yb = (int)floor(tm / (two_pi / 64));
+    return yb < 0 ? 0 : (yb > 63 ? 63 : yb);
+}
+
+// Cell (of 32) of leaf translation index i along x (ax = 0) or y (ax = 1).
+__host__ __device__ inline int prior_xy_cell(const PriorConst &P, int ax, int32_t i)
+{
+    const double x = P.r * (double)i;
+    const double lo = P.tmin[ax], hi = P.tmax[ax];
+    const int c = hi > lo ? (int)floor(32 * (x - lo) / (hi - lo)) : 0;
+    return c < 0 ? 0 : (c > 31 ? 31 : c);
+}
+
+// Prior key of a level-l node: the best yaw-bin logit over the leaf yaws
+// below it plus the best cell logit over the leaf translations below it.
+// The leaf yaw cells below yaw cell c are [c P, (c+1) P - 1] (P: product of
+// the yaw divisions of levels 1..l, clipped to the leaf cell count); the
+// leaf translation cells below t are [t 2^l, (t+1) 2^l - 1] (clipped to the
+// search range).
+__host__ __device__ inline double prior_key(const PriorConst &P, const float *prior, int level, int32_t tx, int32_t ty,
+                                            int32_t yaw)
+{
+    int64_t span = 1;
+    for (int m = 1; m <= level; ++m) span *= P.a_yaw[m];
+    const int64_t y0 = (int64_t)yaw * span;
+    int64_t y1 = ((int64_t)yaw + 1) * span - 1;
+    if (y1 > P.n_yaw0 - 1) y1 = P.n_yaw0 - 1;
+    double ky = -__builtin_huge_val();
+    for (int64_t i = y0; i <= y1; ++i) {
+        const double v = prior[prior_yaw_bin(P.wmin_yaw + P.dprime_yaw0 * ((double)i + 0.5))];
+        if (v > ky) ky = v;
+    }
+    uint32_t cells[2] = {0u, 0u};
+    const int32_t t[2] = {tx, ty};
+    for (int ax = 0; ax < 2; ++ax) {
+        int64_t i0 = (int64_t)t[ax] * ((int64_t)1 << level), i1 = ((int64_t)t[ax] + 1) * ((int64_t)1 << level) - 1;
+        if (i0 < P.lo[ax]) i0 = P.lo[ax];
+        if (i1 > P.hi[ax]) i1 = P.hi[ax];
+        for (int64_t i = i0; i <= i1; ++i) cells[ax] |= 1u << prior_xy_cell(P, ax, (int32_t)i);
+    }
+    double kxy = -__builtin_huge_val();
+    for (int cx = 0; cx < 32; ++cx) {
+        if (!((cells[0] >> cx) & 1u)) continue;
+        for (int cy = 0; cy < 32; ++cy) {
+            if (!((cells[1] >> cy) & 1u)) continue;
+            const double v = prior[64 + cx * 32 + cy];
+            if (v > kxy) kxy = v;
+        }
+    }
+    return ky + kxy;
+}
 
 inline int grid_for(int64_t n, int threads, int cap)
 {
@@ -273,15 +352,18 @@ __device__ inline int bucket_of(int score, int level, const SearchConst &C)
 
 // One tile of 32 groups (256 node slots) of a scored batch: the queue bucket
 // of every kept child (score >= best), its rank among the tile's earlier
-// children of the same bucket, and the tile's count per bucket.
+// children of the same bucket, and the tile's count per bucket.  Run by a
+// whole workgroup of NT >= 256 threads; thread s < 256 handles slot s.
+template <int NT>
 __device__ void tile_pass(int t, const uint4 *groups, int32_t *scores, State *st, const SearchConst &C,
                           int n_groups, int32_t *q_arr, int32_t *rank_arr, int32_t *hist, int *sq, int *sm)
 {
     const int s = threadIdx.x;
+    const bool slot = s < kTileSlots;
     const int g = t * kTileGroups + s / 8, j = s & 7;
     const int best = ld_agent(&st->best);
     int q = -1;
-    if (g < n_groups) {
+    if (slot && g < n_groups) {
         const uint4 G = groups[g];
         const uint32_t mask = (G.w >> 8) & 0xFF;
         if ((mask >> j) & 1u) {
@@ -289,7 +371,7 @@ __device__ void tile_pass(int t, const uint4 *groups, int32_t *scores, State *st
             if (sc >= best) q = bucket_of(sc, (int)(G.w & 0xFF), C);
         }
     }
-    sq[s] = q;
+    if (slot) sq[s] = q;
     __syncthreads();
     int rank = 0, cnt = 0;
     if (q >= 0) {
@@ -299,13 +381,15 @@ __device__ void tile_pass(int t, const uint4 *groups, int32_t *scores, State *st
             rank += e & (i < s);
         }
     }
-    q_arr[(int64_t)t * kTileSlots + s] = q;
-    rank_arr[(int64_t)t * kTileSlots + s] = rank;
+    if (slot) {
+        q_arr[(int64_t)t * kTileSlots + s] = q;
+        rank_arr[(int64_t)t * kTileSlots + s] = rank;
+    }
     if (q >= 0 && rank == 0) hist[(int64_t)t * C.q_count + q] = cnt;
-    const int qmn = block_min_int<kTileSlots>(q >= 0 ? q : INT_MAX, sm);
-    const int qmx = -block_min_int<kTileSlots>(q >= 0 ? -q : INT_MAX, sm);
+    const int qmn = block_min_int<NT>(q >= 0 ? q : INT_MAX, sm);
+    const int qmx = -block_min_int<NT>(q >= 0 ? -q : INT_MAX, sm);
     int tot;
-    (void)block_scan_incl<kTileSlots>(q >= 0 ? 1 : 0, sm, &tot);
+    (void)block_scan_incl<NT>(q >= 0 ? 1 : 0, sm, &tot);
     if (threadIdx.x == 0 && tot > 0) {
         atomicMin(&st->q_min, qmn);
         atomicMax(&st->q_max, qmx);
@@ -313,10 +397,11 @@ __device__ void tile_pass(int t, const uint4 *groups, int32_t *scores, State *st
     }
 }
 
+template <int NT>
 struct ScoreSmem {
-    int red[kScoreThreads / 64][8];
+    int red[NT / 64][8];
     int sq[kTileSlots];
-    int sm[kScoreThreads / 64];
+    int sm[NT / 64];
     int s_last;
 };
 
@@ -330,8 +415,9 @@ struct ScoreArgs {
     int32_t *q_arr, *rank_arr, *hist;
 };
 
-template <bool POW2>
-__device__ void score_items(State *st, const ScoreArgs &A, const MapView &map, const SearchConst &C, ScoreSmem &sh)
+template <bool POW2, int NT>
+__device__ void score_items(State *st, const ScoreArgs &A, const MapView &map, const SearchConst &C,
+                            ScoreSmem<NT> &sh)
 {
     const uint4 *__restrict__ groups = A.groups;
     const float *__restrict__ X = A.X;
@@ -345,7 +431,7 @@ __device__ void score_items(State *st, const ScoreArgs &A, const MapView &map, c
     if (n_groups <= 0) return;
     const int K = C.K;
     int S = (C.score_items + n_groups - 1) / n_groups;
-    S = max(1, min(S, (K + 1023) / 1024));
+    S = max(1, min(S, (K + NT * kUnroll - 1) / (NT * kUnroll)));
     const int64_t n_items = (int64_t)n_groups * S;
     for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
         const int g = (int)(item / S), sp = (int)(item % S);
@@ -363,13 +449,13 @@ __device__ void score_items(State *st, const ScoreArgs &A, const MapView &map, c
         const uint32_t ey = (uint32_t)(lv.bmax[1] - lv.bmin[1]);
         const uint32_t ez = (uint32_t)(lv.bmax[2] - lv.bmin[2]);
         int c0 = 0, c1 = 0, c2 = 0, c3 = 0, c4 = 0, c5 = 0, c6 = 0, c7 = 0;
-        for (int kb = k_begin + (int)threadIdx.x; kb < k_end; kb += kScoreThreads * kUnroll) {
+        for (int kb = k_begin + (int)threadIdx.x; kb < k_end; kb += NT * kUnroll) {
             uint32_t h[kUnroll], klo[kUnroll], khi[kUnroll];
             int i0[kUnroll];
             int state[kUnroll];   // 0: miss, 1: probing, 2: found
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
-                const int k = kb + u * kScoreThreads;
+                const int k = kb + u * NT;
                 state[u] = 0;
                 h[u] = 0;
                 klo[u] = khi[u] = 0;
@@ -444,7 +530,7 @@ __device__ void score_items(State *st, const ScoreArgs &A, const MapView &map, c
         __syncthreads();
         if (threadIdx.x < 8) {
             int sum = 0;
-            for (int wv = 0; wv < kScoreThreads / 64; ++wv) sum += red[wv][threadIdx.x];
+            for (int wv = 0; wv < NT / 64; ++wv) sum += red[wv][threadIdx.x];
             atomicAdd(&scores[8 * (int64_t)g + threadIdx.x], sum);
             __threadfence();
         }
@@ -460,7 +546,7 @@ __device__ void score_items(State *st, const ScoreArgs &A, const MapView &map, c
         __syncthreads();
         if (sh.s_last) {
             __threadfence();
-            tile_pass(t, groups, scores, st, C, n_groups, A.q_arr, A.rank_arr, A.hist, sh.sq, sh.sm);
+            tile_pass<NT>(t, groups, scores, st, C, n_groups, A.q_arr, A.rank_arr, A.hist, sh.sq, sh.sm);
             if (threadIdx.x == 0) __hip_atomic_store(&tile_done[t], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         __syncthreads();
@@ -470,8 +556,8 @@ __device__ void score_items(State *st, const ScoreArgs &A, const MapView &map, c
 template <bool POW2>
 __global__ __launch_bounds__(kScoreThreads) void k_score(State *st, ScoreArgs A, MapView map, SearchConst C)
 {
-    __shared__ ScoreSmem sh;
-    score_items<POW2>(st, A, map, C, sh);
+    __shared__ ScoreSmem<kScoreThreads> sh;
+    score_items<POW2, kScoreThreads>(st, A, map, C, sh);
 }
 
 // ------------------------------------------------------------------ initial set
@@ -857,12 +943,19 @@ __device__ void serial_body(State *st, const SearchConst &C, Bucket *bk, uint4 *
                             const PushBufs &B, int do_gather, SerialSmem<NT> &sh)
 {
     if (ld_agent(&st->done)) return;
+    const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
     if (ld_agent(&st->batch)) push_finish<NT>(st, C, bk, groups, B, sh.sm);
     __syncthreads();
+    const uint64_t t1 = __builtin_amdgcn_s_memrealtime();
+    if (threadIdx.x == 0) st->t_push += (int64_t)(t1 - t0);
     if (ld_agent(&st->done)) return;
     if (threadIdx.x == 0) st->batch = 0;
     __syncthreads();
-    if (do_gather) gather<NT>(st, bk, B.chunk_next, B.arena, C, groups, scores, sh.sm, sh.smatch, sh.s_last);
+    if (do_gather) {
+        gather<NT>(st, bk, B.chunk_next, B.arena, C, groups, scores, sh.sm, sh.smatch, sh.s_last);
+        __syncthreads();
+        if (threadIdx.x == 0) st->t_gather += (int64_t)(__builtin_amdgcn_s_memrealtime() - t1);
+    }
 }
 
 __global__ __launch_bounds__(kSerialThreads) void k_serial(State *st, SearchConst C, Bucket *bk, uint4 *groups,
@@ -874,7 +967,7 @@ __global__ __launch_bounds__(kSerialThreads) void k_serial(State *st, SearchCons
 
 // ------------------------------------------------------------------ persistent search loop
 
-constexpr int kPersistThreads = 256;
+constexpr int kPersistThreads = 1024;   // as wide as k_serial: the serial phase runs in workgroup 0
 constexpr unsigned kSpinLimit = 1u << 26;
 
 // Grid-wide barrier for a cooperative launch: arrive on bar[0], wait for the
@@ -917,19 +1010,19 @@ __global__ __launch_bounds__(kPersistThreads) void k_persistent(State *st, Score
                                                                 Bucket *bk, uint4 *groups, int32_t *scores,
                                                                 PushBufs B, unsigned *bar, int32_t max_iters)
 {
-    __shared__ ScoreSmem ssh;
+    __shared__ ScoreSmem<kPersistThreads> ssh;
     __shared__ SerialSmem<kPersistThreads> sh;
     __shared__ int s_ok;
     for (int it = 0; it < max_iters; ++it) {
         if (ld_agent(&st->done)) break;
-        score_items<POW2>(st, A, map, C, ssh);
+        score_items<POW2, kPersistThreads>(st, A, map, C, ssh);
         if (!grid_sync(bar, &st->error, &s_ok)) break;
         if (blockIdx.x == 0) serial_body<kPersistThreads>(st, C, bk, groups, scores, B, 1, sh);
         if (!grid_sync(bar, &st->error, &s_ok)) break;
     }
 }
 
-// ------------------------------------------------------------------ learned prior: batches and seed dives
+// ------------------------------------------------------------------ learned prior: batches and seed beam
 
 // A batch already written to `groups` (initial nodes in prior order): zero
 // its scores and reset the push bookkeeping.
@@ -945,28 +1038,30 @@ __global__ void k_begin_batch(State *st, int32_t *scores, int32_t n_groups)
     }
 }
 
-// Children of every live dive as groups (branching order), one after the
-// other; a dive whose node has no child stops.  `ds` is the batch header the
-// scoring kernel reads.
-__global__ void k_dive_expand(Dive *d, int M, SearchConst C, uint4 *groups, int32_t *scores, State *st, State *ds)
+// Seed beam step 1: the children of every beam node as groups, beam order
+// then branching order (one wave; the beam holds at most 64 nodes).  `ds` is
+// the batch header the scoring kernel reads.
+__global__ __launch_bounds__(64) void k_beam_expand(BeamBuf *bb, SearchConst C, uint4 *groups, int32_t *scores,
+                                                    State *st, State *ds)
 {
-    if (blockIdx.x != 0 || threadIdx.x != 0) return;
-    int g = 0;
-    for (int i = 0; i < M; ++i) {
-        if (!d[i].active) continue;
-        int32_t t[3], ang[3], level;
-        node_unpack(d[i].node, t, ang, level);
-        if (level == 0) continue;
-        int rc[3], nn, ng;
-        uint32_t tmask;
-        child_counts(C, t, ang, level, rc, tmask, nn, ng);
-        st->nodes_expanded += 1;
-        d[i].g0 = g;
-        d[i].ng = ng;
-        if (ng == 0) {
-            d[i].active = 0;
-            continue;
-        }
+    __shared__ int s_ng[kMaxBeam];
+    const int tid = threadIdx.x;
+    const int n = bb->count;
+    int32_t t[3] = {0, 0, 0}, ang[3] = {0, 0, 0}, level = 0;
+    int rc[3] = {0, 0, 0}, nn = 0, ng = 0;
+    uint32_t tmask = 0;
+    if (tid < n) {
+        node_unpack(bb->nodes[tid].node, t, ang, level);
+        if (level > 0) child_counts(C, t, ang, level, rc, tmask, nn, ng);
+    }
+    s_ng[tid] = ng;
+    __syncthreads();
+    int g = 0, total = 0;
+    for (int i = 0; i < n; ++i) {
+        if (i < tid) g += s_ng[i];
+        total += s_ng[i];
+    }
+    if (ng > 0) {
         for (int ja = 0; ja < rc[0]; ++ja)
             for (int jb = 0; jb < rc[1]; ++jb)
                 for (int jg = 0; jg < rc[2]; ++jg) {
@@ -978,58 +1073,108 @@ __global__ void k_dive_expand(Dive *d, int M, SearchConst C, uint4 *groups, int3
                                              (uint32_t)(level - 1) | (tmask << 8));
                 }
     }
-    ds->batch = 1;
-    ds->n_groups = g;
+    if (tid == 0) {
+        st->nodes_expanded += n;
+        ds->n_groups = total;
+        ds->batch = total > 0 ? 1 : 0;
+    }
 }
 
-// Each live dive moves to its highest-scoring child (ties: the first in
-// branching order).
-__global__ void k_dive_pick(Dive *d, int M, const uint4 *groups, const int32_t *scores, State *st)
+// Seed beam step 2: among the scored children at or above the threshold,
+// the `W` first in (score desc, prior key desc, position asc) order become
+// the next beam; position is the child's slot (group, member), i.e. beam
+// order then branching order.
+__global__ __launch_bounds__(kBeamThreads) void k_beam_pick(BeamBuf *bb, int W, const uint4 *groups,
+                                                            const int32_t *scores, const State *ds, State *st,
+                                                            PriorConst P, const float *prior, int32_t threshold)
 {
-    if (blockIdx.x != 0 || threadIdx.x != 0) return;
-    for (int i = 0; i < M; ++i) {
-        if (!d[i].active) continue;
-        int best = -1;
-        uint4 node = d[i].node;
-        for (int gi = d[i].g0; gi < d[i].g0 + d[i].ng; ++gi) {
-            const uint4 G = groups[gi];
-            const uint32_t mask = (G.w >> 8) & 0xFF;
-            for (int j = 0; j < 8; ++j) {
-                if (!((mask >> j) & 1u)) continue;
-                const int sc = scores[8 * gi + j];
-                st->dive_scored += 1;
-                if (sc > best) {
-                    best = sc;
-                    const int jx = (j >> 2) & 1, jy = (j >> 1) & 1, jz = j & 1;
-                    node = make_uint4(pack16(lo16s(G.x) + jx, hi16s(G.x) + jy), pack16(lo16s(G.y) + jz, hi16u(G.y)),
-                                      G.z, G.w & 0xFFu);
-                }
+    __shared__ int s_score[kBeamSlots];
+    __shared__ double s_key[kBeamSlots];
+    __shared__ int s_children, s_valid;
+    const int tid = threadIdx.x;
+    const int n_slots = 8 * min(ds->n_groups, kBeamSlots / 8);
+    if (tid == 0) {
+        s_children = 0;
+        s_valid = 0;
+    }
+    __syncthreads();
+    int children = 0, valid = 0;
+    for (int sl = tid; sl < n_slots; sl += kBeamThreads) {
+        const uint4 G = groups[sl >> 3];
+        const int j = sl & 7;
+        int sc = -1;
+        double key = 0.0;
+        if (((G.w >> 8) >> j) & 1u) {
+            ++children;
+            const int v = scores[sl];
+            if (v >= threshold) {
+                sc = v;
+                ++valid;
+                key = prior_key(P, prior, (int)(G.w & 0xFF), lo16s(G.x) + ((j >> 2) & 1), hi16s(G.x) + ((j >> 1) & 1),
+                                (int32_t)hi16u(G.z));
             }
         }
-        d[i].node = node;
-        d[i].score = best;
+        s_score[sl] = sc;
+        s_key[sl] = key;
+    }
+    atomicAdd(&s_children, children);
+    atomicAdd(&s_valid, valid);
+    __syncthreads();
+    for (int sl = tid; sl < n_slots; sl += kBeamThreads) {
+        const int sc = s_score[sl];
+        if (sc < 0) continue;
+        const double key = s_key[sl];
+        int rank = 0;
+        for (int u = 0; u < n_slots; ++u) {
+            const int su = s_score[u];
+            rank += su > sc || (su == sc && (s_key[u] > key || (s_key[u] == key && u < sl)));
+        }
+        if (rank < W) {
+            const uint4 G = groups[sl >> 3];
+            const int j = sl & 7;
+            const int jx = (j >> 2) & 1, jy = (j >> 1) & 1, jz = j & 1;
+            BeamNode b;
+            b.node = make_uint4(pack16(lo16s(G.x) + jx, hi16s(G.x) + jy), pack16(lo16s(G.y) + jz, hi16u(G.y)), G.z,
+                                G.w & 0xFFu);
+            b.score = sc;
+            b.pad = 0;
+            b.key = key;
+            bb->nodes[rank] = b;
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        bb->count = min(W, s_valid);
+        st->dive_scored += s_children;
     }
 }
 
-// The best dive leaf (highest score, then lexicographically smallest) seeds
+// The best beam leaf (highest score, then lexicographically smallest) seeds
 // the incumbent if it reaches the running best.
-__global__ void k_dive_seed(const Dive *d, int M, State *st)
+__global__ void k_beam_seed(const BeamBuf *bb, State *st)
 {
     if (blockIdx.x != 0 || threadIdx.x != 0) return;
-    for (int i = 0; i < M; ++i) {
-        if (!d[i].active) continue;
+    int have = 0, best = -1;
+    int32_t leaf[6] = {0, 0, 0, 0, 0, 0};
+    for (int i = 0; i < bb->count; ++i) {
         int32_t t[3], ang[3], level;
-        node_unpack(d[i].node, t, ang, level);
-        if (level != 0 || d[i].score < st->best) continue;
-        const int32_t leaf[6] = {t[0], t[1], t[2], ang[0], ang[1], ang[2]};
-        if (!st->have_match || d[i].score > st->best || leaf_less(leaf, st->match)) {
-            for (int k = 0; k < 6; ++k) st->match[k] = leaf[k];
+        node_unpack(bb->nodes[i].node, t, ang, level);
+        if (level != 0) continue;
+        const int32_t cand[6] = {t[0], t[1], t[2], ang[0], ang[1], ang[2]};
+        const int sc = bb->nodes[i].score;
+        if (!have || sc > best || (sc == best && leaf_less(cand, leaf))) {
+            for (int k = 0; k < 6; ++k) leaf[k] = cand[k];
+            best = sc;
+            have = 1;
         }
-        st->have_match = 1;
-        st->best = d[i].score;
-        st->seeded = 1;
-        st->seed_score = d[i].score;
     }
+    if (!have || best < st->best) return;
+    if (!st->have_match || best > st->best || leaf_less(leaf, st->match))
+        for (int k = 0; k < 6; ++k) st->match[k] = leaf[k];
+    st->have_match = 1;
+    st->best = best;
+    st->seeded = 1;
+    st->seed_score = best;
 }
 
 // ------------------------------------------------------------------ host side
@@ -1103,8 +1248,10 @@ struct bbs_workspace {
     int64_t state_n = 0;
     unsigned long long *maxsq = nullptr;
     int64_t maxsq_n = 0;
-    Dive *dives = nullptr;
-    int64_t dives_n = 0;
+    BeamBuf *beam = nullptr;
+    int64_t beam_n = 0;
+    float *prior = nullptr;
+    int64_t prior_n = 0;
     unsigned *bar = nullptr;
     int64_t bar_n = 0;
     State *dstate = nullptr;
@@ -1121,7 +1268,7 @@ void free_ws(bbs_workspace *w)
 {
     void *ptrs[] = {w->arena, w->chunk_next, w->buckets, w->hist, w->totals, w->pT, w->pf, w->pc0, w->groups, w->scores,
                     w->q_arr, w->rank_arr, w->tile_done, w->scan, w->scan_aos, w->scan_tmp, w->mkeys, w->mhist,
-                    w->trig, w->state, w->maxsq, w->dives, w->dstate, w->bar};
+                    w->trig, w->state, w->maxsq, w->beam, w->prior, w->dstate, w->bar};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (w->host_state) (void)hipHostFree(w->host_state);
@@ -1306,17 +1453,36 @@ int64_t max_children(const Grid &g)
     return mc;
 }
 
-// Initial nodes in descending prior key (yaw-bin logit + cell logit, summed in
-// double), ties in enumeration order, as one-node groups.
-std::vector<uint4> prior_order(const Grid &g, const bbs_search_range *range, const float *prior)
+PriorConst prior_const(const Grid &g, const bbs_search_range *range)
+{
+    PriorConst P;
+    std::memset(&P, 0, sizeof(P));
+    P.wmin_yaw = g.wmin[2];
+    P.dprime_yaw0 = g.dprime[2][0];
+    P.r = (double)g.r;
+    for (int ax = 0; ax < 2; ++ax) {
+        P.tmin[ax] = (double)range->min[ax];
+        P.tmax[ax] = (double)range->max[ax];
+        P.lo[ax] = g.lo[ax];
+        P.hi[ax] = g.hi[ax];
+    }
+    P.n_yaw0 = g.n[2][0];
+    for (int l = 0; l <= g.levels; ++l) P.a_yaw[l] = g.a[2][l];
+    return P;
+}
+
+// Initial nodes (enumeration order as in k_enum_initial) sorted by
+// descending prior key, ties in enumeration order, as one-node groups, with
+// their keys.
+struct KeyedGroup {
+    double key;
+    uint4 grp;
+};
+
+std::vector<KeyedGroup> prior_order(const Grid &g, const PriorConst &P, const float *prior)
 {
     const int L = g.levels;
-    const double two_pi = 2.0 * 3.14159265358979323846;
-    struct Item {
-        double key;
-        uint4 grp;
-    };
-    std::vector<Item> items;
+    std::vector<KeyedGroup> items;
     const int32_t P0[3] = {g.lo[0] >> (L + 1), g.lo[1] >> (L + 1), g.lo[2] >> (L + 1)};
     const int32_t P1[3] = {g.hi[0] >> (L + 1), g.hi[1] >> (L + 1), g.hi[2] >> (L + 1)};
     for (int32_t px = P0[0]; px <= P1[0]; ++px)
@@ -1324,37 +1490,21 @@ std::vector<uint4> prior_order(const Grid &g, const bbs_search_range *range, con
             for (int32_t pz = P0[2]; pz <= P1[2]; ++pz)
                 for (int32_t ia = 0; ia < g.n[0][L]; ++ia)
                     for (int32_t ib = 0; ib < g.n[1][L]; ++ib)
-                        for (int32_t ig = 0; ig < g.n[2][L]; ++ig) {
-                            const double th = cell_angle(g, 2, ig, L);
-                            const double tm = th - two_pi * std::floor(th / two_pi);
-                            int yb = (int)std::floor(tm / (two_pi / 64));
-                            yb = std::min(std::max(yb, 0), 63);
+                        for (int32_t ig = 0; ig < g.n[2][L]; ++ig)
                             for (int j = 0; j < 8; ++j) {
                                 const int jx = (j >> 2) & 1, jy = (j >> 1) & 1, jz = j & 1;
                                 const int32_t t[3] = {2 * px + jx, 2 * py + jy, 2 * pz + jz};
                                 bool ok = true;
                                 for (int a = 0; a < 3; ++a) ok = ok && t[a] >= (g.lo[a] >> L) && t[a] <= (g.hi[a] >> L);
                                 if (!ok) continue;
-                                int cell[2];
-                                for (int a = 0; a < 2; ++a) {
-                                    const double rl = std::ldexp((double)g.r, L);
-                                    const double x = rl * ((double)t[a] + 0.5);
-                                    const double lo = range->min[a], hi = range->max[a];
-                                    int c = hi > lo ? (int)std::floor(32 * (x - lo) / (hi - lo)) : 0;
-                                    cell[a] = std::min(std::max(c, 0), 31);
-                                }
-                                const double key = (double)prior[yb] + (double)prior[64 + cell[0] * 32 + cell[1]];
-                                const int bj = 4 * (t[0] & 1) + 2 * (t[1] & 1) + (t[2] & 1);
-                                const uint4 grp = make_uint4(pack16(t[0] - (t[0] & 1), t[1] - (t[1] & 1)),
-                                                             pack16(t[2] - (t[2] & 1), ia), pack16(ib, ig),
-                                                             (uint32_t)L | ((1u << bj) << 8));
-                                items.push_back(Item{key, grp});
+                                const double key = prior_key(P, prior, L, t[0], t[1], ig);
+                                const uint4 grp = make_uint4(pack16(2 * px, 2 * py), pack16(2 * pz, ia), pack16(ib, ig),
+                                                             (uint32_t)L | ((1u << j) << 8));
+                                items.push_back(KeyedGroup{key, grp});
                             }
-                        }
-    std::stable_sort(items.begin(), items.end(), [](const Item &a, const Item &b) { return a.key > b.key; });
-    std::vector<uint4> out(items.size());
-    for (size_t i = 0; i < items.size(); ++i) out[i] = items[i].grp;
-    return out;
+    std::stable_sort(items.begin(), items.end(),
+                     [](const KeyedGroup &a, const KeyedGroup &b) { return a.key > b.key; });
+    return items;
 }
 
 }  // namespace
@@ -1523,25 +1673,37 @@ extern "C" bbs_status bbs_localize(const bbs_map *map, bbs_workspace *ws, const 
     // prior (learned proposal): usable only if every logit is finite
     bool use_prior = o.prior != nullptr;
     for (int i = 0; use_prior && i < 1088; ++i) use_prior = std::isfinite(o.prior[i]);
-    // at most 64 dives, and never more children than the group buffer holds
-    const int n_dives = use_prior ? (int)std::max<int64_t>(0, std::min<int64_t>({(int64_t)o.n_seed_dives, 64,
-                                                                                 cap_groups / std::max<int64_t>(1, mc / 8)}))
-                                  : 0;
-    std::vector<uint4> ordered;
-    if (use_prior) ordered = prior_order(g, range, o.prior);
-    std::vector<uint4> cand;          // dive start nodes: first initial nodes (prior order) reaching the threshold
-    std::vector<int32_t> cand_score;
+    // beam width: at most 64, at most kBeamSlots children per step, and never
+    // more children than the group buffer holds
+    const int beam_w = use_prior ? (int)std::max<int64_t>(0, std::min<int64_t>({(int64_t)o.seed_beam, kMaxBeam,
+                                                                                kBeamSlots / mc,
+                                                                                cap_groups / std::max<int64_t>(1, mc / 8)}))
+                                 : 0;
+    const PriorConst PC = prior_const(g, range);
+    std::vector<KeyedGroup> ordered;
+    std::vector<uint4> ordered_groups;
+    if (use_prior) {
+        ordered = prior_order(g, PC, o.prior);
+        ordered_groups.resize(ordered.size());
+        for (size_t i = 0; i < ordered.size(); ++i) ordered_groups[i] = ordered[i].grp;
+    }
+    struct BeamCand {
+        int32_t score;
+        double key;
+        int64_t pos;
+    };
+    std::vector<BeamCand> cands;      // initial nodes reaching the threshold (pos: place in the prior order)
 
     // initial set, in chunks of the group buffer; the last chunk's serial
-    // kernel also gathers the first batch of the search (unless dives come first)
+    // kernel also gathers the first batch of the search (unless the beam comes first)
     int64_t init_chunks = 0;
     const int64_t n_groups_init = use_prior ? (int64_t)ordered.size() : n_init_groups;
     for (int64_t g0 = 0; g0 < n_groups_init; g0 += cap_groups) {
         const int32_t cnt = (int32_t)std::min<int64_t>(cap_groups, n_groups_init - g0);
         const bool last = g0 + cnt >= n_groups_init;
         if (use_prior) {
-            BBS_HIP(hipMemcpyAsync(ws->groups, ordered.data() + g0, (size_t)cnt * sizeof(uint4), hipMemcpyHostToDevice,
-                                   s));
+            BBS_HIP(hipMemcpyAsync(ws->groups, ordered_groups.data() + g0, (size_t)cnt * sizeof(uint4),
+                                   hipMemcpyHostToDevice, s));
             k_begin_batch<<<grid_for(8 * (int64_t)cnt, 256, 1024), 256, 0, s>>>(ws->state, ws->scores, cnt);
         } else {
             k_enum_initial<<<grid_for(cnt, 256, 4096), 256, 0, s>>>(ws->groups, ws->scores, g0, cnt, C, P0[0], P0[1],
@@ -1550,39 +1712,58 @@ extern "C" bbs_status bbs_localize(const bbs_map *map, bbs_workspace *ws, const 
         if (prof) BBS_HIP(record(ev_used++));
         launch_score(S, map, ws, ws->state, 0, score_grid, true);
         if (prof) BBS_HIP(record(ev_used++));
-        if (n_dives > 0 && (int)cand.size() < n_dives) {
+        if (beam_w > 0) {
             std::vector<int32_t> sc((size_t)cnt * 8);
             BBS_HIP(hipMemcpyAsync(sc.data(), ws->scores, sc.size() * 4, hipMemcpyDeviceToHost, s));
             BBS_HIP(hipStreamSynchronize(s));
-            for (int32_t i = 0; i < cnt && (int)cand.size() < n_dives; ++i) {
-                const uint4 G = ordered[(size_t)(g0 + i)];
-                const uint32_t mask = (G.w >> 8) & 0xFF;
-                const int j = __builtin_ctz(mask);
+            for (int32_t i = 0; i < cnt; ++i) {
+                const uint4 G = ordered_groups[(size_t)(g0 + i)];
+                const int j = __builtin_ctz((G.w >> 8) & 0xFF);
                 const int32_t v = sc[(size_t)i * 8 + j];
-                if (v < C.threshold) continue;
-                const int jx = (j >> 2) & 1, jy = (j >> 1) & 1, jz = j & 1;
-                cand.push_back(make_uint4(pack16(lo16s(G.x) + jx, hi16s(G.x) + jy), pack16(lo16s(G.y) + jz, hi16u(G.y)),
-                                          G.z, G.w & 0xFFu));
-                cand_score.push_back(v);
+                if (v >= C.threshold) cands.push_back(BeamCand{v, ordered[(size_t)(g0 + i)].key, g0 + i});
             }
         }
-        serial(last && cand.empty() ? 1 : 0);
+        serial(last && cands.empty() ? 1 : 0);
         ++init_chunks;
     }
-    if (!cand.empty()) {
-        const int M = (int)cand.size();
-        std::vector<Dive> d((size_t)M);
-        for (int i = 0; i < M; ++i) d[i] = Dive{cand[i], 1, 0, 0, cand_score[i]};
-        if (ensure(ws->dives, ws->dives_n, M) || ensure(ws->dstate, ws->dstate_n, 1)) return BBS_ERR_OOM;
-        BBS_HIP(hipMemcpyAsync(ws->dives, d.data(), (size_t)M * sizeof(Dive), hipMemcpyHostToDevice, s));
+    int beam_used = 0;
+    if (!cands.empty()) {
+        // initial beam: the beam_w best by (score desc, key desc, position asc)
+        const size_t W = std::min(cands.size(), (size_t)beam_w);
+        std::partial_sort(cands.begin(), cands.begin() + W, cands.end(), [](const BeamCand &a, const BeamCand &b) {
+            if (a.score != b.score) return a.score > b.score;
+            if (a.key != b.key) return a.key > b.key;
+            return a.pos < b.pos;
+        });
+        BeamBuf hb;
+        std::memset(&hb, 0, sizeof(hb));
+        hb.count = (int32_t)W;
+        for (size_t i = 0; i < W; ++i) {
+            const uint4 G = ordered_groups[(size_t)cands[i].pos];
+            const int j = __builtin_ctz((G.w >> 8) & 0xFF);
+            const int jx = (j >> 2) & 1, jy = (j >> 1) & 1, jz = j & 1;
+            hb.nodes[i].node = make_uint4(pack16(lo16s(G.x) + jx, hi16s(G.x) + jy), pack16(lo16s(G.y) + jz, hi16u(G.y)),
+                                          G.z, G.w & 0xFFu);
+            hb.nodes[i].score = cands[i].score;
+            hb.nodes[i].key = cands[i].key;
+        }
+        if (ensure(ws->beam, ws->beam_n, 1) || ensure(ws->dstate, ws->dstate_n, 1) ||
+            ensure(ws->prior, ws->prior_n, 1088))
+            return BBS_ERR_OOM;
+        BBS_HIP(hipMemcpyAsync(ws->beam, &hb, sizeof(hb), hipMemcpyHostToDevice, s));
+        BBS_HIP(hipMemcpyAsync(ws->prior, o.prior, 1088 * sizeof(float), hipMemcpyHostToDevice, s));
         BBS_HIP(hipMemsetAsync(ws->dstate, 0, sizeof(State), s));
         for (int step = 0; step < L; ++step) {
-            k_dive_expand<<<1, 64, 0, s>>>(ws->dives, M, C, ws->groups, ws->scores, ws->state, ws->dstate);
+            k_beam_expand<<<1, 64, 0, s>>>(ws->beam, C, ws->groups, ws->scores, ws->state, ws->dstate);
             launch_score(S, map, ws, ws->dstate, 0, score_grid, false);
-            k_dive_pick<<<1, 64, 0, s>>>(ws->dives, M, ws->groups, ws->scores, ws->state);
+            k_beam_pick<<<1, kBeamThreads, 0, s>>>(ws->beam, beam_w, ws->groups, ws->scores, ws->dstate, ws->state, PC,
+                                                   ws->prior, C.threshold);
         }
-        k_dive_seed<<<1, 64, 0, s>>>(ws->dives, M, ws->state);
+        k_beam_seed<<<1, 64, 0, s>>>(ws->beam, ws->state);
         serial(1);
+        beam_used = beam_w;
+        // the host copies above read pageable memory; finish them before hb goes away
+        BBS_HIP(hipStreamSynchronize(s));
     }
     BBS_HIP(hipGetLastError());
     BBS_HIP(hipMemcpyAsync(ws->host_state, ws->state, sizeof(State), hipMemcpyDeviceToHost, s));
@@ -1713,8 +1894,11 @@ extern "C" bbs_status bbs_localize(const bbs_map *map, bbs_workspace *ws, const 
     out->nodes_expanded = fs.nodes_expanded;
     out->nodes_scored = init_nodes + fs.nodes_scored + fs.dive_scored;
     out->prior_used = use_prior ? 1 : 0;
+    out->seed_beam_used = beam_used;
     out->persistent_used = persistent_used ? 1 : 0;
     out->seeded = fs.seeded;
+    out->serial_ms[0] = (double)fs.t_push * 1e-5;
+    out->serial_ms[1] = (double)fs.t_gather * 1e-5;
     out->seed_score = fs.seeded ? fs.seed_score : 0;
     out->flushes = fs.flushes;
     out->leaves_accepted = fs.leaves_accepted;

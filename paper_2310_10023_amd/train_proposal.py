@@ -1,6 +1,9 @@
 """Train the learned proposal network on (scan, plain-BnB optimum) pairs.
 
-    python -m paper_2310_10023_amd.train_proposal --maps 40 --scans 50 --out weights.npz
+    python -m paper_2310_10023_amd.train_proposal --maps 50 --scans 400 --out weights.npz
+
+or in shards: `--map-start S --maps M --data-out shard.npz` per shard, then
+`--data a.npz,b.npz,... --out weights.npz`.
 
 For every seeded training city (seeds 0.. maps-1; the benchmark city 1000 is
 held out) scans are ray-cast from random street poses, localized by the
@@ -50,22 +53,19 @@ def he_init(seed: int) -> np.ndarray:
     return flat
 
 
-_SCENE = None
-
-
-def _init_worker(boxes, ground, extent, streets):
-    global _SCENE
-    _SCENE = synth.Scene(points=np.zeros((0, 3), np.float32), boxes=boxes, ground=ground, walls_box=None,
-                         extent=extent, streets=streets)
-
-
 def _scan_worker(args):
-    seed, k = args
-    sc = synth.scan_scene(_SCENE, seed, k, z=1.8, rp_deg=3.0, n_beams=64, n_az=2048, voxel=0.5)
+    geom, seed, k = args
+    boxes, ground, extent, streets = geom
+    scene = synth.Scene(points=np.zeros((0, 3), np.float32), boxes=boxes, ground=ground, walls_box=None,
+                        extent=extent, streets=streets)
+    sc = synth.scan_scene(scene, seed, k, z=1.8, rp_deg=3.0, n_beams=64, n_az=2048, voxel=0.5)
     return sc.points, sc.pose
 
 
-def make_dataset(map_seeds, scans_per_map, k=10000, workers=8, bnb_workers=4, log=print):
+def make_dataset(map_seeds, scans_per_map, pool, k=10000, bnb_workers=4, log=print):
+    """(BEV image, yaw bin, xy cell) of the plain-BnB optimum for `scans_per_map`
+    seeded scans of each city in `map_seeds`.  `pool` is a process pool
+    created before the GPU is initialised; it ray-casts the scans."""
     lo, hi = synth.search_range_city()
     T = synth.threshold_95(k)
     images, yaws, cells, meta = [], [], [], []
@@ -73,9 +73,8 @@ def make_dataset(map_seeds, scans_per_map, k=10000, workers=8, bnb_workers=4, lo
         t0 = time.time()
         city = synth.city_scene(ms)
         gmap = bbs.Map(city.points, 1.0, 6)
-        with mp.get_context("fork").Pool(workers, initializer=_init_worker,
-                                         initargs=(city.boxes, city.ground, city.extent, city.streets)) as pool:
-            scans = pool.map(_scan_worker, [(10_000 * ms + i, k) for i in range(scans_per_map)])
+        geom = (city.boxes, city.ground, city.extent, city.streets)
+        scans = pool.map(_scan_worker, [(geom, 10_000 * ms + i, k) for i in range(scans_per_map)], chunksize=8)
         pts = [s[0] for s in scans]
         res, _, _ = bbs.serve(gmap, pts, [(lo, hi)] * len(pts), [T] * len(pts), [0.0] * len(pts),
                               workers=bnb_workers)
@@ -89,6 +88,7 @@ def make_dataset(map_seeds, scans_per_map, k=10000, workers=8, bnb_workers=4, lo
             meta.append((ms, float(np.hypot(*(np.array(r["pose"][:2]) - pose[:2])))))
             kept += 1
         gmap.close()
+        del city
         log(f"[data] map {ms}: {kept}/{len(pts)} localized in {time.time() - t0:.1f} s")
     return np.stack(images), np.array(yaws, np.int32), np.array(cells, np.int32), meta
 
@@ -121,29 +121,44 @@ def train(images, yaw, xy, epochs=40, batch=128, lr=2e-3, weight_decay=1e-4, see
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
-    ap.add_argument("--maps", type=int, default=40)
-    ap.add_argument("--scans", type=int, default=50)
+    ap.add_argument("--maps", type=int, default=50)
+    ap.add_argument("--map-start", type=int, default=0, help="first training city seed")
+    ap.add_argument("--scans", type=int, default=400)
     ap.add_argument("--epochs", type=int, default=40)
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
-    ap.add_argument("--out", required=True)
-    ap.add_argument("--data", default=None, help="cache of the generated pairs (.npz)")
+    ap.add_argument("--out", default=None, help="trained parameters (.npz)")
+    ap.add_argument("--data", default=None,
+                    help="comma-separated cached pair files (.npz) to train on instead of generating pairs")
+    ap.add_argument("--data-out", default=None, help="write the generated pairs here (.npz)")
     args = ap.parse_args()
+    if not args.out and not args.data_out:
+        ap.error("nothing to do: give --out and/or --data-out")
+    # the ray-casting workers are forked before anything touches the GPU
+    pool = None if args.data else mp.get_context("fork").Pool(args.workers)
     import torch
     torch.cuda.set_device(0)
     t0 = time.time()
-    if args.data and os.path.exists(args.data):
-        d = np.load(args.data)
-        images, yaw, xy = d["images"], d["yaw"], d["xy"]
+    if args.data:
+        parts = [np.load(f) for f in args.data.split(",")]
+        images = np.concatenate([d["images"] for d in parts])
+        yaw = np.concatenate([d["yaw"] for d in parts])
+        xy = np.concatenate([d["xy"] for d in parts])
     else:
-        images, yaw, xy, _ = make_dataset(range(args.maps), args.scans, workers=args.workers,
-                                          log=lambda m: print(m, flush=True))
-        if args.data:
-            np.savez_compressed(args.data, images=images, yaw=yaw, xy=xy)
+        seeds = range(args.map_start, args.map_start + args.maps)
+        images, yaw, xy, meta = make_dataset(seeds, args.scans, pool, log=lambda m: print(m, flush=True))
+        pool.close()
+        pool.join()
+        if args.data_out:
+            np.savez_compressed(args.data_out, images=images, yaw=yaw, xy=xy,
+                                map_seed=np.array([m[0] for m in meta], np.int32),
+                                xy_err=np.array([m[1] for m in meta], np.float64))
     print(f"[data] {len(images)} pairs in {time.time() - t0:.1f} s", flush=True)
+    if not args.out:
+        return
     params = train(images, yaw, xy, epochs=args.epochs, log=lambda m: print(m, flush=True))
     np.savez_compressed(args.out, params=params,
-                        info=json.dumps({"pairs": int(len(images)), "maps": args.maps, "scans_per_map": args.scans,
-                                         "epochs": args.epochs}))
+                        info=json.dumps({"pairs": int(len(images)), "epochs": args.epochs,
+                                         "data": args.data or f"cities {args.map_start}..{args.map_start + args.maps - 1}"}))
     print(f"[train] wrote {args.out} after {time.time() - t0:.1f} s", flush=True)
 
 

@@ -11,6 +11,7 @@ import pytest
 
 import oracle
 import paper_2310_10023_amd as bbs
+from paper_2310_10023_amd import proposal
 import synth
 
 pytestmark = pytest.mark.gpu
@@ -266,10 +267,11 @@ def test_localize_errors(room):
 
 
 @pytest.mark.parametrize("translation_only", [False, True])
-@pytest.mark.parametrize("dives", [0, 3])
-def test_localize_with_prior_equals_oracle(room, translation_only, dives):
-    """Prior-ordered initial set and seed dives: same schedule as the oracle."""
-    say("localize prior", translation_only, dives)
+@pytest.mark.parametrize("beam", [0, 3, 16, 1000])
+def test_localize_with_prior_equals_oracle(room, translation_only, beam):
+    """Prior-ordered initial set and seed beam: same schedule as the oracle
+    (the oracle runs at the beam width the library reports after clamping)."""
+    say("localize prior", translation_only, beam)
     scene, g, o = room
     sc = synth.scan_scene(scene, 21, 1200, z=1.5, z_jitter=0.25, rp_deg=2.0)
     lo, hi = synth.search_range_room()
@@ -279,13 +281,34 @@ def test_localize_with_prior_equals_oracle(room, translation_only, dives):
         lo[:2], hi[:2] = sc.pose[:2] - 2.0, sc.pose[:2] + 2.0
     T = synth.threshold_95(1200)
     prior = np.random.default_rng(3).normal(size=1088).astype(np.float32) * 2
-    want = oracle.Search(o, sc.points, lo, hi, translation_only=translation_only).localize(
-        T, batch=500, threads=8, prior=prior, n_seed_dives=dives)
     got = bbs.localize(g, sc.points, lo, hi, T, batch_size=500, translation_only=translation_only, prior=prior,
-                       n_seed_dives=dives)
+                       seed_beam=beam)
+    assert got["seed_beam_used"] <= min(beam, 64)
+    if beam:
+        assert got["seed_beam_used"] > 0
+    want = oracle.Search(o, sc.points, lo, hi, translation_only=translation_only).localize(
+        T, batch=500, threads=8, prior=prior, seed_beam=got["seed_beam_used"])
     compare(got, want)
     assert got["prior_used"] == want["prior_used"] == 1
     assert (got["seeded"], got["seed_score"]) == (want["seeded"], want["seed_score"])
+
+
+def test_true_pose_prior_seeds_the_incumbent(room):
+    """A prior peaked at the scan's true yaw bin and translation cell leads
+    the beam to a leaf at or above the threshold."""
+    say("true-pose prior")
+    scene, g, o = room
+    sc = synth.scan_scene(scene, 23, 1500, z=1.5, z_jitter=0.25, rp_deg=2.0)
+    lo, hi = synth.search_range_room()
+    T = synth.threshold_95(1500)
+    prior = np.zeros(1088, np.float32)
+    prior[proposal.yaw_bin(sc.pose[5])] = 8.0
+    prior[64 + proposal.xy_cell(sc.pose[0], sc.pose[1], lo, hi)] = 8.0
+    got = bbs.localize(g, sc.points, lo, hi, T, batch_size=2000, prior=prior, seed_beam=8)
+    assert got["seeded"] == 1 and got["seed_score"] >= T
+    want = oracle.Search(o, sc.points, lo, hi).localize(T, batch=2000, threads=8, prior=prior,
+                                                         seed_beam=got["seed_beam_used"])
+    compare(got, want)
 
 
 def test_serve_matches_single_queries(room):

@@ -201,22 +201,101 @@ def test_room_success_criterion(seed):
     assert err_t < 2.0 and err_r < 0.05, (err_t, err_r)
 
 
-# ------------------------------------------------------------------ learned prior (ordering and seed dives)
+# ------------------------------------------------------------------ learned prior (ordering and seed beam)
+#
+# Not in the paper.  The prior key of a node is the best yaw-bin logit over
+# the leaf yaws below it plus the best translation-cell logit over the leaf
+# translations below it.  Pins: a leaf's key is the logit pair of its own
+# bins (the label binning of the training data); a parent's key is the
+# maximum of its children's keys (the leaves below a node are the disjoint
+# union of the leaves below its children, and the children are every
+# rotation child paired with every translation child); a seed beam wide
+# enough to keep every node reaching the threshold finds the exhaustive
+# optimum in translation-only mode (the bound is valid there, so every leaf
+# at or above the threshold has all its ancestors at or above it too).
 
-@pytest.mark.parametrize("dives", [0, 1, 4])
+
+def _label_bins(s, leaf):
+    """Yaw bin and translation cell of a leaf, the way training labels are
+    binned: the leaf's yaw is its cell centre, its translation r * i."""
+    two_pi = 2 * math.pi
+    g = s.grid
+    yaw = g.wmin[2] + g.dprime[2][0] * (leaf[6] + 0.5)
+    yb = int(math.floor((yaw % two_pi) / (two_pi / 64))) % 64
+    cells = []
+    for ax in range(2):
+        x = float(np.float32(g.r)) * leaf[1 + ax]
+        c = int(math.floor(32 * (x - g.tmin[ax]) / (g.tmax[ax] - g.tmin[ax])))
+        cells.append(min(max(c, 0), 31))
+    return yb, cells[0] * 32 + cells[1]
+
+
+@pytest.mark.parametrize("translation_only", [True, False])
+def test_prior_key_of_leaf_is_its_bin_logits(translation_only):
+    s = tiny_case(4, translation_only=translation_only, rp_deg=2.0, z_w=0.5)
+    rng = np.random.default_rng(11)
+    prior = rng.normal(size=1088).astype(np.float32)
+    g = s.grid
+    for _ in range(200):
+        leaf = [0] + [int(rng.integers(g.lo[a], g.hi[a] + 1)) for a in range(3)] + \
+               [int(rng.integers(0, g.n[a][0])) for a in range(3)]
+        yb, cell = _label_bins(s, leaf)
+        assert s.prior_key(prior, leaf) == float(prior[yb]) + float(prior[64 + cell])
+
+
+@pytest.mark.parametrize("translation_only", [True, False])
+def test_prior_key_of_parent_is_max_over_children(translation_only):
+    s = tiny_case(5, translation_only=translation_only, rp_deg=2.0, z_w=0.5, levels=3)
+    prior = np.random.default_rng(12).normal(size=1088).astype(np.float32) * 4
+    L = s.grid.levels
+    # walk the tree from every top-level cell, checking every expanded node
+    frontier = []
+    for x in range(s.grid.lo[0] >> L, (s.grid.hi[0] >> L) + 1):
+        for y in range(s.grid.lo[1] >> L, (s.grid.hi[1] >> L) + 1):
+            for z in range(s.grid.lo[2] >> L, (s.grid.hi[2] >> L) + 1):
+                for ig in range(s.n(2, L)):
+                    frontier.append([L, x, y, z, 0, 0, ig])
+    checked = 0
+    rng = np.random.default_rng(0)
+    while frontier and checked < 300:
+        node = frontier.pop(int(rng.integers(len(frontier))))
+        if node[0] == 0:
+            continue
+        ch = s.children(node)
+        assert len(ch) > 0
+        kc = max(s.prior_key(prior, c) for c in ch)
+        assert s.prior_key(prior, node) == kc
+        checked += 1
+        frontier.extend(c.tolist() for c in ch[rng.permutation(len(ch))[:3]])
+    assert checked >= 50
+
+
+@pytest.mark.parametrize("beam", [0, 1, 4])
 @pytest.mark.parametrize("seed", [0, 2])
-def test_prior_keeps_translation_only_result_exact(seed, dives):
-    """Ordering ties by a prior and seeding the incumbent by greedy dives leave
-    the translation-only optimum unchanged (pruning stays strict)."""
+def test_prior_keeps_translation_only_result_exact(seed, beam):
+    """Ordering ties by a prior and seeding the incumbent by a beam leave the
+    translation-only optimum unchanged (pruning stays strict)."""
     s = tiny_case(seed, rp_deg=2.0, z_w=0.5)
     T = int(0.6 * s.k)
     bf = s.bruteforce(T, threads=8)
     prior = np.random.default_rng(seed).normal(size=1088).astype(np.float32) * 3
-    r = s.localize(T, batch=64, threads=8, prior=prior, n_seed_dives=dives)
+    r = s.localize(T, batch=64, threads=8, prior=prior, seed_beam=beam)
     assert r["prior_used"] == 1
     assert (r["found"], r["score"], r["leaf"]) == (bf["found"], bf["score"], bf["leaf"])
     if r["seeded"]:
         assert r["seed_score"] <= r["score"]
+
+
+@pytest.mark.parametrize("seed", [1, 3])
+def test_full_width_beam_finds_exhaustive_optimum(seed):
+    s = tiny_case(seed, rp_deg=2.0, z_w=0.5)
+    T = int(0.6 * s.k)
+    bf = s.bruteforce(T, threads=8)
+    assert bf["found"] == 1
+    prior = np.random.default_rng(seed).normal(size=1088).astype(np.float32)
+    r = s.localize(T, batch=64, threads=8, prior=prior, seed_beam=1 << 30)
+    assert r["seeded"] == 1 and r["seed_score"] == bf["score"]
+    assert (r["score"], r["leaf"]) == (bf["score"], bf["leaf"])
 
 
 def test_flat_prior_changes_nothing_and_nan_prior_is_ignored():
@@ -226,18 +305,20 @@ def test_flat_prior_changes_nothing_and_nan_prior_is_ignored():
     flat = s.localize(T, batch=100, threads=8, prior=np.zeros(1088, np.float32))
     nan = np.zeros(1088, np.float32)
     nan[5] = np.nan
-    ign = s.localize(T, batch=100, threads=8, prior=nan, n_seed_dives=4)
+    ign = s.localize(T, batch=100, threads=8, prior=nan, seed_beam=4)
     assert flat["prior_used"] == 1 and ign["prior_used"] == 0 and ign["seeded"] == 0
     for key in ("found", "score", "leaf", "nodes_expanded", "nodes_scored", "flushes"):
         assert flat[key] == plain[key] and ign[key] == plain[key], key
 
 
-def test_seed_dive_counts_and_incumbent():
+def test_seed_beam_counts_and_incumbent():
     s = tiny_case(3, translation_only=True, rp_deg=2.0, z_w=0.5)
     T = int(0.5 * s.k)
     prior = np.random.default_rng(5).normal(size=1088).astype(np.float32)
-    a = s.localize(T, batch=64, threads=8, prior=prior, n_seed_dives=0)
-    b = s.localize(T, batch=64, threads=8, prior=prior, n_seed_dives=2)
+    a = s.localize(T, batch=64, threads=8, prior=prior, seed_beam=0)
+    b = s.localize(T, batch=64, threads=8, prior=prior, seed_beam=2)
     assert b["seeded"] == 1 and T <= b["seed_score"] <= b["score"] == a["score"]
-    # a dive expands one node per level and scores all of that node's children
-    assert b["nodes_expanded"] >= 3 and b["nodes_scored"] > b["initial_size"]
+    # the beam expands at most two nodes per level and scores their children
+    L = s.grid.levels
+    assert L <= b["nodes_expanded"] - a["nodes_expanded"] + 2 * L
+    assert b["nodes_scored"] > b["initial_size"]
