@@ -140,6 +140,14 @@ bbs_status bbs_build_map(const float *xyz, int64_t n, int32_t xyz_on_device, flo
 /* Release a map (NULL is ignored). */
 void bbs_free_map(bbs_map *map);
 
+/* Lookup layout of level `level` (0..l_max) as the scoring kernel reads it:
+ * *dense = 1 if the level's occupancy masks are also held as a dense grid
+ * over the brick bounding box (chosen at build time when the grid has at
+ * most 4x the hash table's slots), 0 if lookups probe the hash table;
+ * *dense_entries = grid entries (16 bytes each), 0 without a grid.  Either
+ * output may be NULL.  Membership and scores do not depend on the layout. */
+bbs_status bbs_map_layout(const bbs_map *map, int32_t level, int32_t *dense, int64_t *dense_entries);
+
 /* Map facts: l_max, r, and per level the number of voxels in the dilated set
  * D_l, the number of hash slots and of occupied slots.  Arrays of 16. */
 bbs_status bbs_map_info(const bbs_map *map, int32_t *levels, float *min_res, int64_t *voxels,

@@ -23,7 +23,7 @@ MAX_LEVELS = 16
 
 EXPORTED_SYMBOLS = (
     "bbs_default_options", "bbs_abi_version", "bbs_last_error", "bbs_build_map", "bbs_free_map", "bbs_map_info",
-    "bbs_map_dump_level", "bbs_map_contains", "bbs_workspace_create", "bbs_workspace_free", "bbs_localize",
+    "bbs_map_layout", "bbs_map_dump_level", "bbs_map_contains", "bbs_workspace_create", "bbs_workspace_free", "bbs_localize",
     "bbs_score_nodes", "bbs_serve", "bbs_net_param_count", "bbs_net_create", "bbs_net_free", "bbs_net_set_params",
     "bbs_net_get_params", "bbs_net_forward", "bbs_net_train_step", "bbs_bev_image", "bbs_autotune",
 )
@@ -105,6 +105,8 @@ def lib():
         L.bbs_free_map.argtypes = [P]
         L.bbs_map_info.argtypes = [P, C.POINTER(I32), C.POINTER(F), P, P, P]
         L.bbs_map_info.restype = C.c_int
+        L.bbs_map_layout.argtypes = [P, I32, C.POINTER(I32), C.POINTER(I64)]
+        L.bbs_map_layout.restype = C.c_int
         L.bbs_map_dump_level.argtypes = [P, I32, P, I64, C.POINTER(I64)]
         L.bbs_map_dump_level.restype = C.c_int
         L.bbs_map_contains.argtypes = [P, I32, P, I64, P]
@@ -207,8 +209,15 @@ class Map:
         _check(lib().bbs_map_info(self._h, C.byref(lv), C.byref(r), vox.ctypes.data, slots.ctypes.data,
                                   bricks.ctypes.data))
         n = lv.value + 1
+        dense, dense_n = [], []
+        for l in range(n):
+            d = C.c_int32()
+            e = C.c_int64()
+            _check(lib().bbs_map_layout(self._h, l, C.byref(d), C.byref(e)))
+            dense.append(bool(d.value))
+            dense_n.append(e.value)
         return {"levels": lv.value, "min_res": r.value, "voxels": vox[:n].tolist(), "slots": slots[:n].tolist(),
-                "bricks": bricks[:n].tolist()}
+                "bricks": bricks[:n].tolist(), "dense": dense, "dense_entries": dense_n}
 
     def dump_level(self, level: int) -> np.ndarray:
         """Voxels of D_level as an (m, 3) int32 array, sorted lexicographically."""

@@ -23,6 +23,8 @@ namespace {
 constexpr int kThreads = 256;
 constexpr unsigned long long kEmpty64 = 0xFFFFFFFFFFFFFFFFull;
 constexpr int32_t kPackBias = 1 << 20;
+constexpr int64_t kDenseRatio = 4;              // dense grid only if its entries <= 4 x the hash capacity
+constexpr int64_t kDenseMax = (int64_t)1 << 27; // and at most 2^27 entries (2 GiB)
 
 inline int grid_for(int64_t n, int threads = kThreads, int cap = 8192)
 {
@@ -243,6 +245,21 @@ __global__ void k_compact(const Slot *src, uint64_t src_n, uint2 *dkeys, uint4 *
     }
 }
 
+// Copy every brick of a finished level into its dense grid (zeroed before).
+__global__ void k_fill_dense(const uint2 *keys, const uint4 *bits, uint64_t cap, uint4 *dense, int32_t bx0, int32_t by0,
+                             int32_t bz0, int32_t nbx, int32_t nby)
+{
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < cap; i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint2 kk = keys[i];
+        if (kk.x == kEmptyLo && kk.y == kEmptyHi) continue;
+        const unsigned long long key = ((unsigned long long)kk.y << 32) | kk.x;
+        const int32_t bx = (int32_t)((key >> 38) & 0x7FFFF) - kBrickBias;
+        const int32_t by = (int32_t)((key >> 19) & 0x7FFFF) - kBrickBias;
+        const int32_t bz = (int32_t)(key & 0x7FFFF) - kBrickBias;
+        dense[dense_index((uint32_t)(bx - bx0), (uint32_t)(by - by0), (uint32_t)(bz - bz0), nbx, nby)] = bits[i];
+    }
+}
+
 __global__ void k_fill_level(uint2 *keys, uint4 *bits, uint64_t n)
 {
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
@@ -394,6 +411,9 @@ bbs::MapView bbs_map::view() const
         LevelView &lv = v.lv[l];
         lv.keys = l <= levels ? keys[l] : nullptr;
         lv.bits = l <= levels ? bits[l] : nullptr;
+        lv.dense = l <= levels ? dense[l] : nullptr;
+        lv.nbx = l <= levels ? nbx[l] : 0;
+        lv.nby = l <= levels ? nby[l] : 0;
         lv.cap_mask = l <= levels ? (uint32_t)(cap[l] - 1) : 0u;
         for (int a = 0; a < 3; ++a) {
             lv.bmin[a] = l <= levels ? bmin[l][a] : 1;
@@ -409,6 +429,7 @@ extern "C" void bbs_free_map(bbs_map *map)
     for (int l = 0; l < kMaxLevels; ++l) {
         if (map->keys[l]) (void)hipFree(map->keys[l]);
         if (map->bits[l]) (void)hipFree(map->bits[l]);
+        if (map->dense[l]) (void)hipFree(map->dense[l]);
     }
     delete map;
 }
@@ -537,10 +558,40 @@ extern "C" bbs_status bbs_build_map(const float *xyz, int64_t n, int32_t xyz_on_
                 m->bmax[l][a] = bbox[3 + a];
             }
             m->voxels[l] = (int64_t)nv;
+            // dense mask grid when the bounding box (in 2x2x2 blocks) holds at
+            // most kDenseRatio x the hash capacity
+            const int64_t nb3[3] = {((int64_t)bbox[3] - bbox[0] + 2) / 2, ((int64_t)bbox[4] - bbox[1] + 2) / 2,
+                                    ((int64_t)bbox[5] - bbox[2] + 2) / 2};
+            const int64_t dn = 8 * nb3[0] * nb3[1] * nb3[2];
+            if (dn <= kDenseRatio * (int64_t)cap && dn <= kDenseMax) {
+                void *dd = nullptr;
+                if (alloc_dev(&dd, (size_t)dn * sizeof(uint4))) {
+                    bbs_free_map(m);
+                    return BBS_ERR_OOM;
+                }
+                m->dense[l] = static_cast<uint4 *>(dd);
+                m->dense_n[l] = dn;
+                m->nbx[l] = (int32_t)nb3[0];
+                m->nby[l] = (int32_t)nb3[1];
+                BBS_HIP(hipMemsetAsync(dd, 0, (size_t)dn * sizeof(uint4), s));
+                k_fill_dense<<<grid_for((int64_t)cap), kThreads, 0, s>>>(m->keys[l], m->bits[l], cap, m->dense[l],
+                                                                         bbox[0], bbox[1], bbox[2], m->nbx[l], m->nby[l]);
+                BBS_HIP(hipGetLastError());
+                BBS_HIP(hipStreamSynchronize(s));
+            }
             break;
         }
     }
     *out = m;
+    return BBS_OK;
+}
+
+extern "C" bbs_status bbs_map_layout(const bbs_map *map, int32_t level, int32_t *dense, int64_t *dense_entries)
+{
+    if (!map) return fail(BBS_ERR_INVALID_ARG, "bbs_map_layout: map is NULL");
+    if (level < 0 || level > map->levels) return fail(BBS_ERR_INVALID_ARG, "bbs_map_layout: level out of range");
+    if (dense) *dense = map->dense[level] ? 1 : 0;
+    if (dense_entries) *dense_entries = map->dense_n[level];
     return BBS_OK;
 }
 

@@ -334,8 +334,9 @@ __device__ inline void rotation(const double2 *trig, const SearchConst &C, int l
 // (bx + jx, by + jy, bz + jz) is w + j with w = floor(floor(R s / r) / 2^l) +
 // (bx, by, bz) (float32 transform, fixed evaluation order, no contraction).
 // The brick floor(w / 4) holds all eight candidate voxels, so one probe per
-// point answers the whole group.  Each thread keeps kUnroll points (and their
-// probe chains) in flight.  A group's points are split over several
+// point answers the whole group.  A level with a dense mask grid is read with
+// one load per point; otherwise the brick is looked up in the hash table.
+// Each thread keeps kUnroll points (and their probe chains) in flight.  A group's points are split over several
 // workgroups when the batch has few groups; partial counts are added with
 // integer atomics into scores zeroed by the producer of the batch.
 // Batch header fields written by another workgroup of the same launch are
@@ -443,7 +444,8 @@ __device__ void score_items(State *st, const ScoreArgs &A, const MapView &map, c
         rotation(trig, C, level, hi16u(G.y), lo16u(G.z), hi16u(G.z), R);
         const LevelView lv = map.lv[level];
         const uint2 *__restrict__ keys = lv.keys;
-        const uint4 *__restrict__ bitsv = lv.bits;
+        const bool use_dense = lv.dense != nullptr;      // uniform over the workgroup
+        const uint4 *__restrict__ bitsv = use_dense ? lv.dense : lv.bits;
         const uint32_t cap_mask = lv.cap_mask;
         const uint32_t ex = (uint32_t)(lv.bmax[0] - lv.bmin[0]);
         const uint32_t ey = (uint32_t)(lv.bmax[1] - lv.bmin[1]);
@@ -474,31 +476,39 @@ __device__ void score_items(State *st, const ScoreArgs &A, const MapView &map, c
                     }
                     const int32_t wx = w[0] + bx, wy = w[1] + by, wz = w[2] + bz;
                     const int32_t Bx = wx >> 2, By = wy >> 2, Bz = wz >> 2;
-                    if ((uint32_t)(Bx - lv.bmin[0]) <= ex && (uint32_t)(By - lv.bmin[1]) <= ey &&
-                        (uint32_t)(Bz - lv.bmin[2]) <= ez) {
-                        state[u] = 1;
-                        klo[u] = brick_key_lo(Bx, By, Bz);
-                        khi[u] = brick_key_hi(Bx, By, Bz);
-                        h[u] = brick_hash(Bx, By, Bz) & cap_mask;
+                    const uint32_t rx = (uint32_t)(Bx - lv.bmin[0]), ry = (uint32_t)(By - lv.bmin[1]),
+                                   rz = (uint32_t)(Bz - lv.bmin[2]);
+                    if (rx <= ex && ry <= ey && rz <= ez) {
                         i0[u] = ((wz & 3) * 5 + (wy & 3)) * 5 + (wx & 3);   // 0 .. 93
-                    }
-                }
-            }
-            for (;;) {
-                bool again = false;
-#pragma unroll
-                for (int u = 0; u < kUnroll; ++u) {
-                    if (state[u] == 1) {
-                        const uint2 kk = keys[h[u]];
-                        if (kk.x == klo[u] && kk.y == khi[u]) state[u] = 2;
-                        else if (kk.x == kEmptyLo && kk.y == kEmptyHi) state[u] = 0;
-                        else {
-                            h[u] = (h[u] + 1) & cap_mask;
-                            again = true;
+                        if (use_dense) {
+                            state[u] = 2;
+                            h[u] = dense_index(rx, ry, rz, lv.nbx, lv.nby);
+                        } else {
+                            state[u] = 1;
+                            klo[u] = brick_key_lo(Bx, By, Bz);
+                            khi[u] = brick_key_hi(Bx, By, Bz);
+                            h[u] = brick_hash(Bx, By, Bz) & cap_mask;
                         }
                     }
                 }
-                if (!again) break;
+            }
+            if (!use_dense) {
+                for (;;) {
+                    bool again = false;
+    #pragma unroll
+                    for (int u = 0; u < kUnroll; ++u) {
+                        if (state[u] == 1) {
+                            const uint2 kk = keys[h[u]];
+                            if (kk.x == klo[u] && kk.y == khi[u]) state[u] = 2;
+                            else if (kk.x == kEmptyLo && kk.y == kEmptyHi) state[u] = 0;
+                            else {
+                                h[u] = (h[u] + 1) & cap_mask;
+                                again = true;
+                            }
+                        }
+                    }
+                    if (!again) break;
+                }
             }
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {

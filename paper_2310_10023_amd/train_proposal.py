@@ -93,11 +93,29 @@ def make_dataset(map_seeds, scans_per_map, pool, k=10000, bnb_workers=4, log=pri
     return np.stack(images), np.array(yaws, np.int32), np.array(cells, np.int32), meta
 
 
-def train(images, yaw, xy, epochs=40, batch=128, lr=2e-3, weight_decay=1e-4, seed=0, log=print):
+def evaluate(net, images, yaw, xy, batch=256):
+    """Held-out metrics: mean loss terms are not needed here, only how often
+    the true yaw bin / translation cell is among the top-k logits."""
+    hits = {"yaw_top1": 0, "yaw_top4": 0, "yaw_top8": 0, "xy_top1": 0, "xy_top16": 0}
+    for b0 in range(0, len(images), batch):
+        out = net.forward(images[b0:b0 + batch])
+        ry = np.argsort(-out[:, :64], axis=1)
+        rc = np.argsort(-out[:, 64:], axis=1)
+        ty, tc = yaw[b0:b0 + batch], xy[b0:b0 + batch]
+        for k in (1, 4, 8):
+            hits[f"yaw_top{k}"] += int(np.sum(np.any(ry[:, :k] == ty[:, None], axis=1)))
+        for k in (1, 16):
+            hits[f"xy_top{k}"] += int(np.sum(np.any(rc[:, :k] == tc[:, None], axis=1)))
+    n = max(len(images), 1)
+    return {k: v / n for k, v in hits.items()}
+
+
+def train(images, yaw, xy, epochs=40, batch=128, lr=2e-3, weight_decay=1e-4, seed=0, val=None, log=print):
     rng = np.random.default_rng(seed)
-    net = proposal.Net(max_batch=batch, params=he_init(seed))
+    net = proposal.Net(max_batch=max(batch, 256), params=he_init(seed))
     n = len(images)
     steps = 0
+    total_steps = max(1, epochs * (n // batch))
     for ep in range(epochs):
         perm = rng.permutation(n)
         # yaw augmentation: rotating the scan by whole azimuth bins shifts the image
@@ -110,13 +128,16 @@ def train(images, yaw, xy, epochs=40, batch=128, lr=2e-3, weight_decay=1e-4, see
             shift = rng.integers(0, 64, size=len(idx))
             img = np.stack([np.roll(images[i], s, axis=1) for i, s in zip(idx, shift)])
             y = (yaw[idx] - shift) % 64
-            cur_lr = lr * 0.5 * (1 + math.cos(math.pi * steps / max(1, epochs * (n // batch))))
+            cur_lr = lr * 0.5 * (1 + math.cos(math.pi * steps / total_steps))
             loss, _ = net.train_step(img, y, xy[idx], lr=cur_lr, weight_decay=weight_decay)
             tot += loss
             cnt += 1
             steps += 1
-        log(f"[train] epoch {ep}: loss {tot / max(cnt, 1):.3f}")
-    return net.get_params()
+        msg = f"[train] epoch {ep}: loss {tot / max(cnt, 1):.3f}"
+        if val is not None and (ep % 5 == 4 or ep == epochs - 1):
+            msg += " val " + json.dumps({k: round(v, 3) for k, v in evaluate(net, *val).items()})
+        log(msg)
+    return net.get_params(), (evaluate(net, *val) if val is not None else None)
 
 
 def main():
@@ -130,6 +151,8 @@ def main():
     ap.add_argument("--data", default=None,
                     help="comma-separated cached pair files (.npz) to train on instead of generating pairs")
     ap.add_argument("--data-out", default=None, help="write the generated pairs here (.npz)")
+    ap.add_argument("--val-maps", type=int, default=5,
+                    help="the last N training cities of the data are held out for validation")
     args = ap.parse_args()
     if not args.out and not args.data_out:
         ap.error("nothing to do: give --out and/or --data-out")
@@ -143,9 +166,11 @@ def main():
         images = np.concatenate([d["images"] for d in parts])
         yaw = np.concatenate([d["yaw"] for d in parts])
         xy = np.concatenate([d["xy"] for d in parts])
+        map_seed = np.concatenate([d["map_seed"] for d in parts])
     else:
         seeds = range(args.map_start, args.map_start + args.maps)
         images, yaw, xy, meta = make_dataset(seeds, args.scans, pool, log=lambda m: print(m, flush=True))
+        map_seed = np.array([m[0] for m in meta], np.int32)
         pool.close()
         pool.join()
         if args.data_out:
@@ -155,9 +180,17 @@ def main():
     print(f"[data] {len(images)} pairs in {time.time() - t0:.1f} s", flush=True)
     if not args.out:
         return
-    params = train(images, yaw, xy, epochs=args.epochs, log=lambda m: print(m, flush=True))
+    held = np.unique(map_seed)[-args.val_maps:] if args.val_maps > 0 else np.zeros(0, np.int32)
+    is_val = np.isin(map_seed, held)
+    val = (images[is_val], yaw[is_val], xy[is_val]) if is_val.any() else None
+    print(f"[train] {int((~is_val).sum())} training pairs, {int(is_val.sum())} held-out pairs "
+          f"(cities {held.tolist()})", flush=True)
+    params, val_metrics = train(images[~is_val], yaw[~is_val], xy[~is_val], epochs=args.epochs, val=val,
+                                log=lambda m: print(m, flush=True))
     np.savez_compressed(args.out, params=params,
-                        info=json.dumps({"pairs": int(len(images)), "epochs": args.epochs,
+                        info=json.dumps({"pairs": int((~is_val).sum()), "held_out_pairs": int(is_val.sum()),
+                                         "held_out_cities": held.tolist(), "epochs": args.epochs,
+                                         "held_out_metrics": val_metrics,
                                          "data": args.data or f"cities {args.map_start}..{args.map_start + args.maps - 1}"}))
     print(f"[train] wrote {args.out} after {time.time() - t0:.1f} s", flush=True)
 

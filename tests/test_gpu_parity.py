@@ -100,6 +100,24 @@ def test_scores_equal_oracle_room(room, k):
     want = s.score_nodes(nodes, threads=8)
     got = bbs.score_nodes(g, sc.points, lo, hi, nodes)
     np.testing.assert_array_equal(got, want)
+    assert all(g.info()["dense"])          # the room's levels are read from dense grids
+
+
+def test_scores_hash_layout_equal_oracle():
+    """Two copies of the room 900 m apart: the bounding boxes are mostly
+    empty, so no level gets a dense grid and every lookup probes the hash
+    table; scores still equal the oracle's."""
+    say("scores hash layout")
+    room = synth.room_scene(0)
+    both = np.concatenate([room.points, room.points + np.array([900.0, 0.0, 0.0], np.float32)])
+    g = bbs.Map(both, 0.5, 4)
+    assert not any(g.info()["dense"])
+    o = oracle.Map(both, 0.5, 4)
+    sc = synth.scan_scene(room, 7, 1500, z=1.5, z_jitter=0.25, rp_deg=2.0)
+    lo, hi = synth.search_range_room()
+    s = oracle.Search(o, sc.points, lo, hi)
+    nodes = random_nodes(s, np.random.default_rng(21), 3000, 4)
+    np.testing.assert_array_equal(bbs.score_nodes(g, sc.points, lo, hi, nodes), s.score_nodes(nodes, threads=8))
 
 
 def test_scores_non_power_of_two_voxel():
