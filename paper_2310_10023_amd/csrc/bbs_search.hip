@@ -445,45 +445,129 @@ __device__ void score_items(State *st, const ScoreArgs &A, const MapView &map, c
         const LevelView lv = map.lv[level];
         const uint2 *__restrict__ keys = lv.keys;
         const bool use_dense = lv.dense != nullptr;      // uniform over the workgroup
-        const uint4 *__restrict__ bitsv = use_dense ? lv.dense : lv.bits;
+        const uint4 *__restrict__ bitsv = lv.bits;
         const uint32_t cap_mask = lv.cap_mask;
         const uint32_t ex = (uint32_t)(lv.bmax[0] - lv.bmin[0]);
         const uint32_t ey = (uint32_t)(lv.bmax[1] - lv.bmin[1]);
         const uint32_t ez = (uint32_t)(lv.bmax[2] - lv.bmin[2]);
         int c0 = 0, c1 = 0, c2 = 0, c3 = 0, c4 = 0, c5 = 0, c6 = 0, c7 = 0;
-        for (int kb = k_begin + (int)threadIdx.x; kb < k_end; kb += NT * kUnroll) {
-            uint32_t h[kUnroll], klo[kUnroll], khi[kUnroll];
-            int i0[kUnroll];
-            int state[kUnroll];   // 0: miss, 1: probing, 2: found
+        if (use_dense) {
+            // Branch-free: clamped scan loads and every grid load of the
+            // kUnroll points are issued before any result is used; a point
+            // past the range or outside the box reads entry 0 and counts 0.
+            // The eight counts run as two SWAR words of four 8-bit lanes
+            // (members 0, 4, 2, 6 and 1, 5, 3, 7), folded into the int
+            // counters every kFold rounds, before a lane can overflow.
+            constexpr int kFold = 255 / kUnroll;
+            uint32_t acc_a = 0, acc_b = 0;
+            int rounds = 0;
+            const uint4 *__restrict__ dense = lv.dense;
+            const int32_t nbx = lv.nbx, nby = lv.nby;
+            for (int kb = k_begin + (int)threadIdx.x; kb < k_end; kb += NT * kUnroll) {
+                float sx[kUnroll], sy[kUnroll], sz[kUnroll];
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
-                const int k = kb + u * NT;
-                state[u] = 0;
-                h[u] = 0;
-                klo[u] = khi[u] = 0;
-                i0[u] = 0;
-                if (k < k_end) {
-                    const float sx = X[k], sy = Y[k], sz = Z[k];
+                for (int u = 0; u < kUnroll; ++u) {
+                    const int k = min(kb + u * NT, k_end - 1);
+                    sx[u] = X[k];
+                    sy[u] = Y[k];
+                    sz[u] = Z[k];
+                }
+                uint32_t idx[kUnroll], i0[kUnroll];
+                bool ok[kUnroll];
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u) {
                     int32_t w[3];
 #pragma unroll
                     for (int row = 0; row < 3; ++row) {
-                        float t0 = R[3 * row + 0] * sx;
-                        float t1 = R[3 * row + 1] * sy;
-                        float t2 = R[3 * row + 2] * sz;
+                        float t0 = R[3 * row + 0] * sx[u];
+                        float t1 = R[3 * row + 1] * sy[u];
+                        float t2 = R[3 * row + 2] * sz[u];
                         float p = (t0 + t1) + t2;
                         float q = POW2 ? p * C.inv_r : p / C.r;
                         w[row] = ((int32_t)floorf(q) >> level);
                     }
                     const int32_t wx = w[0] + bx, wy = w[1] + by, wz = w[2] + bz;
-                    const int32_t Bx = wx >> 2, By = wy >> 2, Bz = wz >> 2;
-                    const uint32_t rx = (uint32_t)(Bx - lv.bmin[0]), ry = (uint32_t)(By - lv.bmin[1]),
-                                   rz = (uint32_t)(Bz - lv.bmin[2]);
-                    if (rx <= ex && ry <= ey && rz <= ez) {
-                        i0[u] = ((wz & 3) * 5 + (wy & 3)) * 5 + (wx & 3);   // 0 .. 93
-                        if (use_dense) {
-                            state[u] = 2;
-                            h[u] = dense_index(rx, ry, rz, lv.nbx, lv.nby);
-                        } else {
+                    const uint32_t rx = (uint32_t)((wx >> 2) - lv.bmin[0]);
+                    const uint32_t ry = (uint32_t)((wy >> 2) - lv.bmin[1]);
+                    const uint32_t rz = (uint32_t)((wz >> 2) - lv.bmin[2]);
+                    ok[u] = kb + u * NT < k_end && rx <= ex && ry <= ey && rz <= ez;
+                    const uint32_t blk = __umul24(__umul24(rz >> 1, (uint32_t)nby) + (ry >> 1), (uint32_t)nbx) + (rx >> 1);
+                    idx[u] = ok[u] ? ((blk << 3) | ((rz & 1u) << 2) | ((ry & 1u) << 1) | (rx & 1u)) : 0u;
+                    i0[u] = (uint32_t)(((wz & 3) * 5 + (wy & 3)) * 5 + (wx & 3));   // 0 .. 93
+                }
+                uint4 bits[kUnroll];
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u) bits[u] = dense[idx[u]];
+                // keep every mask whole in registers: one 16-byte load per point,
+                // never a load split by which words the window needs
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u)
+                    asm volatile("" : "+v"(bits[u].x), "+v"(bits[u].y), "+v"(bits[u].z), "+v"(bits[u].w));
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u) {
+                    const uint32_t word = i0[u] >> 5;
+                    const uint32_t lo = word == 0 ? bits[u].x : (word == 1 ? bits[u].y : bits[u].z);
+                    const uint32_t hi = word == 0 ? bits[u].y : (word == 1 ? bits[u].z : bits[u].w);
+                    uint32_t win = __builtin_amdgcn_alignbit(hi, lo, i0[u] & 31u);
+                    win = ok[u] ? win : 0u;
+                    // member j = 4 jx + 2 jy + jz sits at window bit 25 jz + 5 jy + jx
+                    const uint32_t qa = (win & 3u) | ((win >> 3) & 0xCu);           // members 0, 4, 2, 6
+                    const uint32_t qb = ((win >> 25) & 3u) | ((win >> 28) & 0xCu);  // members 1, 5, 3, 7
+                    // spread bit i of a 4-bit value to bit 8 i
+                    acc_a += __umul24(qa, 0x204081u) & 0x01010101u;
+                    acc_b += __umul24(qb, 0x204081u) & 0x01010101u;
+                }
+                if (++rounds == kFold) {
+                    c0 += acc_a & 0xFF;
+                    c4 += (acc_a >> 8) & 0xFF;
+                    c2 += (acc_a >> 16) & 0xFF;
+                    c6 += acc_a >> 24;
+                    c1 += acc_b & 0xFF;
+                    c5 += (acc_b >> 8) & 0xFF;
+                    c3 += (acc_b >> 16) & 0xFF;
+                    c7 += acc_b >> 24;
+                    acc_a = acc_b = 0;
+                    rounds = 0;
+                }
+            }
+            c0 += acc_a & 0xFF;
+            c4 += (acc_a >> 8) & 0xFF;
+            c2 += (acc_a >> 16) & 0xFF;
+            c6 += acc_a >> 24;
+            c1 += acc_b & 0xFF;
+            c5 += (acc_b >> 8) & 0xFF;
+            c3 += (acc_b >> 16) & 0xFF;
+            c7 += acc_b >> 24;
+        } else {
+            for (int kb = k_begin + (int)threadIdx.x; kb < k_end; kb += NT * kUnroll) {
+                uint32_t h[kUnroll], klo[kUnroll], khi[kUnroll];
+                int i0[kUnroll];
+                int state[kUnroll];   // 0: miss, 1: probing, 2: found
+    #pragma unroll
+                for (int u = 0; u < kUnroll; ++u) {
+                    const int k = kb + u * NT;
+                    state[u] = 0;
+                    h[u] = 0;
+                    klo[u] = khi[u] = 0;
+                    i0[u] = 0;
+                    if (k < k_end) {
+                        const float sx = X[k], sy = Y[k], sz = Z[k];
+                        int32_t w[3];
+    #pragma unroll
+                        for (int row = 0; row < 3; ++row) {
+                            float t0 = R[3 * row + 0] * sx;
+                            float t1 = R[3 * row + 1] * sy;
+                            float t2 = R[3 * row + 2] * sz;
+                            float p = (t0 + t1) + t2;
+                            float q = POW2 ? p * C.inv_r : p / C.r;
+                            w[row] = ((int32_t)floorf(q) >> level);
+                        }
+                        const int32_t wx = w[0] + bx, wy = w[1] + by, wz = w[2] + bz;
+                        const int32_t Bx = wx >> 2, By = wy >> 2, Bz = wz >> 2;
+                        const uint32_t rx = (uint32_t)(Bx - lv.bmin[0]), ry = (uint32_t)(By - lv.bmin[1]),
+                                       rz = (uint32_t)(Bz - lv.bmin[2]);
+                        if (rx <= ex && ry <= ey && rz <= ez) {
+                            i0[u] = ((wz & 3) * 5 + (wy & 3)) * 5 + (wx & 3);   // 0 .. 93
                             state[u] = 1;
                             klo[u] = brick_key_lo(Bx, By, Bz);
                             khi[u] = brick_key_hi(Bx, By, Bz);
@@ -491,8 +575,6 @@ __device__ void score_items(State *st, const ScoreArgs &A, const MapView &map, c
                         }
                     }
                 }
-            }
-            if (!use_dense) {
                 for (;;) {
                     bool again = false;
     #pragma unroll
@@ -509,24 +591,24 @@ __device__ void score_items(State *st, const ScoreArgs &A, const MapView &map, c
                     }
                     if (!again) break;
                 }
-            }
-#pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
-                if (state[u] == 2) {
-                    const uint4 bits = bitsv[h[u]];
-                    const int word = i0[u] >> 5;
-                    const uint32_t lo = word == 0 ? bits.x : (word == 1 ? bits.y : bits.z);
-                    const uint32_t hi = word == 0 ? bits.y : (word == 1 ? bits.z : bits.w);
-                    const uint32_t win = __builtin_amdgcn_alignbit(hi, lo, (uint32_t)(i0[u] & 31));
-                    // member j = 4 jx + 2 jy + jz sits at window bit 25 jz + 5 jy + jx
-                    c0 += (win >> 0) & 1u;
-                    c1 += (win >> 25) & 1u;
-                    c2 += (win >> 5) & 1u;
-                    c3 += (win >> 30) & 1u;
-                    c4 += (win >> 1) & 1u;
-                    c5 += (win >> 26) & 1u;
-                    c6 += (win >> 6) & 1u;
-                    c7 += (win >> 31) & 1u;
+    #pragma unroll
+                for (int u = 0; u < kUnroll; ++u) {
+                    if (state[u] == 2) {
+                        const uint4 bits = bitsv[h[u]];
+                        const int word = i0[u] >> 5;
+                        const uint32_t lo = word == 0 ? bits.x : (word == 1 ? bits.y : bits.z);
+                        const uint32_t hi = word == 0 ? bits.y : (word == 1 ? bits.z : bits.w);
+                        const uint32_t win = __builtin_amdgcn_alignbit(hi, lo, (uint32_t)(i0[u] & 31));
+                        // member j = 4 jx + 2 jy + jz sits at window bit 25 jz + 5 jy + jx
+                        c0 += (win >> 0) & 1u;
+                        c1 += (win >> 25) & 1u;
+                        c2 += (win >> 5) & 1u;
+                        c3 += (win >> 30) & 1u;
+                        c4 += (win >> 1) & 1u;
+                        c5 += (win >> 26) & 1u;
+                        c6 += (win >> 6) & 1u;
+                        c7 += (win >> 31) & 1u;
+                    }
                 }
             }
         }
@@ -785,132 +867,214 @@ __device__ inline void child_counts(const SearchConst &C, const int32_t t[3], co
 // Pops the queue until more than b children are pending (Alg. 2).  Between
 // two flushes nothing is pushed, so pops come in (score desc, level asc,
 // FIFO) order straight off the buckets: a leaf bucket is accepted whole (its
-// lexicographically smallest leaf competes for the match), an inner bucket
-// is consumed node by node, a chunk at a time, until the pending count
-// passes b.  Buckets below the running best are never touched (their nodes
-// would be pruned).  Writes the pending children as groups and zeroes their
-// score slots.
+// lexicographically smallest leaf competes for the match), inner nodes are
+// consumed in order until the pending count passes b.  Buckets below the
+// running best are never touched (their nodes would be pruned).
+//
+// The non-empty buckets of the live range are listed first (one pass of NT
+// buckets at a time).  Inner nodes are then consumed in windows of up to NT
+// nodes that may span several buckets: a window is a run of consecutive
+// listed inner buckets, each contributing the rest of its head chunk, and it
+// extends past a bucket only if that bucket ends in this chunk (otherwise its
+// next chunk comes first).  Writes the pending children as groups and zeroes
+// their score slots.
+template <int NT>
+struct GatherSmem {
+    int sm[NT / 64];
+    int smatch[NT][6];
+    int lq[NT];               // listed buckets (bucket index), in queue order
+    Bucket lb[NT];            // their current head / tail
+    int pre[NT];              // window: inclusive prefix of segment lengths
+    int s_last[2];
+    int s_end;
+};
+
+__device__ inline int seg_len(const Bucket &b)
+{
+    return (b.head_chunk == b.tail_chunk ? b.tail_fill : kChunk) - b.head_off;
+}
+
 template <int NT>
 __device__ void gather(State *st, Bucket *bk, const int32_t *chunk_next, const uint4 *arena, const SearchConst &C,
-                       uint4 *groups, int32_t *scores, int *sm, int (*smatch)[6], int *s_last)
+                       uint4 *groups, int32_t *scores, GatherSmem<NT> &sh)
 {
+    static_assert(NT >= kChunk, "a window must be able to hold a whole chunk segment");
     const int tid = threadIdx.x;
     const int Lp1 = C.levels + 1;
     int best = st->best;
     int have = st->have_match;
     int32_t match[6];
     for (int i = 0; i < 6; ++i) match[i] = st->match[i];
-    int q = st->top_q;
+    int q = st->top_q;                 // no bucket below q holds nodes
     int64_t pend = 0;
     int ngrp = 0;
     int64_t expanded = 0, leaves = 0;
     bool cut = false;
-    for (;;) {
-        if (best > C.K) break;
-        const int qlim = min((C.K - best) * Lp1 + C.levels, C.q_count - 1);
-        int found = INT_MAX;
-        for (int b0 = q; b0 <= qlim; b0 += NT) {
-            const int qq = b0 + tid;
-            const int cand = (qq <= qlim && bk[qq].head_chunk >= 0) ? qq : INT_MAX;
-            found = block_min_int<NT>(cand, sm);
-            if (found != INT_MAX) break;
-        }
-        if (found == INT_MAX) break;
-        q = found;
-        const int level = q % Lp1;
-        const int score = C.K - q / Lp1;
-        const Bucket b = bk[q];
-        int c = b.head_chunk, off = b.head_off;
-        if (level == 0) {
-            int32_t mine[6] = {INT_MAX, INT_MAX, INT_MAX, INT_MAX, INT_MAX, INT_MAX};
-            while (c >= 0) {
-                const int end = c == b.tail_chunk ? b.tail_fill : kChunk;
-                for (int i = off + tid; i < end; i += NT) {
-                    int32_t t[3], ang[3], lv;
-                    node_unpack(arena[(int64_t)c * kChunk + i], t, ang, lv);
-                    const int32_t cand[6] = {t[0], t[1], t[2], ang[0], ang[1], ang[2]};
-                    if (leaf_less(cand, mine))
-                        for (int k = 0; k < 6; ++k) mine[k] = cand[k];
-                }
-                leaves += end - off;
-                c = c == b.tail_chunk ? -1 : chunk_next[c];
-                off = 0;
+    while (!cut && best <= C.K) {
+        int qlim = min((C.K - best) * Lp1 + C.levels, C.q_count - 1);
+        if (q > qlim) break;
+        // list the non-empty buckets among the next NT
+        const int scan_end = min(q + NT - 1, qlim);
+        {
+            const int qq = q + tid;
+            Bucket b = Bucket{-1, 0, -1, 0};
+            if (qq <= scan_end) b = bk[qq];
+            const int ne = b.head_chunk >= 0 ? 1 : 0;
+            int n_list;
+            const int pos = block_scan_incl<NT>(ne, sh.sm, &n_list) - ne;
+            if (ne) {
+                sh.lq[pos] = qq;
+                sh.lb[pos] = b;
             }
             __syncthreads();
-            for (int k = 0; k < 6; ++k) smatch[tid][k] = mine[k];
-            __syncthreads();
-            for (int sh = NT / 2; sh > 0; sh >>= 1) {
-                if (tid < sh && leaf_less(smatch[tid + sh], smatch[tid]))
-                    for (int k = 0; k < 6; ++k) smatch[tid][k] = smatch[tid + sh][k];
-                __syncthreads();
-            }
-            if (!have || score > best || leaf_less(smatch[0], match))
-                for (int k = 0; k < 6; ++k) match[k] = smatch[0][k];
-            __syncthreads();
-            have = 1;
-            best = score;
-            if (tid == 0) bk[q] = Bucket{-1, 0, -1, 0};
-            ++q;
-            continue;
-        }
-        while (c >= 0) {
-            const int end = c == b.tail_chunk ? b.tail_fill : kChunk;
-            const int avail = min(end - off, NT);
-            const int i = off + tid;
-            const bool valid = tid < avail;
-            int32_t t[3] = {0, 0, 0}, ang[3] = {0, 0, 0}, lv = level;
-            int rc[3] = {0, 0, 0}, nn = 0, ng = 0;
-            uint32_t tmask = 0;
-            if (valid) {
-                node_unpack(arena[(int64_t)c * kChunk + i], t, ang, lv);
-                child_counts(C, t, ang, level, rc, tmask, nn, ng);
-            }
-            int tot_n, tot_g;
-            const int incl_n = block_scan_incl<NT>(nn, sm, &tot_n);
-            const int incl_g = block_scan_incl<NT>(ng, sm, &tot_g);
-            const int over = (valid && pend + incl_n > C.batch) ? tid : INT_MAX;
-            const int cutidx = block_min_int<NT>(over, sm);
-            const int consumed = cutidx != INT_MAX ? cutidx + 1 : avail;
-            if (tid < consumed && ng > 0) {
-                int gi = ngrp + incl_g - ng;
-                for (int ja = 0; ja < rc[0]; ++ja)
-                    for (int jb = 0; jb < rc[1]; ++jb)
-                        for (int jg = 0; jg < rc[2]; ++jg) {
-                            const int ra = C.a[0][level] * ang[0] + ja;
-                            const int rb = C.a[1][level] * ang[1] + jb;
-                            const int rg = C.a[2][level] * ang[2] + jg;
-                            groups[gi++] = make_uint4(pack16(2 * t[0], 2 * t[1]), pack16(2 * t[2], ra),
-                                                      pack16(rb, rg), (uint32_t)(level - 1) | (tmask << 8));
+            int e = 0;
+            while (e < n_list && !cut) {
+                const int qe = sh.lq[e];
+                if (qe > qlim) break;
+                if (qe % Lp1 == 0) {
+                    // a leaf bucket: accept all of it
+                    const int score = C.K - qe / Lp1;
+                    const Bucket lbk = sh.lb[e];
+                    int c = lbk.head_chunk, off = lbk.head_off;
+                    int32_t mine[6] = {INT_MAX, INT_MAX, INT_MAX, INT_MAX, INT_MAX, INT_MAX};
+                    while (c >= 0) {
+                        const int end = c == lbk.tail_chunk ? lbk.tail_fill : kChunk;
+                        for (int i = off + tid; i < end; i += NT) {
+                            int32_t t[3], ang[3], lv;
+                            node_unpack(arena[(int64_t)c * kChunk + i], t, ang, lv);
+                            const int32_t cand[6] = {t[0], t[1], t[2], ang[0], ang[1], ang[2]};
+                            if (leaf_less(cand, mine))
+                                for (int k = 0; k < 6; ++k) mine[k] = cand[k];
                         }
+                        leaves += end - off;
+                        c = c == lbk.tail_chunk ? -1 : chunk_next[c];
+                        off = 0;
+                    }
+                    __syncthreads();
+                    for (int k = 0; k < 6; ++k) sh.smatch[tid][k] = mine[k];
+                    __syncthreads();
+                    for (int h = NT / 2; h > 0; h >>= 1) {
+                        if (tid < h && leaf_less(sh.smatch[tid + h], sh.smatch[tid]))
+                            for (int k = 0; k < 6; ++k) sh.smatch[tid][k] = sh.smatch[tid + h][k];
+                        __syncthreads();
+                    }
+                    if (!have || score > best || leaf_less(sh.smatch[0], match))
+                        for (int k = 0; k < 6; ++k) match[k] = sh.smatch[0][k];
+                    __syncthreads();
+                    have = 1;
+                    best = score;
+                    qlim = min((C.K - best) * Lp1 + C.levels, C.q_count - 1);
+                    if (tid == 0) bk[qe] = Bucket{-1, 0, -1, 0};
+                    ++e;
+                    continue;
+                }
+                // window of inner buckets e .. e + n_win - 1
+                {
+                    const int i = e + tid;
+                    int seg = 0;
+                    bool ok = false;
+                    if (i < n_list) {
+                        const int qi = sh.lq[i];
+                        ok = qi <= qlim && qi % Lp1 != 0;
+                        seg = ok ? seg_len(sh.lb[i]) : 0;
+                    }
+                    int tot;
+                    const int incl = block_scan_incl<NT>(seg, sh.sm, &tot);
+                    // an entry may follow the previous one only if that one ends in its head chunk
+                    bool prev_last = true;
+                    if (tid > 0 && i < n_list) prev_last = sh.lb[i - 1].head_chunk == sh.lb[i - 1].tail_chunk;
+                    const bool in_win = i < n_list && ok && incl <= NT && (tid == 0 || prev_last);
+                    const int first_out = block_min_int<NT>(in_win ? INT_MAX : tid, sh.sm);
+                    const int n_win = first_out == INT_MAX ? min(NT, n_list - e) : first_out;
+                    if (tid < n_win) sh.pre[tid] = incl;
+                    if (tid == 0) sh.s_end = n_win;
+                    __syncthreads();
+                }
+                const int n_win = sh.s_end;
+                const int W = sh.pre[n_win - 1];
+                // node t of the window: entry j with pre[j-1] <= t < pre[j]
+                int32_t t3[3] = {0, 0, 0}, ang[3] = {0, 0, 0}, lv = 0;
+                int rc[3] = {0, 0, 0}, nn = 0, ng = 0;
+                uint32_t tmask = 0;
+                int level = 0;
+                const bool valid = tid < W;
+                if (valid) {
+                    int lo = 0, hi = n_win - 1;
+                    while (lo < hi) {
+                        const int mid = (lo + hi) >> 1;
+                        if (sh.pre[mid] > tid) hi = mid;
+                        else lo = mid + 1;
+                    }
+                    const int j = lo;
+                    const int base = j > 0 ? sh.pre[j - 1] : 0;
+                    const Bucket bj = sh.lb[e + j];
+                    level = sh.lq[e + j] % Lp1;
+                    node_unpack(arena[(int64_t)bj.head_chunk * kChunk + bj.head_off + (tid - base)], t3, ang, lv);
+                    child_counts(C, t3, ang, level, rc, tmask, nn, ng);
+                }
+                int tot_n, tot_g;
+                const int incl_n = block_scan_incl<NT>(nn, sh.sm, &tot_n);
+                const int incl_g = block_scan_incl<NT>(ng, sh.sm, &tot_g);
+                const int over = (valid && pend + incl_n > C.batch) ? tid : INT_MAX;
+                const int cutidx = block_min_int<NT>(over, sh.sm);
+                const int consumed = cutidx != INT_MAX ? cutidx + 1 : W;
+                if (tid < consumed && ng > 0) {
+                    int gi = ngrp + incl_g - ng;
+                    for (int ja = 0; ja < rc[0]; ++ja)
+                        for (int jb = 0; jb < rc[1]; ++jb)
+                            for (int jg = 0; jg < rc[2]; ++jg) {
+                                const int ra = C.a[0][level] * ang[0] + ja;
+                                const int rb = C.a[1][level] * ang[1] + jb;
+                                const int rg = C.a[2][level] * ang[2] + jg;
+                                groups[gi++] = make_uint4(pack16(2 * t3[0], 2 * t3[1]), pack16(2 * t3[2], ra),
+                                                          pack16(rb, rg), (uint32_t)(level - 1) | (tmask << 8));
+                            }
+                }
+                if (tid == consumed - 1) {
+                    sh.s_last[0] = incl_n;
+                    sh.s_last[1] = incl_g;
+                }
+                __syncthreads();
+                pend += sh.s_last[0];
+                ngrp += sh.s_last[1];
+                expanded += consumed;
+                // advance the window's buckets (one thread per entry)
+                int next_e = e + n_win;
+                if (tid < n_win) {
+                    const int base = tid > 0 ? sh.pre[tid - 1] : 0;
+                    const int seg = sh.pre[tid] - base;
+                    const int used = min(max(consumed - base, 0), seg);
+                    Bucket b = sh.lb[e + tid];
+                    if (used == seg) {
+                        if (b.head_chunk == b.tail_chunk) b = Bucket{-1, 0, -1, 0};
+                        else {
+                            b.head_chunk = chunk_next[b.head_chunk];
+                            b.head_off = 0;
+                        }
+                    } else {
+                        b.head_off += used;
+                    }
+                    if (used > 0) {
+                        bk[sh.lq[e + tid]] = b;
+                        sh.lb[e + tid] = b;
+                    }
+                }
+                __syncthreads();
+                if (cutidx != INT_MAX) {
+                    cut = true;
+                    break;
+                }
+                // the last window bucket may continue in its next chunk
+                const Bucket lastb = sh.lb[e + n_win - 1];
+                if (lastb.head_chunk >= 0) next_e = e + n_win - 1;
+                e = next_e;
             }
-            if (tid == consumed - 1) {
-                s_last[0] = incl_n;
-                s_last[1] = incl_g;
-            }
+            // after a cut the window's first bucket (at or before the cut) is
+            // the lowest that may still hold nodes; otherwise every listed
+            // bucket up to scan_end is empty or lies below the running best
+            q = cut ? sh.lq[e] : scan_end + 1;
             __syncthreads();
-            pend += s_last[0];
-            ngrp += s_last[1];
-            expanded += consumed;
-            __syncthreads();
-            off += consumed;
-            if (off == end) {
-                c = c == b.tail_chunk ? -1 : chunk_next[c];
-                off = 0;
-            }
-            if (cutidx != INT_MAX) {
-                cut = true;
-                break;
-            }
         }
-        if (tid == 0) {
-            if (c < 0) bk[q] = Bucket{-1, 0, -1, 0};
-            else {
-                bk[q].head_chunk = c;
-                bk[q].head_off = off;
-            }
-        }
-        if (cut) break;
-        ++q;
     }
     __syncthreads();
     for (int i = tid; i < 8 * ngrp; i += NT) scores[i] = 0;
@@ -944,8 +1108,7 @@ __device__ void gather(State *st, Bucket *bk, const int32_t *chunk_next, const u
 template <int NT>
 struct SerialSmem {
     int sm[NT / 64];
-    int smatch[NT][6];
-    int s_last[2];
+    GatherSmem<NT> g;
 };
 
 template <int NT>
@@ -962,7 +1125,7 @@ __device__ void serial_body(State *st, const SearchConst &C, Bucket *bk, uint4 *
     if (threadIdx.x == 0) st->batch = 0;
     __syncthreads();
     if (do_gather) {
-        gather<NT>(st, bk, B.chunk_next, B.arena, C, groups, scores, sh.sm, sh.smatch, sh.s_last);
+        gather<NT>(st, bk, B.chunk_next, B.arena, C, groups, scores, sh.g);
         __syncthreads();
         if (threadIdx.x == 0) st->t_gather += (int64_t)(__builtin_amdgcn_s_memrealtime() - t1);
     }
