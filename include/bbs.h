@@ -105,8 +105,9 @@ typedef struct {
     int32_t persistent_used;  /* 1: the search loop ran as one persistent kernel */
     int32_t seed_beam_used;   /* beam width after clamping (0: no beam ran) */
     int32_t reserved_r;
-    double serial_ms[2];      /* device time of the serial queue work: push, then gather
-                                 (summed over iterations, from the 100 MHz device clock) */
+    double serial_ms[4];      /* device time of the serial queue work, summed over iterations
+                                 (100 MHz device clock): push, gather, and of push the
+                                 bucket prefix over tiles and the chunk allocation */
 } bbs_result;
 
 /* Fill *opt with the defaults (b = 10000, roto-translational, no profiling,

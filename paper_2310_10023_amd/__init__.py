@@ -59,7 +59,7 @@ class Result(C.Structure):
                 ("score_kernel_ms", C.c_double), ("score_launches", C.c_int64), ("score_pairs", C.c_int64),
                 ("score_groups", C.c_int64), ("phase_ms", C.c_double * 4), ("prior_used", C.c_int32),
                 ("seeded", C.c_int32), ("seed_score", C.c_int32), ("persistent_used", C.c_int32),
-                ("seed_beam_used", C.c_int32), ("reserved_r", C.c_int32), ("serial_ms", C.c_double * 2)]
+                ("seed_beam_used", C.c_int32), ("reserved_r", C.c_int32), ("serial_ms", C.c_double * 4)]
 
     def as_dict(self):
         return {"found": self.found, "score": self.score, "leaf": list(self.leaf), "pose": list(self.pose),

@@ -59,6 +59,7 @@ struct State {
     int64_t dive_scored;      // children scored by the seed beam
     int32_t seeded, seed_score;
     int64_t t_push, t_gather; // device real-time ticks (100 MHz) spent in the serial push and gather
+    int64_t t_push_prefix, t_push_alloc;   // of t_push: bucket prefix over tiles, chunk allocation
 };
 
 // ---- learned prior: seed beam (not in the paper)
@@ -437,7 +438,10 @@ __device__ void score_items(State *st, const ScoreArgs &A, const MapView &map, c
     for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
         const int g = (int)(item / S), sp = (int)(item % S);
         const int k_begin = (int)((int64_t)K * sp / S), k_end = (int)((int64_t)K * (sp + 1) / S);
-        const uint4 G = groups[g];
+        // the group is the same for every lane of the item: keep it in scalar registers
+        const uint4 Gv = groups[g];
+        const uint4 G = make_uint4(__builtin_amdgcn_readfirstlane(Gv.x), __builtin_amdgcn_readfirstlane(Gv.y),
+                                   __builtin_amdgcn_readfirstlane(Gv.z), __builtin_amdgcn_readfirstlane(Gv.w));
         const int level = (int)(G.w & 0xFF);
         const int bx = lo16s(G.x), by = hi16s(G.x), bz = lo16s(G.y);
         float R[9];
@@ -467,10 +471,11 @@ __device__ void score_items(State *st, const ScoreArgs &A, const MapView &map, c
                 float sx[kUnroll], sy[kUnroll], sz[kUnroll];
 #pragma unroll
                 for (int u = 0; u < kUnroll; ++u) {
-                    const int k = min(kb + u * NT, k_end - 1);
-                    sx[u] = X[k];
-                    sy[u] = Y[k];
-                    sz[u] = Z[k];
+                    // 32-bit byte offsets (K <= 2^24): base + offset addressing
+                    const uint32_t koff = (uint32_t)min(kb + u * NT, k_end - 1) * 4u;
+                    sx[u] = *reinterpret_cast<const float *>(reinterpret_cast<const char *>(X) + koff);
+                    sy[u] = *reinterpret_cast<const float *>(reinterpret_cast<const char *>(Y) + koff);
+                    sz[u] = *reinterpret_cast<const float *>(reinterpret_cast<const char *>(Z) + koff);
                 }
                 uint32_t idx[kUnroll], i0[kUnroll];
                 bool ok[kUnroll];
@@ -497,7 +502,8 @@ __device__ void score_items(State *st, const ScoreArgs &A, const MapView &map, c
                 }
                 uint4 bits[kUnroll];
 #pragma unroll
-                for (int u = 0; u < kUnroll; ++u) bits[u] = dense[idx[u]];
+                for (int u = 0; u < kUnroll; ++u)     // grid entries < 2^27: byte offset < 2^31
+                    bits[u] = *reinterpret_cast<const uint4 *>(reinterpret_cast<const char *>(dense) + idx[u] * 16u);
                 // keep every mask whole in registers: one 16-byte load per point,
                 // never a load split by which words the window needs
 #pragma unroll
@@ -726,7 +732,9 @@ __device__ void push_finish(State *st, const SearchConst &C, Bucket *bk, const u
     const int n_tiles = (st->n_groups + kTileGroups - 1) / kTileGroups;
     if (q_max < q_min || kept == 0) return;
     const int nq = q_max - q_min + 1;
-    // per-bucket prefix over tiles (loads first, in blocks of 16 tiles)
+    const uint64_t tp0 = __builtin_amdgcn_s_memrealtime();
+    // per-bucket prefix over tiles (tile-major histogram: the lanes of a wave
+    // read consecutive buckets of one tile; loads in blocks of 16 tiles)
     for (int qi = tid; qi < nq; qi += NT) {
         const int q = q_min + qi;
         int acc = 0;
@@ -744,6 +752,7 @@ __device__ void push_finish(State *st, const SearchConst &C, Bucket *bk, const u
         B.totals[qi] = acc;
     }
     __syncthreads();
+    const uint64_t tp1 = __builtin_amdgcn_s_memrealtime();
     // chunks needed, then allocation in bucket order
     int64_t total_new = 0;
     for (int c = 0; c < nq; c += NT) {
@@ -802,32 +811,66 @@ __device__ void push_finish(State *st, const SearchConst &C, Bucket *bk, const u
         run += tot;
     }
     __syncthreads();
+    if (tid == 0) {
+        st->t_push_prefix += (int64_t)(tp1 - tp0);
+        st->t_push_alloc += (int64_t)(__builtin_amdgcn_s_memrealtime() - tp1);
+    }
     // scatter: the child of rank r in its bucket fills the tail chunk first
     const int n_slots = n_tiles * kTileSlots;
-    for (int i = tid; i < n_slots; i += NT) {
-        const int q = B.q_arr[i];
-        if (q < 0) continue;
-        const int t = i / kTileSlots, sl = i % kTileSlots;
-        const int g = t * kTileGroups + sl / 8, j = sl & 7;
-        const uint4 G = groups[g];
-        const int qi = q - q_min;
-        const int r = B.hist[(int64_t)t * C.q_count + q] + B.rank_arr[i];
-        const int T = B.pT[qi], f = B.pf[qi];
-        const int space = T >= 0 ? kChunk - f : 0;
-        int64_t pos;
-        if (r < space) pos = (int64_t)T * kChunk + f + r;
-        else {
-            const int r2 = r - space;
-            pos = (int64_t)(B.pc0[qi] + r2 / kChunk) * kChunk + (r2 % kChunk);
+    constexpr int kU = 4;                       // slots in flight per thread
+    for (int i0 = tid; i0 < n_slots; i0 += kU * NT) {
+        int qv[kU], rk[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int i = i0 + u * NT;
+            qv[u] = i < n_slots ? B.q_arr[i] : -1;
+            rk[u] = i < n_slots ? B.rank_arr[i] : 0;
         }
-        const int jx = (j >> 2) & 1, jy = (j >> 1) & 1, jz = j & 1;
-        const int x = lo16s(G.x) + jx, y = hi16s(G.x) + jy, z = lo16s(G.y) + jz;
-        B.arena[pos] = make_uint4(pack16(x, y), pack16(z, hi16u(G.y)), G.z, G.w & 0xFFu);
+        int base[kU], Tc[kU], fc[kU], c0[kU];
+        uint4 G[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int i = i0 + u * NT;
+            const bool ok = qv[u] >= 0;
+            const int q = ok ? qv[u] : q_min;             // safe indices for empty slots
+            const int t = ok ? i / kTileSlots : 0;
+            const int g = ok ? t * kTileGroups + (i % kTileSlots) / 8 : 0;
+            base[u] = B.hist[(int64_t)t * C.q_count + q];
+            Tc[u] = B.pT[q - q_min];
+            fc[u] = B.pf[q - q_min];
+            c0[u] = B.pc0[q - q_min];
+            G[u] = groups[g];
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            if (qv[u] < 0) continue;
+            const int i = i0 + u * NT;
+            const int j = i & 7;
+            const int r = base[u] + rk[u];
+            const int space = Tc[u] >= 0 ? kChunk - fc[u] : 0;
+            int64_t pos;
+            if (r < space) pos = (int64_t)Tc[u] * kChunk + fc[u] + r;
+            else {
+                const int r2 = r - space;
+                pos = (int64_t)(c0[u] + r2 / kChunk) * kChunk + (r2 % kChunk);
+            }
+            const int jx = (j >> 2) & 1, jy = (j >> 1) & 1, jz = j & 1;
+            const int x = lo16s(G[u].x) + jx, y = hi16s(G[u].x) + jy, z = lo16s(G[u].y) + jz;
+            B.arena[pos] = make_uint4(pack16(x, y), pack16(z, hi16u(G[u].y)), G[u].z, G[u].w & 0xFFu);
+        }
     }
     __syncthreads();
-    for (int i = tid; i < n_slots; i += NT) {
-        const int q = B.q_arr[i];
-        if (q >= 0 && B.rank_arr[i] == 0) B.hist[(int64_t)(i / kTileSlots) * C.q_count + q] = 0;
+    for (int i0 = tid; i0 < n_slots; i0 += kU * NT) {
+        int qv[kU], rk[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int i = i0 + u * NT;
+            qv[u] = i < n_slots ? B.q_arr[i] : -1;
+            rk[u] = i < n_slots ? B.rank_arr[i] : 1;
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u)
+            if (qv[u] >= 0 && rk[u] == 0) B.hist[(int64_t)((i0 + u * NT) / kTileSlots) * C.q_count + qv[u]] = 0;
     }
     if (tid == 0) {
         st->chunk_top = chunk_top + (int)total_new;
@@ -2072,6 +2115,8 @@ extern "C" bbs_status bbs_localize(const bbs_map *map, bbs_workspace *ws, const 
     out->seeded = fs.seeded;
     out->serial_ms[0] = (double)fs.t_push * 1e-5;
     out->serial_ms[1] = (double)fs.t_gather * 1e-5;
+    out->serial_ms[2] = (double)fs.t_push_prefix * 1e-5;
+    out->serial_ms[3] = (double)fs.t_push_alloc * 1e-5;
     out->seed_score = fs.seeded ? fs.seed_score : 0;
     out->flushes = fs.flushes;
     out->leaves_accepted = fs.leaves_accepted;
