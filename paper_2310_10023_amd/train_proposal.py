@@ -110,9 +110,9 @@ def evaluate(net, images, yaw, xy, batch=256):
     return {k: v / n for k, v in hits.items()}
 
 
-def train(images, yaw, xy, epochs=40, batch=128, lr=2e-3, weight_decay=1e-4, seed=0, val=None, log=print):
+def train(images, yaw, xy, epochs=40, batch=128, lr=2e-3, weight_decay=1e-4, seed=0, val=None, init=None, log=print):
     rng = np.random.default_rng(seed)
-    net = proposal.Net(max_batch=max(batch, 256), params=he_init(seed))
+    net = proposal.Net(max_batch=max(batch, 256), params=he_init(seed) if init is None else init)
     n = len(images)
     steps = 0
     total_steps = max(1, epochs * (n // batch))
@@ -151,6 +151,8 @@ def main():
     ap.add_argument("--data", default=None,
                     help="comma-separated cached pair files (.npz) to train on instead of generating pairs")
     ap.add_argument("--data-out", default=None, help="write the generated pairs here (.npz)")
+    ap.add_argument("--init", default=None, help="start from these parameters (.npz) instead of He-normal weights")
+    ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--val-maps", type=int, default=5,
                     help="the last N training cities of the data are held out for validation")
     args = ap.parse_args()
@@ -185,12 +187,13 @@ def main():
     val = (images[is_val], yaw[is_val], xy[is_val]) if is_val.any() else None
     print(f"[train] {int((~is_val).sum())} training pairs, {int(is_val.sum())} held-out pairs "
           f"(cities {held.tolist()})", flush=True)
-    params, val_metrics = train(images[~is_val], yaw[~is_val], xy[~is_val], epochs=args.epochs, val=val,
-                                log=lambda m: print(m, flush=True))
+    init = np.load(args.init)["params"] if args.init else None
+    params, val_metrics = train(images[~is_val], yaw[~is_val], xy[~is_val], epochs=args.epochs, lr=args.lr, val=val,
+                                init=init, log=lambda m: print(m, flush=True))
     np.savez_compressed(args.out, params=params,
                         info=json.dumps({"pairs": int((~is_val).sum()), "held_out_pairs": int(is_val.sum()),
                                          "held_out_cities": held.tolist(), "epochs": args.epochs,
-                                         "held_out_metrics": val_metrics,
+                                         "held_out_metrics": val_metrics, "init": bool(args.init),
                                          "data": args.data or f"cities {args.map_start}..{args.map_start + args.maps - 1}"}))
     print(f"[train] wrote {args.out} after {time.time() - t0:.1f} s", flush=True)
 
