@@ -143,17 +143,18 @@ __device__ inline uint32_t find_or_insert(Slot *table, uint32_t cap_mask, int32_
     return 0xFFFFFFFFu;
 }
 
-// OR every voxel of D_level into each brick that covers it.  A voxel v lies in
-// brick floor(v / 4) and, on each axis where v is a multiple of 4, also in the
-// brick below (as its fifth layer).
-__global__ void k_insert_bricks(const unsigned long long *uniq, int64_t n_uniq, int level, int dilate, Slot *table,
+// OR every voxel of D_level into each brick that covers it.  `occ` holds the
+// distinct occupied voxels of the level (Occ_level); each marks itself and,
+// with dilation, its neighbours v - j, j in {0,1}^3.  A voxel v lies in brick
+// floor(v / 4) and, on each axis where v is a multiple of 4, also in the brick
+// below (as its fifth layer).
+__global__ void k_insert_bricks(const unsigned long long *occ, int64_t n_occ, int dilate, Slot *table,
                                 uint32_t cap_mask, unsigned long long *n_bricks, int *err)
 {
     const int jmax = dilate ? 1 : 0;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_uniq; i += (int64_t)gridDim.x * blockDim.x) {
-        int32_t v0[3];
-        unpack_voxel(uniq[i], v0[0], v0[1], v0[2]);
-        int32_t w[3] = {v0[0] >> level, v0[1] >> level, v0[2] >> level};
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_occ; i += (int64_t)gridDim.x * blockDim.x) {
+        int32_t w[3];
+        unpack_voxel(occ[i], w[0], w[1], w[2]);
         for (int jx = 0; jx <= jmax; ++jx)
             for (int jy = 0; jy <= jmax; ++jy)
                 for (int jz = 0; jz <= jmax; ++jz) {
@@ -179,6 +180,16 @@ __global__ void k_insert_bricks(const unsigned long long *uniq, int64_t n_uniq, 
                                 atomicOr(&words[bit >> 5], 1u << (bit & 31));
                             }
                 }
+    }
+}
+
+// Occupied voxels one level up: floor(v / 2) of every voxel (its parent).
+__global__ void k_parent_keys(const unsigned long long *occ, int64_t n, unsigned long long *out)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        int32_t x, y, z;
+        unpack_voxel(occ[i], x, y, z);
+        out[i] = pack_voxel(x >> 1, y >> 1, z >> 1);
     }
 }
 
@@ -485,8 +496,6 @@ extern "C" bbs_status bbs_build_map(const float *xyz, int64_t n, int32_t xyz_on_
         return fail(BBS_ERR_INVALID_ARG,
                     "bbs_build_map: a map point is not finite or its voxel is outside [-2^20 + 2, 2^20 - 2)");
     if (err) return fail(BBS_ERR_INTERNAL, "bbs_build_map: voxel set overflow");
-    dkeys.reset();
-    dset.reset();
     dxyz.reset();
 
     bbs_map *m = new bbs_map();
@@ -496,9 +505,39 @@ extern "C" bbs_status bbs_build_map(const float *xyz, int64_t n, int32_t xyz_on_
     (void)hipGetDevice(&m->device);
     const uint4 home = home_mask();
 
-    uint64_t tmp_cap = next_pow2(std::max<uint64_t>(1024, 4 * n_uniq));
+    // Occ_0 is in duniq; Occ_{l+1} = distinct parents of Occ_l (floor division
+    // nests), so every level inserts only its own distinct voxels
+    DevBuf docc2;
+    if (alloc_dev(&docc2.p, (size_t)n_uniq * 8)) {
+        bbs_free_map(m);
+        return BBS_ERR_OOM;
+    }
+    unsigned long long *occ = duniq.as<unsigned long long>(), *occ_next = docc2.as<unsigned long long>();
+    int64_t n_occ = (int64_t)n_uniq;
     for (int l = 0; l <= levels; ++l) {
+        if (l > 0) {
+            // occ_next = distinct parents of occ
+            k_parent_keys<<<grid_for(n_occ), kThreads, 0, s>>>(occ, n_occ, dkeys.as<unsigned long long>());
+            const uint64_t pcap = next_pow2((uint64_t)n_occ * 2);
+            k_fill_u64<<<grid_for((int64_t)pcap), kThreads, 0, s>>>(dset.as<unsigned long long>(), pcap, kEmpty64);
+            BBS_HIP(hipMemsetAsync(dcount.p, 0, 64, s));
+            k_dedupe<<<grid_for(n_occ), kThreads, 0, s>>>(dkeys.as<unsigned long long>(), n_occ,
+                                                           dset.as<unsigned long long>(), pcap - 1, occ_next,
+                                                           dcount.as<unsigned long long>(), derr.as<int>());
+            BBS_HIP(hipGetLastError());
+            unsigned long long n_next = 0;
+            BBS_HIP(hipMemcpyAsync(&n_next, dcount.p, 8, hipMemcpyDeviceToHost, s));
+            BBS_HIP(hipMemcpyAsync(&err, derr.p, 4, hipMemcpyDeviceToHost, s));
+            BBS_HIP(hipStreamSynchronize(s));
+            if (err) {
+                bbs_free_map(m);
+                return fail(BBS_ERR_INTERNAL, "bbs_build_map: voxel set overflow");
+            }
+            std::swap(occ, occ_next);
+            n_occ = (int64_t)n_next;
+        }
         int dilate = (l > 0 || dilate_leaf) ? 1 : 0;
+        uint64_t tmp_cap = next_pow2(std::max<uint64_t>(1024, 4 * (uint64_t)n_occ));
         for (;;) {
             DevBuf tmp;
             if (alloc_dev(&tmp.p, tmp_cap * sizeof(Slot))) {
@@ -508,9 +547,9 @@ extern "C" bbs_status bbs_build_map(const float *xyz, int64_t n, int32_t xyz_on_
             BBS_HIP(hipMemsetAsync(dcount.p, 0, 64, s));
             BBS_HIP(hipMemsetAsync(derr.p, 0, 64, s));
             k_fill_slots<<<grid_for((int64_t)tmp_cap), kThreads, 0, s>>>(tmp.as<Slot>(), tmp_cap);
-            k_insert_bricks<<<grid_for((int64_t)n_uniq), kThreads, 0, s>>>(
-                duniq.as<unsigned long long>(), (int64_t)n_uniq, l, dilate, tmp.as<Slot>(), (uint32_t)(tmp_cap - 1),
-                dcount.as<unsigned long long>(), derr.as<int>());
+            k_insert_bricks<<<grid_for(n_occ), kThreads, 0, s>>>(occ, n_occ, dilate, tmp.as<Slot>(),
+                                                                  (uint32_t)(tmp_cap - 1),
+                                                                  dcount.as<unsigned long long>(), derr.as<int>());
             BBS_HIP(hipGetLastError());
             unsigned long long nb = 0;
             BBS_HIP(hipMemcpyAsync(&nb, dcount.p, 8, hipMemcpyDeviceToHost, s));
