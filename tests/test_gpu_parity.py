@@ -285,6 +285,67 @@ def test_localize_errors(room):
     assert r["found"] == 0 and r["nodes_expanded"] == 0
 
 
+def test_localize_empty_inputs_are_errors(room):
+    say("empty inputs")
+    scene, g, _ = room
+    lo, hi = synth.search_range_room()
+    with pytest.raises(bbs.BbsError) as e:
+        bbs.localize(g, np.zeros((0, 3), np.float32), lo, hi, 0)
+    assert e.value.status == -1
+    with pytest.raises(bbs.BbsError) as e:
+        bbs.Map(np.zeros((0, 3), np.float32), 0.5, 2)
+    assert e.value.status == -1
+
+
+def test_localize_scan_off_the_map(room):
+    """Every point misses the map: all scores are 0, nothing reaches T = 1."""
+    say("scan off the map")
+    scene, g, o = room
+    sc = synth.scan_scene(scene, 3, 800, z=1.5, rp_deg=2.0)
+    far = sc.points + np.array([5000.0, 0.0, 0.0], np.float32)
+    lo, hi = synth.search_range_room()
+    want = oracle.Search(o, far, lo, hi).localize(1, batch=1000, threads=8)
+    got = bbs.localize(g, far, lo, hi, 1, batch_size=1000)
+    compare(got, want)
+    assert got["found"] == 0 and got["nodes_expanded"] == 0
+
+
+def test_localize_single_cell_fixed_angles(room):
+    """One translation leaf and fixed angles: the search scores one leaf."""
+    say("single cell")
+    scene, g, o = room
+    sc = synth.scan_scene(scene, 9, 1000, z=1.5, rp_deg=0.0)
+    p = sc.pose
+    cell = np.floor(p[:3] / 0.5) * 0.5
+    lo = np.array([cell[0], cell[1], cell[2], 0, 0, p[5]], np.float32)
+    hi = np.array([cell[0], cell[1], cell[2], 0, 0, p[5]], np.float32)
+    for T in (0, 500, 1001):
+        want = oracle.Search(o, sc.points, lo, hi).localize(T, batch=100, threads=4)
+        got = bbs.localize(g, sc.points, lo, hi, T, batch_size=100)
+        compare(got, want)
+    assert want["nodes_scored"] == want["initial_size"]
+
+
+@pytest.mark.parametrize("batch", [3000, 64000])
+def test_localize_ragged_range_negative_yaw(room, batch):
+    """Translation bounds off the voxel grid and a yaw range starting below
+    zero (the prior's yaw bins wrap), with and without a prior."""
+    say("ragged range, batch", batch)
+    scene, g, o = room
+    sc = synth.scan_scene(scene, 12, 1500, z=1.5, z_jitter=0.25, rp_deg=2.0)
+    lo = np.array([-9.73, -8.11, 1.07, -0.03, -0.03, -1.3], np.float32)
+    hi = np.array([8.41, 9.37, 1.93, 0.03, 0.03, 4.1], np.float32)
+    T = int(0.9 * 1500)
+    want = oracle.Search(o, sc.points, lo, hi).localize(T, batch=batch, threads=8)
+    compare(bbs.localize(g, sc.points, lo, hi, T, batch_size=batch), want)
+    prior = np.random.default_rng(12).normal(size=1088).astype(np.float32)
+    got = bbs.localize(g, sc.points, lo, hi, T, batch_size=batch, prior=prior, seed_beam=8)
+    want = oracle.Search(o, sc.points, lo, hi).localize(T, batch=batch, threads=8, prior=prior,
+                                                        seed_beam=got["seed_beam_used"])
+    compare(got, want)
+    assert (got["seeded"], got["seed_score"]) == (want["seeded"], want["seed_score"])
+
+
 @pytest.mark.parametrize("translation_only", [False, True])
 @pytest.mark.parametrize("beam", [0, 3, 16, 1000])
 def test_localize_with_prior_equals_oracle(room, translation_only, beam):
@@ -370,6 +431,18 @@ def test_city_map_and_sampled_scores(city):
     lo, hi = synth.search_range_city()
     s = oracle.Search(o, sc.points, lo, hi)
     nodes = random_nodes(s, np.random.default_rng(1), 1500, 6)
+    np.testing.assert_array_equal(bbs.score_nodes(g, sc.points, lo, hi, nodes), s.score_nodes(nodes, threads=16))
+
+
+def test_city_scores_largest_scan(city):
+    """Sampled node scores at the largest scan size of the stream workload
+    (30,000 points) on the full city map."""
+    say("city scores K = 30000")
+    c, g, o = city
+    sc = synth.scan_scene(c, 77, 30000, z=1.8, rp_deg=3.0, n_beams=64, n_az=2048, voxel=0.25)
+    lo, hi = synth.search_range_city()
+    s = oracle.Search(o, sc.points, lo, hi)
+    nodes = random_nodes(s, np.random.default_rng(30), 600, 6)
     np.testing.assert_array_equal(bbs.score_nodes(g, sc.points, lo, hi, nodes), s.score_nodes(nodes, threads=16))
 
 
