@@ -358,7 +358,8 @@ __device__ inline int bucket_of(int score, int level, const SearchConst &C)
 // whole workgroup of NT >= 256 threads; thread s < 256 handles slot s.
 template <int NT>
 __device__ void tile_pass(int t, const uint4 *groups, int32_t *scores, State *st, const SearchConst &C,
-                          int n_groups, int32_t *q_arr, int32_t *rank_arr, int32_t *hist, int *sq, int *sm)
+                          int n_groups, int32_t *q_arr, int32_t *rank_arr, int32_t *hist, uint32_t *qmask, int *sq,
+                          int *sm)
 {
     const int s = threadIdx.x;
     const bool slot = s < kTileSlots;
@@ -387,7 +388,10 @@ __device__ void tile_pass(int t, const uint4 *groups, int32_t *scores, State *st
         q_arr[(int64_t)t * kTileSlots + s] = q;
         rank_arr[(int64_t)t * kTileSlots + s] = rank;
     }
-    if (q >= 0 && rank == 0) hist[(int64_t)t * C.q_count + q] = cnt;
+    if (q >= 0 && rank == 0) {
+        hist[(int64_t)t * C.q_count + q] = cnt;
+        atomicOr(&qmask[q >> 5], 1u << (q & 31));
+    }
     const int qmn = block_min_int<NT>(q >= 0 ? q : INT_MAX, sm);
     const int qmx = -block_min_int<NT>(q >= 0 ? -q : INT_MAX, sm);
     int tot;
@@ -415,6 +419,7 @@ struct ScoreArgs {
     int32_t *scores;
     int32_t *tile_done;        // NULL: no tile pass
     int32_t *q_arr, *rank_arr, *hist;
+    uint32_t *qmask;           // bit q: some tile of the batch holds a child of bucket q
 };
 
 template <bool POW2, int NT>
@@ -644,7 +649,7 @@ __device__ void score_items(State *st, const ScoreArgs &A, const MapView &map, c
         __syncthreads();
         if (sh.s_last) {
             __threadfence();
-            tile_pass<NT>(t, groups, scores, st, C, n_groups, A.q_arr, A.rank_arr, A.hist, sh.sq, sh.sm);
+            tile_pass<NT>(t, groups, scores, st, C, n_groups, A.q_arr, A.rank_arr, A.hist, A.qmask, sh.sq, sh.sm);
             if (threadIdx.x == 0) __hip_atomic_store(&tile_done[t], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         __syncthreads();
@@ -716,6 +721,8 @@ __device__ inline void bucket_space(const Bucket &b, int cnt, int &T, int &f, in
 struct PushBufs {
     int32_t *q_arr, *rank_arr, *hist, *totals, *pT, *pf, *pc0, *chunk_next;
     uint4 *arena;
+    uint32_t *qmask;           // occupied buckets of the batch (set by the tile passes, cleared here)
+    int32_t *qlist;            // the occupied buckets in order
 };
 
 // Second half of the stable counting sort, run by the serial workgroup after
@@ -731,12 +738,32 @@ __device__ void push_finish(State *st, const SearchConst &C, Bucket *bk, const u
     const int64_t kept = st->kept;
     const int n_tiles = (st->n_groups + kTileGroups - 1) / kTileGroups;
     if (q_max < q_min || kept == 0) return;
-    const int nq = q_max - q_min + 1;
     const uint64_t tp0 = __builtin_amdgcn_s_memrealtime();
-    // per-bucket prefix over tiles (tile-major histogram: the lanes of a wave
-    // read consecutive buckets of one tile; loads in blocks of 16 tiles)
-    for (int qi = tid; qi < nq; qi += NT) {
-        const int q = q_min + qi;
+    // the occupied buckets in order (bitmap words of [q_min, q_max], read and cleared)
+    const int w0 = q_min >> 5, nw = (q_max >> 5) - w0 + 1;
+    int n_occ = 0;
+    for (int c = 0; c < nw; c += NT) {
+        const int wi = c + tid;
+        uint32_t m = 0;
+        if (wi < nw) {
+            m = B.qmask[w0 + wi];
+            if (m) B.qmask[w0 + wi] = 0u;
+        }
+        const int pc = __popc(m);
+        int tot;
+        const int incl = block_scan_incl<NT>(pc, sm, &tot);
+        int pos = n_occ + incl - pc;
+        while (m) {
+            const int bit = __ffs(m) - 1;
+            m &= m - 1u;
+            B.qlist[pos++] = (w0 + wi) * 32 + bit;
+        }
+        n_occ += tot;
+    }
+    __syncthreads();
+    // per-bucket prefix over tiles (tile-major histogram; loads in blocks of 16 tiles)
+    for (int i = tid; i < n_occ; i += NT) {
+        const int q = B.qlist[i];
         int acc = 0;
         for (int t0 = 0; t0 < n_tiles; t0 += 16) {
             int v[16];
@@ -749,18 +776,18 @@ __device__ void push_finish(State *st, const SearchConst &C, Bucket *bk, const u
                     acc += v[u];
                 }
         }
-        B.totals[qi] = acc;
+        B.totals[i] = acc;
     }
     __syncthreads();
     const uint64_t tp1 = __builtin_amdgcn_s_memrealtime();
     // chunks needed, then allocation in bucket order
     int64_t total_new = 0;
-    for (int c = 0; c < nq; c += NT) {
+    for (int c = 0; c < n_occ; c += NT) {
         const int i = c + tid;
         int nch = 0;
-        if (i < nq && B.totals[i] > 0) {
+        if (i < n_occ) {
             int T, f, space;
-            bucket_space(bk[q_min + i], B.totals[i], T, f, space, nch);
+            bucket_space(bk[B.qlist[i]], B.totals[i], T, f, space, nch);
         }
         int tot;
         (void)block_scan_incl<NT>(nch, sm, &tot);
@@ -776,10 +803,10 @@ __device__ void push_finish(State *st, const SearchConst &C, Bucket *bk, const u
         return;
     }
     int64_t run = 0;
-    for (int c = 0; c < nq; c += NT) {
+    for (int c = 0; c < n_occ; c += NT) {
         const int i = c + tid;
-        const int q = q_min + i;
-        const int cnt = i < nq ? B.totals[i] : 0;
+        const int q = i < n_occ ? B.qlist[i] : 0;
+        const int cnt = i < n_occ ? B.totals[i] : 0;
         int T = -1, f = kChunk, space = 0, nch = 0;
         Bucket b = Bucket{-1, 0, -1, 0};
         if (cnt > 0) {
@@ -789,10 +816,11 @@ __device__ void push_finish(State *st, const SearchConst &C, Bucket *bk, const u
         int tot;
         const int incl = block_scan_incl<NT>(nch, sm, &tot);
         if (cnt > 0) {
+            const int qi = q - q_min;
             const int c0 = chunk_top + (int)run + incl - nch;
-            B.pT[i] = T;
-            B.pf[i] = f;
-            B.pc0[i] = c0;
+            B.pT[qi] = T;
+            B.pf[qi] = f;
+            B.pc0[qi] = c0;
             if (nch > 0) {
                 if (T >= 0) B.chunk_next[T] = c0;
                 else {
@@ -1434,6 +1462,10 @@ struct bbs_workspace {
     int64_t buckets_n = 0;
     int32_t *hist = nullptr;
     int64_t hist_n = 0;
+    uint32_t *qmask = nullptr;
+    int64_t qmask_n = 0;
+    int32_t *qlist = nullptr;
+    int64_t qlist_n = 0;
     int32_t *totals = nullptr;
     int64_t totals_n = 0;
     int32_t *pT = nullptr, *pf = nullptr, *pc0 = nullptr;
@@ -1484,7 +1516,7 @@ void free_ws(bbs_workspace *w)
 {
     void *ptrs[] = {w->arena, w->chunk_next, w->buckets, w->hist, w->totals, w->pT, w->pf, w->pc0, w->groups, w->scores,
                     w->q_arr, w->rank_arr, w->tile_done, w->scan, w->scan_aos, w->scan_tmp, w->mkeys, w->mhist,
-                    w->trig, w->state, w->maxsq, w->beam, w->prior, w->dstate, w->bar};
+                    w->trig, w->state, w->maxsq, w->beam, w->prior, w->dstate, w->bar, w->qmask, w->qlist};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (w->host_state) (void)hipHostFree(w->host_state);
@@ -1650,6 +1682,7 @@ ScoreArgs score_args(const Setup &S, bbs_workspace *ws, int32_t n_fixed, bool ti
     A.q_arr = ws->q_arr;
     A.rank_arr = ws->rank_arr;
     A.hist = ws->hist;
+    A.qmask = ws->qmask;
     return A;
 }
 
@@ -1843,7 +1876,12 @@ extern "C" bbs_status bbs_localize(const bbs_map *map, bbs_workspace *ws, const 
         if (ensure(ws->hist, ws->hist_n, n_tiles * qn)) return BBS_ERR_OOM;
         ws->hist_dirty = true;
     }
+    if (!ws->qmask || ws->qmask_n < qn / 32 + 1) {
+        if (ensure(ws->qmask, ws->qmask_n, qn / 32 + 1) || ensure(ws->qlist, ws->qlist_n, qn)) return BBS_ERR_OOM;
+        ws->hist_dirty = true;
+    }
     if (ws->hist_dirty) {
+        BBS_HIP(hipMemsetAsync(ws->qmask, 0, (size_t)ws->qmask_n * 4, s));
         BBS_HIP(hipMemsetAsync(ws->hist, 0, (size_t)ws->hist_n * 4, s));
         BBS_HIP(hipMemsetAsync(ws->tile_done, 0, (size_t)ws->tile_done_n * 4, s));
         ws->hist_dirty = false;
@@ -1875,6 +1913,8 @@ extern "C" bbs_status bbs_localize(const bbs_map *map, bbs_workspace *ws, const 
     B.q_arr = ws->q_arr;
     B.rank_arr = ws->rank_arr;
     B.hist = ws->hist;
+    B.qmask = ws->qmask;
+    B.qlist = ws->qlist;
     B.totals = ws->totals;
     B.pT = ws->pT;
     B.pf = ws->pf;
