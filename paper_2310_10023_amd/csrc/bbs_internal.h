@@ -136,6 +136,7 @@ struct SearchConst {
     int32_t thi[3][kMaxLevels];
     int32_t trig_off[3][kMaxLevels]; // offset of (axis, level) in the cos/sin table
     int32_t q_count;               // number of queue buckets
+    int32_t max_children;          // most children of one node on this grid
     int32_t threshold;             // initial best score (clamped to [0, K + 1])
     int64_t batch;                 // b
     float r;

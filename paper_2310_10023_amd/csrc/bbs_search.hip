@@ -958,6 +958,7 @@ struct GatherSmem {
     int pre[NT];              // window: inclusive prefix of segment lengths
     int s_last[2];
     int s_end;
+    int s_cut;
 };
 
 __device__ inline int seg_len(const Bucket &b)
@@ -1083,11 +1084,26 @@ __device__ void gather(State *st, Bucket *bk, const int32_t *chunk_next, const u
                     node_unpack(arena[(int64_t)bj.head_chunk * kChunk + bj.head_off + (tid - base)], t3, ang, lv);
                     child_counts(C, t3, ang, level, rc, tmask, nn, ng);
                 }
-                int tot_n, tot_g;
-                const int incl_n = block_scan_incl<NT>(nn, sh.sm, &tot_n);
-                const int incl_g = block_scan_incl<NT>(ng, sh.sm, &tot_g);
-                const int over = (valid && pend + incl_n > C.batch) ? tid : INT_MAX;
-                const int cutidx = block_min_int<NT>(over, sh.sm);
+                int incl_n, incl_g;
+                if (C.max_children <= 64) {
+                    // one scan of (children, groups) packed as nn | ng << 17: a
+                    // window holds at most NT * 64 = 2^16 children, NT * 8 groups
+                    int tot_p;
+                    const int incl_p = block_scan_incl<NT>(nn | (ng << 17), sh.sm, &tot_p);
+                    incl_n = incl_p & 0x1FFFF;
+                    incl_g = incl_p >> 17;
+                } else {
+                    int tot_n, tot_g;
+                    incl_n = block_scan_incl<NT>(nn, sh.sm, &tot_n);
+                    incl_g = block_scan_incl<NT>(ng, sh.sm, &tot_g);
+                }
+                // pend <= b here, and the running count passes b at exactly one
+                // node of the window, if any
+                if (tid == 0) sh.s_cut = INT_MAX;
+                __syncthreads();
+                if (valid && pend + incl_n > C.batch && pend + incl_n - nn <= C.batch) sh.s_cut = tid;
+                __syncthreads();
+                const int cutidx = sh.s_cut;
                 const int consumed = cutidx != INT_MAX ? cutidx + 1 : W;
                 if (tid < consumed && ng > 0) {
                     int gi = ngrp + incl_g - ng;
@@ -1856,6 +1872,7 @@ extern "C" bbs_status bbs_localize(const bbs_map *map, bbs_workspace *ws, const 
         init_nodes = cnt[0] * cnt[1] * cnt[2] * n_rot_top;
     }
     const int64_t mc = max_children(g);
+    S.C.max_children = (int32_t)std::min<int64_t>(mc, INT32_MAX);
     const int64_t cap_groups = std::max<int64_t>(o.batch_size + mc, 4096);
     const int64_t n_tiles = (cap_groups + kTileGroups - 1) / kTileGroups;
     const int64_t qn = std::max<int32_t>(C.q_count, 1);
