@@ -370,7 +370,12 @@ __device__ void tile_pass(int t, const uint4 *groups, int32_t *scores, State *st
         const uint4 G = groups[g];
         const uint32_t mask = (G.w >> 8) & 0xFF;
         if ((mask >> j) & 1u) {
-            const int sc = __hip_atomic_load(&scores[8 * (int64_t)g + j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            // read with an atomic at the adds' coherence point (see the scoring
+            // hand-off); the zero is opaque so the add is not turned into a load
+            int zero;
+            asm volatile("v_mov_b32 %0, 0" : "=v"(zero));
+            const int sc = __hip_atomic_fetch_add(&scores[8 * (int64_t)g + j], zero, __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
             if (sc >= best) q = bucket_of(sc, (int)(G.w & 0xFF), C);
         }
     }
@@ -631,11 +636,18 @@ __device__ void score_items(State *st, const ScoreArgs &A, const MapView &map, c
         if (lane == 0)
             for (int j = 0; j < 8; ++j) red[wave][j] = c[j];
         __syncthreads();
+        // Hand-off to the tile pass without a device-scope fence (which on this
+        // GPU writes back and invalidates the XCD's L2): the scores are added
+        // with returning atomics, which have been performed once the barrier's
+        // wait for outstanding memory operations is over; only then is the
+        // tile counter bumped, and the tile pass reads the scores with atomics
+        // too, at the same coherence point.
         if (threadIdx.x < 8) {
             int sum = 0;
             for (int wv = 0; wv < NT / 64; ++wv) sum += red[wv][threadIdx.x];
-            atomicAdd(&scores[8 * (int64_t)g + threadIdx.x], sum);
-            __threadfence();
+            const int old = __hip_atomic_fetch_add(&scores[8 * (int64_t)g + threadIdx.x], sum, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+            asm volatile("" ::"v"(old));          // keep the returning form of the atomic
         }
         __syncthreads();
         if (!tile_done) continue;
@@ -648,7 +660,6 @@ __device__ void score_items(State *st, const ScoreArgs &A, const MapView &map, c
         }
         __syncthreads();
         if (sh.s_last) {
-            __threadfence();
             tile_pass<NT>(t, groups, scores, st, C, n_groups, A.q_arr, A.rank_arr, A.hist, A.qmask, sh.sq, sh.sm);
             if (threadIdx.x == 0) __hip_atomic_store(&tile_done[t], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
