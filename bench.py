@@ -28,6 +28,12 @@ if ROOT not in sys.path:
 
 METRIC = "nodes scored/s and ms per localization, plain vs learned-order BnB, 1 GPU"
 HBM_PEAK_GBS = 8000.0
+# 32-bit VALU lane-operations per second: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+# (the 157.3 TFLOP/s fp32 vector figure counts a packed FMA as 4 flops per lane-op)
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# ALU work per (node, scan point): 15 fp32 ops of the 3x3 transform and 3 floors,
+# shared by the 8 translational siblings of a rotation, plus ~10 integer ops
+OPS_PER_NODE_POINT = 18 / 8 + 10
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_score_city_traffic.md")
 WEIGHTS = os.path.join(ROOT, "paper_2310_10023_amd", "proposal_weights.npz")
 SCORE_SRC = os.path.join(ROOT, "paper_2310_10023_amd", "csrc", "bbs_search.hip")
@@ -157,11 +163,15 @@ def main():
     groups = sum(r["score_groups"] for r in results)
     launches = sum(r["score_launches"] for r in results)
     kern_ms = sum(r["score_kernel_ms"] for r in results)
-    # algorithmic bytes of the scoring kernel: one 8-byte hash key per
-    # node-point membership test, and the 12-byte scan point once per group
-    # of siblings sharing a rotation
+    # algorithmic work of the scoring kernel per launch: ALU ops per node-point
+    # (its bound: VALU issue), and for reference the memory a one-key-per-voxel
+    # table would read (one 8-byte key per node-point test, the 12-byte scan
+    # point once per group of siblings sharing a rotation)
+    pairs = nodes * args.k
+    alg_ops = pairs * OPS_PER_NODE_POINT
+    achieved = alg_ops / (kern_ms * 1e-3) / 1e12 if kern_ms > 0 else 0.0
     alg_bytes = nodes * args.k * 8 + groups * args.k * 12
-    achieved = alg_bytes / (kern_ms * 1e-3) / 1e9 if kern_ms > 0 else 0.0
+    hbm_alg_gbs = alg_bytes / (kern_ms * 1e-3) / 1e9 if kern_ms > 0 else 0.0
     traffic = measured_traffic()
     lat = sorted(r["phase_ms"][3] for r in results)
     found = sum(r["found"] for r in results)
@@ -202,16 +212,21 @@ def main():
             "iterations_mean": launches / len(seeds),
         },
         "roofline": {
-            "bound": "hbm",
+            "bound": "alu",
             "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
+            "peak": VALU_PEAK_TOPS,
+            "unit": "Tops/s (32-bit VALU lane-operations)",
+            "frac": achieved / VALU_PEAK_TOPS,
             "traffic": traffic,
             "traffic_unit": "HBM bytes per launch (FETCH_SIZE x2.0 + WRITE_SIZE x1.0, copy-calibrated)",
             "kernel": "k_score",
             "launches": launches,
             "avg_launch_us": kern_ms / max(launches, 1) * 1e3,
+            "alg_ops_per_launch": alg_ops / max(launches, 1),
+            "ops_per_node_point": OPS_PER_NODE_POINT,
+            "lookups_per_s": groups * args.k / (kern_ms * 1e-3) if kern_ms > 0 else 0.0,
+            "hbm_algorithmic_gbs": hbm_alg_gbs,
+            "hbm_algorithmic_frac": hbm_alg_gbs / HBM_PEAK_GBS,
             "alg_bytes_per_launch": alg_bytes / max(launches, 1),
         },
         "cpu_baseline": None,
