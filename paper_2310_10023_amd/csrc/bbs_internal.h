@@ -38,11 +38,10 @@ struct alignas(32) Slot {
 // small and cache resident; a mask is read only when its key matches.
 //
 // Where the level's brick bounding box is small enough (at most a few times
-// the hash capacity), the masks are also laid out as a dense grid over that
-// box, which the scoring kernel reads instead: one load per lookup, no key
-// compare and no probe chain.  The grid is stored in 2 x 2 x 2 blocks of
-// bricks (x fastest inside a block, blocks x fastest), so one 128-byte line
-// holds a cube of eight neighbouring bricks; absent bricks hold zero masks.
+// the hash capacity, at most 4096 bricks per axis), the masks are also laid
+// out as a dense row-major grid over that box (x fastest), which the scoring
+// kernel reads instead: one load per lookup, no key compare and no probe
+// chain; absent bricks hold zero masks.
 struct LevelView {
     const uint2 *keys;   // (key lo, key hi); empty = all ones
     const uint4 *bits;   // occupancy of the brick in the same slot
@@ -50,15 +49,14 @@ struct LevelView {
     uint32_t cap_mask;   // capacity - 1 (power of two)
     int32_t bmin[3];     // brick-coordinate bounding box of the level
     int32_t bmax[3];
-    int32_t nbx, nby;    // dense grid: 2 x 2 x 2 blocks along x and y
+    int32_t nx, ny;      // dense grid: bricks along x and y
 };
 
 // Index of brick (rx, ry, rz) (relative to the bounding box minimum) in the
 // dense grid.
-__host__ __device__ inline uint32_t dense_index(uint32_t rx, uint32_t ry, uint32_t rz, int32_t nbx, int32_t nby)
+__host__ __device__ inline uint32_t dense_index(uint32_t rx, uint32_t ry, uint32_t rz, int32_t nx, int32_t ny)
 {
-    const uint32_t blk = ((rz >> 1) * (uint32_t)nby + (ry >> 1)) * (uint32_t)nbx + (rx >> 1);
-    return (blk << 3) | ((rz & 1u) << 2) | ((ry & 1u) << 1) | (rx & 1u);
+    return (rz * (uint32_t)ny + ry) * (uint32_t)nx + rx;
 }
 
 struct MapView {
@@ -169,7 +167,7 @@ struct bbs_map {
     uint4 *bits[bbs::kMaxLevels];
     uint4 *dense[bbs::kMaxLevels];        // dense mask grid of the level, or NULL (hash only)
     int64_t dense_n[bbs::kMaxLevels];     // its entries
-    int32_t nbx[bbs::kMaxLevels], nby[bbs::kMaxLevels];
+    int32_t nx[bbs::kMaxLevels], ny[bbs::kMaxLevels];
     uint64_t cap[bbs::kMaxLevels];
     int64_t bricks[bbs::kMaxLevels];
     int64_t voxels[bbs::kMaxLevels];

@@ -25,6 +25,7 @@ constexpr unsigned long long kEmpty64 = 0xFFFFFFFFFFFFFFFFull;
 constexpr int32_t kPackBias = 1 << 20;
 constexpr int64_t kDenseRatio = 4;              // dense grid only if its entries <= 4 x the hash capacity
 constexpr int64_t kDenseMax = (int64_t)1 << 27; // and at most 2^27 entries (2 GiB)
+constexpr int64_t kDenseAxis = 4096;            // and at most 4096 bricks per axis (24-bit index products)
 
 inline int grid_for(int64_t n, int threads = kThreads, int cap = 8192)
 {
@@ -258,7 +259,7 @@ __global__ void k_compact(const Slot *src, uint64_t src_n, uint2 *dkeys, uint4 *
 
 // Copy every brick of a finished level into its dense grid (zeroed before).
 __global__ void k_fill_dense(const uint2 *keys, const uint4 *bits, uint64_t cap, uint4 *dense, int32_t bx0, int32_t by0,
-                             int32_t bz0, int32_t nbx, int32_t nby)
+                             int32_t bz0, int32_t nx, int32_t ny)
 {
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < cap; i += (uint64_t)gridDim.x * blockDim.x) {
         const uint2 kk = keys[i];
@@ -267,7 +268,7 @@ __global__ void k_fill_dense(const uint2 *keys, const uint4 *bits, uint64_t cap,
         const int32_t bx = (int32_t)((key >> 38) & 0x7FFFF) - kBrickBias;
         const int32_t by = (int32_t)((key >> 19) & 0x7FFFF) - kBrickBias;
         const int32_t bz = (int32_t)(key & 0x7FFFF) - kBrickBias;
-        dense[dense_index((uint32_t)(bx - bx0), (uint32_t)(by - by0), (uint32_t)(bz - bz0), nbx, nby)] = bits[i];
+        dense[dense_index((uint32_t)(bx - bx0), (uint32_t)(by - by0), (uint32_t)(bz - bz0), nx, ny)] = bits[i];
     }
 }
 
@@ -423,8 +424,8 @@ bbs::MapView bbs_map::view() const
         lv.keys = l <= levels ? keys[l] : nullptr;
         lv.bits = l <= levels ? bits[l] : nullptr;
         lv.dense = l <= levels ? dense[l] : nullptr;
-        lv.nbx = l <= levels ? nbx[l] : 0;
-        lv.nby = l <= levels ? nby[l] : 0;
+        lv.nx = l <= levels ? nx[l] : 0;
+        lv.ny = l <= levels ? ny[l] : 0;
         lv.cap_mask = l <= levels ? (uint32_t)(cap[l] - 1) : 0u;
         for (int a = 0; a < 3; ++a) {
             lv.bmin[a] = l <= levels ? bmin[l][a] : 1;
@@ -597,12 +598,13 @@ extern "C" bbs_status bbs_build_map(const float *xyz, int64_t n, int32_t xyz_on_
                 m->bmax[l][a] = bbox[3 + a];
             }
             m->voxels[l] = (int64_t)nv;
-            // dense mask grid when the bounding box (in 2x2x2 blocks) holds at
-            // most kDenseRatio x the hash capacity
-            const int64_t nb3[3] = {((int64_t)bbox[3] - bbox[0] + 2) / 2, ((int64_t)bbox[4] - bbox[1] + 2) / 2,
-                                    ((int64_t)bbox[5] - bbox[2] + 2) / 2};
-            const int64_t dn = 8 * nb3[0] * nb3[1] * nb3[2];
-            if (dn <= kDenseRatio * (int64_t)cap && dn <= kDenseMax) {
+            // dense mask grid when the bounding box holds at most kDenseRatio x
+            // the hash capacity in bricks and at most kDenseAxis bricks per axis
+            const int64_t n3[3] = {(int64_t)bbox[3] - bbox[0] + 1, (int64_t)bbox[4] - bbox[1] + 1,
+                                   (int64_t)bbox[5] - bbox[2] + 1};
+            const int64_t dn = n3[0] * n3[1] * n3[2];
+            const bool axes_ok = n3[0] <= kDenseAxis && n3[1] <= kDenseAxis && n3[2] <= kDenseAxis;
+            if (axes_ok && dn <= kDenseRatio * (int64_t)cap && dn <= kDenseMax) {
                 void *dd = nullptr;
                 if (alloc_dev(&dd, (size_t)dn * sizeof(uint4))) {
                     bbs_free_map(m);
@@ -610,11 +612,11 @@ extern "C" bbs_status bbs_build_map(const float *xyz, int64_t n, int32_t xyz_on_
                 }
                 m->dense[l] = static_cast<uint4 *>(dd);
                 m->dense_n[l] = dn;
-                m->nbx[l] = (int32_t)nb3[0];
-                m->nby[l] = (int32_t)nb3[1];
+                m->nx[l] = (int32_t)n3[0];
+                m->ny[l] = (int32_t)n3[1];
                 BBS_HIP(hipMemsetAsync(dd, 0, (size_t)dn * sizeof(uint4), s));
                 k_fill_dense<<<grid_for((int64_t)cap), kThreads, 0, s>>>(m->keys[l], m->bits[l], cap, m->dense[l],
-                                                                         bbox[0], bbox[1], bbox[2], m->nbx[l], m->nby[l]);
+                                                                         bbox[0], bbox[1], bbox[2], m->nx[l], m->ny[l]);
                 BBS_HIP(hipGetLastError());
                 BBS_HIP(hipStreamSynchronize(s));
             }

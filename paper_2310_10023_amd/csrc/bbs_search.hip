@@ -469,14 +469,30 @@ __device__ void score_items(State *st, const ScoreArgs &A, const MapView &map, c
             // Branch-free: clamped scan loads and every grid load of the
             // kUnroll points are issued before any result is used; a point
             // past the range or outside the box reads entry 0 and counts 0.
-            // The eight counts run as two SWAR words of four 8-bit lanes
-            // (members 0, 4, 2, 6 and 1, 5, 3, 7), folded into the int
-            // counters every kFold rounds, before a lane can overflow.
-            constexpr int kFold = 255 / kUnroll;
-            uint32_t acc_a = 0, acc_b = 0;
+            // u = voxel + (group base - 4 box minimum) per axis: u >> 2 is the
+            // brick relative to the box (negative u fails the unsigned box
+            // test), u & 3 the voxel inside it.  The eight counts are
+            // bit-sliced into two 64-bit words, members 0..3 of the window
+            // bits 0, 5, 25, 30 and members 4..7 of bits 1, 6, 26, 31, in
+            // fields of at least 5 bits, folded every kFold rounds.
+            constexpr int kFold = 31 / kUnroll;
+            constexpr uint32_t kSlice = 0x42000021u;           // window bits 0, 5, 25, 30
+            uint64_t acc_a = 0, acc_b = 0;
             int rounds = 0;
             const uint4 *__restrict__ dense = lv.dense;
-            const int32_t nbx = lv.nbx, nby = lv.nby;
+            const uint32_t nx = (uint32_t)lv.nx, ny = (uint32_t)lv.ny;
+            const int32_t ox = bx - 4 * lv.bmin[0], oy = by - 4 * lv.bmin[1], oz = bz - 4 * lv.bmin[2];
+            auto fold = [&]() {
+                c0 += (int)(acc_a & 31u);
+                c2 += (int)((acc_a >> 5) & 0xFFFFFu);
+                c1 += (int)((acc_a >> 25) & 31u);
+                c3 += (int)(acc_a >> 30);
+                c4 += (int)(acc_b & 31u);
+                c6 += (int)((acc_b >> 5) & 0xFFFFFu);
+                c5 += (int)((acc_b >> 25) & 31u);
+                c7 += (int)(acc_b >> 30);
+                acc_a = acc_b = 0;
+            };
             for (int kb = k_begin + (int)threadIdx.x; kb < k_end; kb += NT * kUnroll) {
                 float sx[kUnroll], sy[kUnroll], sz[kUnroll];
 #pragma unroll
@@ -491,7 +507,7 @@ __device__ void score_items(State *st, const ScoreArgs &A, const MapView &map, c
                 bool ok[kUnroll];
 #pragma unroll
                 for (int u = 0; u < kUnroll; ++u) {
-                    int32_t w[3];
+                    uint32_t v[3];
 #pragma unroll
                     for (int row = 0; row < 3; ++row) {
                         float t0 = R[3 * row + 0] * sx[u];
@@ -499,16 +515,18 @@ __device__ void score_items(State *st, const ScoreArgs &A, const MapView &map, c
                         float t2 = R[3 * row + 2] * sz[u];
                         float p = (t0 + t1) + t2;
                         float q = POW2 ? p * C.inv_r : p / C.r;
-                        w[row] = ((int32_t)floorf(q) >> level);
+                        // floor and convert in one instruction (equal to floorf then
+                        // conversion for the finite, in-range q here; denormals kept)
+                        int32_t fl;
+                        asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(fl) : "v"(q));
+                        v[row] = (uint32_t)((fl >> level) + (row == 0 ? ox : (row == 1 ? oy : oz)));
                     }
-                    const int32_t wx = w[0] + bx, wy = w[1] + by, wz = w[2] + bz;
-                    const uint32_t rx = (uint32_t)((wx >> 2) - lv.bmin[0]);
-                    const uint32_t ry = (uint32_t)((wy >> 2) - lv.bmin[1]);
-                    const uint32_t rz = (uint32_t)((wz >> 2) - lv.bmin[2]);
+                    const uint32_t rx = v[0] >> 2, ry = v[1] >> 2, rz = v[2] >> 2;
                     ok[u] = kb + u * NT < k_end && rx <= ex && ry <= ey && rz <= ez;
-                    const uint32_t blk = __umul24(__umul24(rz >> 1, (uint32_t)nby) + (ry >> 1), (uint32_t)nbx) + (rx >> 1);
-                    idx[u] = ok[u] ? ((blk << 3) | ((rz & 1u) << 2) | ((ry & 1u) << 1) | (rx & 1u)) : 0u;
-                    i0[u] = (uint32_t)(((wz & 3) * 5 + (wy & 3)) * 5 + (wx & 3));   // 0 .. 93
+                    // box dimensions <= 4096 and <= 2^27 entries: 24-bit products are exact
+                    const uint32_t id = __umul24(__umul24(rz, ny) + ry, nx) + rx;
+                    idx[u] = ok[u] ? id : 0u;
+                    i0[u] = ((v[2] & 3u) * 5u + (v[1] & 3u)) * 5u + (v[0] & 3u);   // 0 .. 93
                 }
                 uint4 bits[kUnroll];
 #pragma unroll
@@ -527,33 +545,15 @@ __device__ void score_items(State *st, const ScoreArgs &A, const MapView &map, c
                     uint32_t win = __builtin_amdgcn_alignbit(hi, lo, i0[u] & 31u);
                     win = ok[u] ? win : 0u;
                     // member j = 4 jx + 2 jy + jz sits at window bit 25 jz + 5 jy + jx
-                    const uint32_t qa = (win & 3u) | ((win >> 3) & 0xCu);           // members 0, 4, 2, 6
-                    const uint32_t qb = ((win >> 25) & 3u) | ((win >> 28) & 0xCu);  // members 1, 5, 3, 7
-                    // spread bit i of a 4-bit value to bit 8 i
-                    acc_a += __umul24(qa, 0x204081u) & 0x01010101u;
-                    acc_b += __umul24(qb, 0x204081u) & 0x01010101u;
+                    acc_a += (uint64_t)(win & kSlice);
+                    acc_b += (uint64_t)((win >> 1) & kSlice);
                 }
                 if (++rounds == kFold) {
-                    c0 += acc_a & 0xFF;
-                    c4 += (acc_a >> 8) & 0xFF;
-                    c2 += (acc_a >> 16) & 0xFF;
-                    c6 += acc_a >> 24;
-                    c1 += acc_b & 0xFF;
-                    c5 += (acc_b >> 8) & 0xFF;
-                    c3 += (acc_b >> 16) & 0xFF;
-                    c7 += acc_b >> 24;
-                    acc_a = acc_b = 0;
+                    fold();
                     rounds = 0;
                 }
             }
-            c0 += acc_a & 0xFF;
-            c4 += (acc_a >> 8) & 0xFF;
-            c2 += (acc_a >> 16) & 0xFF;
-            c6 += acc_a >> 24;
-            c1 += acc_b & 0xFF;
-            c5 += (acc_b >> 8) & 0xFF;
-            c3 += (acc_b >> 16) & 0xFF;
-            c7 += acc_b >> 24;
+            fold();
         } else {
             for (int kb = k_begin + (int)threadIdx.x; kb < k_end; kb += NT * kUnroll) {
                 uint32_t h[kUnroll], klo[kUnroll], khi[kUnroll];
