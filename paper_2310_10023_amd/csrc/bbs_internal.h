@@ -41,7 +41,10 @@ struct alignas(32) Slot {
 // the hash capacity, at most 4096 bricks per axis), the masks are also laid
 // out as a dense row-major grid over that box (x fastest), which the scoring
 // kernel reads instead: one load per lookup, no key compare and no probe
-// chain; absent bricks hold zero masks.
+// chain; absent bricks hold zero masks.  The grid has one more layer of
+// (empty) bricks past the box maximum on each axis: a lookup clamps each
+// brick coordinate into [0, extent + 1], so every point outside the box lands
+// on an empty brick without a bounds branch.
 struct LevelView {
     const uint2 *keys;   // (key lo, key hi); empty = all ones
     const uint4 *bits;   // occupancy of the brick in the same slot
@@ -49,7 +52,7 @@ struct LevelView {
     uint32_t cap_mask;   // capacity - 1 (power of two)
     int32_t bmin[3];     // brick-coordinate bounding box of the level
     int32_t bmax[3];
-    int32_t nx, ny;      // dense grid: bricks along x and y
+    int32_t nx, ny;      // dense grid: bricks along x and y (border layer included)
 };
 
 // Index of brick (rx, ry, rz) (relative to the bounding box minimum) in the

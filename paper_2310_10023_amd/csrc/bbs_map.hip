@@ -599,9 +599,11 @@ extern "C" bbs_status bbs_build_map(const float *xyz, int64_t n, int32_t xyz_on_
             }
             m->voxels[l] = (int64_t)nv;
             // dense mask grid when the bounding box holds at most kDenseRatio x
-            // the hash capacity in bricks and at most kDenseAxis bricks per axis
-            const int64_t n3[3] = {(int64_t)bbox[3] - bbox[0] + 1, (int64_t)bbox[4] - bbox[1] + 1,
-                                   (int64_t)bbox[5] - bbox[2] + 1};
+            // the hash capacity in bricks and at most kDenseAxis bricks per axis;
+            // one extra layer of empty bricks past the box maximum on every axis
+            // is where the scoring clamps points that fall outside the box
+            const int64_t n3[3] = {(int64_t)bbox[3] - bbox[0] + 2, (int64_t)bbox[4] - bbox[1] + 2,
+                                   (int64_t)bbox[5] - bbox[2] + 2};
             const int64_t dn = n3[0] * n3[1] * n3[2];
             const bool axes_ok = n3[0] <= kDenseAxis && n3[1] <= kDenseAxis && n3[2] <= kDenseAxis;
             if (axes_ok && dn <= kDenseRatio * (int64_t)cap && dn <= kDenseMax) {

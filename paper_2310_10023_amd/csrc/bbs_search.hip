@@ -301,6 +301,18 @@ __global__ void k_morton_scatter(const float *X, const float *Y, const float *Z,
     }
 }
 
+// Scan padding past the K points up to the next multiple of the largest
+// scoring round: a point whose every rotation leaves the map's boxes (one
+// coordinate at least 2^22 cells from the origin), so it never counts.
+__global__ void k_scan_pad(float *Xs, float *Ys, float *Zs, int32_t K, int32_t kpad, float v)
+{
+    for (int i = K + blockIdx.x * blockDim.x + threadIdx.x; i < kpad; i += gridDim.x * blockDim.x) {
+        Xs[i] = v;
+        Ys[i] = v;
+        Zs[i] = v;
+    }
+}
+
 __global__ void k_fill_buckets(Bucket *b, int32_t n)
 {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
@@ -442,12 +454,16 @@ __device__ void score_items(State *st, const ScoreArgs &A, const MapView &map, c
     const int n_groups = st ? (ld_agent(&st->batch) ? ld_agent(&st->n_groups) : 0) : A.n_groups_fixed;
     if (n_groups <= 0) return;
     const int K = C.K;
+    constexpr int kStep = NT * kUnroll;                 // points of one round of the workgroup
     int S = (C.score_items + n_groups - 1) / n_groups;
-    S = max(1, min(S, (K + NT * kUnroll - 1) / (NT * kUnroll)));
+    S = max(1, min(S, (K + kStep - 1) / kStep));
+    // slices are whole rounds, so only the last one is ragged; its tail runs
+    // over the scan padding (points that fall outside every box)
+    const int chunk = ((K + S - 1) / S + kStep - 1) / kStep * kStep;
     const int64_t n_items = (int64_t)n_groups * S;
     for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
         const int g = (int)(item / S), sp = (int)(item % S);
-        const int k_begin = (int)((int64_t)K * sp / S), k_end = (int)((int64_t)K * (sp + 1) / S);
+        const int k_begin = min(K, sp * chunk), k_end = min(K, k_begin + chunk);
         // the group is the same for every lane of the item: keep it in scalar registers
         const uint4 Gv = groups[g];
         const uint4 G = make_uint4(__builtin_amdgcn_readfirstlane(Gv.x), __builtin_amdgcn_readfirstlane(Gv.y),
@@ -466,48 +482,55 @@ __device__ void score_items(State *st, const ScoreArgs &A, const MapView &map, c
         const uint32_t ez = (uint32_t)(lv.bmax[2] - lv.bmin[2]);
         int c0 = 0, c1 = 0, c2 = 0, c3 = 0, c4 = 0, c5 = 0, c6 = 0, c7 = 0;
         if (use_dense) {
-            // Branch-free: clamped scan loads and every grid load of the
-            // kUnroll points are issued before any result is used; a point
-            // past the range or outside the box reads entry 0 and counts 0.
-            // u = voxel + (group base - 4 box minimum) per axis: u >> 2 is the
-            // brick relative to the box (negative u fails the unsigned box
-            // test), u & 3 the voxel inside it.  The eight counts are
-            // bit-sliced into two 64-bit words, members 0..3 of the window
-            // bits 0, 5, 25, 30 and members 4..7 of bits 1, 6, 26, 31, in
-            // fields of at least 5 bits, folded every kFold rounds.
+            // Branch-free: every scan and grid load of the kUnroll points is
+            // issued before any result is used.  Per axis, w = floor(R s / r)
+            // + (group base - 4 box minimum) 2^l is the level-0 coordinate of
+            // the level-l voxel relative to the box (adding a multiple of 2^l
+            // commutes with the floor of the shift): w >> (l + 2) is the brick,
+            // clamped into the grid's empty border layer when outside the box
+            // (a negative w is a large unsigned value), and bits l, l+1 of w
+            // the voxel inside it.  The eight counts are bit-sliced into two
+            // 64-bit words, members 0..3 of the window bits 0, 5, 25, 30 and
+            // members 4..7 of bits 1, 6, 26, 31, in fields of at least 5 bits,
+            // folded every kFold rounds.
             constexpr int kFold = 31 / kUnroll;
-            constexpr uint32_t kSlice = 0x42000021u;           // window bits 0, 5, 25, 30
+            constexpr uint32_t kSliceA = 0x42000021u;          // window bits 0, 5, 25, 30
+            constexpr uint32_t kSliceB = kSliceA << 1;         // window bits 1, 6, 26, 31
             uint64_t acc_a = 0, acc_b = 0;
             int rounds = 0;
             const uint4 *__restrict__ dense = lv.dense;
             const uint32_t nx = (uint32_t)lv.nx, ny = (uint32_t)lv.ny;
-            const int32_t ox = bx - 4 * lv.bmin[0], oy = by - 4 * lv.bmin[1], oz = bz - 4 * lv.bmin[2];
+            const uint32_t lim[3] = {ex + 1, ey + 1, ez + 1};   // border layer index per axis
+            const int32_t scale = 1 << level;
+            const int32_t off[3] = {(bx - 4 * lv.bmin[0]) * scale, (by - 4 * lv.bmin[1]) * scale,
+                                    (bz - 4 * lv.bmin[2]) * scale};
+            const uint32_t sh = (uint32_t)level + 2u;
             auto fold = [&]() {
                 c0 += (int)(acc_a & 31u);
                 c2 += (int)((acc_a >> 5) & 0xFFFFFu);
                 c1 += (int)((acc_a >> 25) & 31u);
                 c3 += (int)(acc_a >> 30);
-                c4 += (int)(acc_b & 31u);
-                c6 += (int)((acc_b >> 5) & 0xFFFFFu);
-                c5 += (int)((acc_b >> 25) & 31u);
-                c7 += (int)(acc_b >> 30);
+                c4 += (int)((acc_b >> 1) & 31u);
+                c6 += (int)((acc_b >> 6) & 0xFFFFFu);
+                c5 += (int)((acc_b >> 26) & 31u);
+                c7 += (int)(acc_b >> 31);
                 acc_a = acc_b = 0;
             };
-            for (int kb = k_begin + (int)threadIdx.x; kb < k_end; kb += NT * kUnroll) {
+            for (int kb = k_begin + (int)threadIdx.x; kb < k_end; kb += kStep) {
+                // 32-bit byte offsets (K <= 2^24), one per round; the kUnroll
+                // points sit at fixed distances from it
+                const uint32_t koff = (uint32_t)kb * 4u;
                 float sx[kUnroll], sy[kUnroll], sz[kUnroll];
 #pragma unroll
                 for (int u = 0; u < kUnroll; ++u) {
-                    // 32-bit byte offsets (K <= 2^24): base + offset addressing
-                    const uint32_t koff = (uint32_t)min(kb + u * NT, k_end - 1) * 4u;
-                    sx[u] = *reinterpret_cast<const float *>(reinterpret_cast<const char *>(X) + koff);
-                    sy[u] = *reinterpret_cast<const float *>(reinterpret_cast<const char *>(Y) + koff);
-                    sz[u] = *reinterpret_cast<const float *>(reinterpret_cast<const char *>(Z) + koff);
+                    sx[u] = *reinterpret_cast<const float *>(reinterpret_cast<const char *>(X) + koff + u * NT * 4);
+                    sy[u] = *reinterpret_cast<const float *>(reinterpret_cast<const char *>(Y) + koff + u * NT * 4);
+                    sz[u] = *reinterpret_cast<const float *>(reinterpret_cast<const char *>(Z) + koff + u * NT * 4);
                 }
                 uint32_t idx[kUnroll], i0[kUnroll];
-                bool ok[kUnroll];
 #pragma unroll
                 for (int u = 0; u < kUnroll; ++u) {
-                    uint32_t v[3];
+                    uint32_t rb[3], f[3];
 #pragma unroll
                     for (int row = 0; row < 3; ++row) {
                         float t0 = R[3 * row + 0] * sx[u];
@@ -519,14 +542,13 @@ __device__ void score_items(State *st, const ScoreArgs &A, const MapView &map, c
                         // conversion for the finite, in-range q here; denormals kept)
                         int32_t fl;
                         asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(fl) : "v"(q));
-                        v[row] = (uint32_t)((fl >> level) + (row == 0 ? ox : (row == 1 ? oy : oz)));
+                        const int32_t w = fl + off[row];
+                        rb[row] = min((uint32_t)(w >> sh), lim[row]);
+                        f[row] = __builtin_amdgcn_ubfe((uint32_t)w, (uint32_t)level, 2u);
                     }
-                    const uint32_t rx = v[0] >> 2, ry = v[1] >> 2, rz = v[2] >> 2;
-                    ok[u] = kb + u * NT < k_end && rx <= ex && ry <= ey && rz <= ez;
                     // box dimensions <= 4096 and <= 2^27 entries: 24-bit products are exact
-                    const uint32_t id = __umul24(__umul24(rz, ny) + ry, nx) + rx;
-                    idx[u] = ok[u] ? id : 0u;
-                    i0[u] = ((v[2] & 3u) * 5u + (v[1] & 3u)) * 5u + (v[0] & 3u);   // 0 .. 93
+                    idx[u] = __umul24(__umul24(rb[2], ny) + rb[1], nx) + rb[0];
+                    i0[u] = (f[2] * 5u + f[1]) * 5u + f[0];   // 0 .. 93
                 }
                 uint4 bits[kUnroll];
 #pragma unroll
@@ -542,11 +564,10 @@ __device__ void score_items(State *st, const ScoreArgs &A, const MapView &map, c
                     const uint32_t word = i0[u] >> 5;
                     const uint32_t lo = word == 0 ? bits[u].x : (word == 1 ? bits[u].y : bits[u].z);
                     const uint32_t hi = word == 0 ? bits[u].y : (word == 1 ? bits[u].z : bits[u].w);
-                    uint32_t win = __builtin_amdgcn_alignbit(hi, lo, i0[u] & 31u);
-                    win = ok[u] ? win : 0u;
+                    const uint32_t win = __builtin_amdgcn_alignbit(hi, lo, i0[u] & 31u);
                     // member j = 4 jx + 2 jy + jz sits at window bit 25 jz + 5 jy + jx
-                    acc_a += (uint64_t)(win & kSlice);
-                    acc_b += (uint64_t)((win >> 1) & kSlice);
+                    acc_a += (uint64_t)(win & kSliceA);
+                    acc_b += (uint64_t)(win & kSliceB);
                 }
                 if (++rounds == kFold) {
                     fold();
@@ -1611,7 +1632,10 @@ struct Setup {
     SearchConst C;
     hipStream_t s;
     bool pow2;
+    int64_t kpad;             // scan arrays' stride: K rounded up to whole scoring rounds
 };
+
+constexpr int kScanPad = 4096;  // the largest scoring round (1024 threads x kUnroll points)
 
 // Upload the scan, derive d_max, the grid and the cos/sin tables.
 bbs_status setup_search(const bbs_map *m, bbs_workspace *ws, const float *scan, int64_t k, int on_device,
@@ -1626,7 +1650,9 @@ bbs_status setup_search(const bbs_map *m, bbs_workspace *ws, const float *scan, 
             return fail(BBS_ERR_INVALID_ARG, "bbs_localize: search range must be finite with min <= max");
     if (batch < 1 || batch > (1 << 24)) return fail(BBS_ERR_INVALID_ARG, "bbs_localize: batch_size must be in [1, 2^24]");
     S.s = s;
-    if (ensure(ws->scan, ws->scan_n, 3 * k) || ensure(ws->scan_tmp, ws->scan_tmp_n, 3 * k) ||
+    const int64_t kp = (k + kScanPad - 1) / kScanPad * kScanPad;
+    S.kpad = kp;
+    if (ensure(ws->scan, ws->scan_n, 3 * kp) || ensure(ws->scan_tmp, ws->scan_tmp_n, 3 * k) ||
         ensure(ws->mkeys, ws->mkeys_n, k) || ensure(ws->mhist, ws->mhist_n, kMortonBins) ||
         ensure(ws->maxsq, ws->maxsq_n, 1))
         return BBS_ERR_OOM;
@@ -1658,7 +1684,10 @@ bbs_status setup_search(const bbs_map *m, bbs_workspace *ws, const float *scan, 
                                                               ws->mhist);
         k_morton_offsets<<<1, 1024, 0, s>>>(ws->mhist);
         k_morton_scatter<<<grid_for(k, 256, 1024), 256, 0, s>>>(tx, ty, tz, ws->mkeys, (int32_t)k, ws->mhist, ws->scan,
-                                                                 ws->scan + k, ws->scan + 2 * k);
+                                                                 ws->scan + kp, ws->scan + 2 * kp);
+        if (kp > k)
+            k_scan_pad<<<grid_for(kp - k, 256, 64), 256, 0, s>>>(ws->scan, ws->scan + kp, ws->scan + 2 * kp, (int32_t)k,
+                                                                 (int32_t)kp, std::ldexp(m->r, 22));
         BBS_HIP(hipGetLastError());
     }
     const Grid &g = S.g;
@@ -1701,8 +1730,8 @@ ScoreArgs score_args(const Setup &S, bbs_workspace *ws, int32_t n_fixed, bool ti
     A.groups = ws->groups;
     A.n_groups_fixed = n_fixed;
     A.X = ws->scan;
-    A.Y = ws->scan + S.C.K;
-    A.Z = ws->scan + 2 * (int64_t)S.C.K;
+    A.Y = ws->scan + S.kpad;
+    A.Z = ws->scan + 2 * S.kpad;
     A.trig = ws->trig;
     A.scores = ws->scores;
     A.tile_done = tile_pass ? ws->tile_done : nullptr;
