@@ -38,25 +38,29 @@ struct alignas(32) Slot {
 // small and cache resident; a mask is read only when its key matches.
 //
 // Where the level's brick bounding box is small enough (at most a few times
-// the hash capacity, at most 4096 bricks per axis), the masks are also laid
-// out as a dense row-major grid over that box (x fastest), which the scoring
-// kernel reads instead: one load per lookup, no key compare and no probe
-// chain; absent bricks hold zero masks.  The grid has one more layer of
-// (empty) bricks past the box maximum on each axis: a lookup clamps each
-// brick coordinate into [0, extent + 1], so every point outside the box lands
-// on an empty brick without a bounds branch.
+// the hash capacity, at most 4096 bricks along x and y), the masks are also
+// laid out as a dense row-major grid of columns over that box (x fastest),
+// which the scoring kernel reads instead: one 8-byte load per lookup, no key
+// compare and no probe chain.  A column is a brick's x-y extent at a single
+// voxel z: entry (x brick, y brick, z voxel) holds the brick's bits of the
+// z-slabs z and z + 1 (50 bits, bit 25 dz + 5 dy + dx), so the eight
+// translational siblings of any voxel sit in one 32-bit window of one
+// entry.  Absent bricks hold zero columns.  The grid has one more layer of
+// (empty) entries past the box maximum on each axis: a lookup clamps each
+// coordinate into it, so every point outside the box lands on an empty entry
+// without a bounds branch.
 struct LevelView {
     const uint2 *keys;   // (key lo, key hi); empty = all ones
     const uint4 *bits;   // occupancy of the brick in the same slot
-    const uint4 *dense;  // dense mask grid over the bounding box, or NULL
+    const uint2 *dense;  // dense column grid over the bounding box, or NULL
     uint32_t cap_mask;   // capacity - 1 (power of two)
     int32_t bmin[3];     // brick-coordinate bounding box of the level
     int32_t bmax[3];
     int32_t nx, ny;      // dense grid: bricks along x and y (border layer included)
 };
 
-// Index of brick (rx, ry, rz) (relative to the bounding box minimum) in the
-// dense grid.
+// Index of the column at brick (rx, ry) and voxel rz (relative to the
+// bounding box minimum) in the dense grid.
 __host__ __device__ inline uint32_t dense_index(uint32_t rx, uint32_t ry, uint32_t rz, int32_t nx, int32_t ny)
 {
     return (rz * (uint32_t)ny + ry) * (uint32_t)nx + rx;
@@ -168,7 +172,7 @@ struct bbs_map {
     int32_t device;
     uint2 *keys[bbs::kMaxLevels];
     uint4 *bits[bbs::kMaxLevels];
-    uint4 *dense[bbs::kMaxLevels];        // dense mask grid of the level, or NULL (hash only)
+    uint2 *dense[bbs::kMaxLevels];        // dense column grid of the level, or NULL (hash only)
     int64_t dense_n[bbs::kMaxLevels];     // its entries
     int32_t nx[bbs::kMaxLevels], ny[bbs::kMaxLevels];
     uint64_t cap[bbs::kMaxLevels];

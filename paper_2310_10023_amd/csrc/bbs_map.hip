@@ -23,9 +23,10 @@ namespace {
 constexpr int kThreads = 256;
 constexpr unsigned long long kEmpty64 = 0xFFFFFFFFFFFFFFFFull;
 constexpr int32_t kPackBias = 1 << 20;
-constexpr int64_t kDenseRatio = 4;              // dense grid only if its entries <= 4 x the hash capacity
-constexpr int64_t kDenseMax = (int64_t)1 << 27; // and at most 2^27 entries (2 GiB)
-constexpr int64_t kDenseAxis = 4096;            // and at most 4096 bricks per axis (24-bit index products)
+constexpr int64_t kDenseRatio = 4;              // dense grid only if its bricks <= 4 x the hash capacity
+constexpr int64_t kDenseMax = (int64_t)1 << 28; // and at most 2^28 entries (2 GiB, byte offsets < 2^31)
+constexpr int64_t kDenseAxis = 4096;            // and at most 4096 bricks along x and y
+constexpr int64_t kDenseZY = (int64_t)1 << 24;  // and z voxels x y bricks <= 2^24 (24-bit index products)
 
 inline int grid_for(int64_t n, int threads = kThreads, int cap = 8192)
 {
@@ -257,8 +258,10 @@ __global__ void k_compact(const Slot *src, uint64_t src_n, uint2 *dkeys, uint4 *
     }
 }
 
-// Copy every brick of a finished level into its dense grid (zeroed before).
-__global__ void k_fill_dense(const uint2 *keys, const uint4 *bits, uint64_t cap, uint4 *dense, int32_t bx0, int32_t by0,
+// Copy every brick of a finished level into its dense column grid (zeroed
+// before): column c of a brick is its z-slabs c and c + 1, bits 25 c to
+// 25 c + 49 of the 125-bit mask.
+__global__ void k_fill_dense(const uint2 *keys, const uint4 *bits, uint64_t cap, uint2 *dense, int32_t bx0, int32_t by0,
                              int32_t bz0, int32_t nx, int32_t ny)
 {
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < cap; i += (uint64_t)gridDim.x * blockDim.x) {
@@ -268,7 +271,15 @@ __global__ void k_fill_dense(const uint2 *keys, const uint4 *bits, uint64_t cap,
         const int32_t bx = (int32_t)((key >> 38) & 0x7FFFF) - kBrickBias;
         const int32_t by = (int32_t)((key >> 19) & 0x7FFFF) - kBrickBias;
         const int32_t bz = (int32_t)(key & 0x7FFFF) - kBrickBias;
-        dense[dense_index((uint32_t)(bx - bx0), (uint32_t)(by - by0), (uint32_t)(bz - bz0), nx, ny)] = bits[i];
+        const uint4 b = bits[i];
+        const unsigned __int128 m = ((unsigned __int128)b.w << 96) | ((unsigned __int128)b.z << 64) |
+                                    ((unsigned __int128)b.y << 32) | (unsigned __int128)b.x;
+        for (int c = 0; c < 4; ++c) {
+            const unsigned long long col = (unsigned long long)(m >> (25 * c)) & ((1ull << 50) - 1ull);
+            const uint32_t z = 4u * (uint32_t)(bz - bz0) + (uint32_t)c;
+            dense[dense_index((uint32_t)(bx - bx0), (uint32_t)(by - by0), z, nx, ny)] =
+                make_uint2((uint32_t)col, (uint32_t)(col >> 32));
+        }
     }
 }
 
@@ -598,25 +609,26 @@ extern "C" bbs_status bbs_build_map(const float *xyz, int64_t n, int32_t xyz_on_
                 m->bmax[l][a] = bbox[3 + a];
             }
             m->voxels[l] = (int64_t)nv;
-            // dense mask grid when the bounding box holds at most kDenseRatio x
-            // the hash capacity in bricks and at most kDenseAxis bricks per axis;
-            // one extra layer of empty bricks past the box maximum on every axis
-            // is where the scoring clamps points that fall outside the box
+            // dense column grid when the bounding box holds at most kDenseRatio x
+            // the hash capacity in bricks and the index products stay within 24
+            // bits; one extra layer of empty entries past the box maximum on
+            // every axis is where the scoring clamps points outside the box
             const int64_t n3[3] = {(int64_t)bbox[3] - bbox[0] + 2, (int64_t)bbox[4] - bbox[1] + 2,
-                                   (int64_t)bbox[5] - bbox[2] + 2};
+                                   4 * ((int64_t)bbox[5] - bbox[2] + 1) + 1};
             const int64_t dn = n3[0] * n3[1] * n3[2];
-            const bool axes_ok = n3[0] <= kDenseAxis && n3[1] <= kDenseAxis && n3[2] <= kDenseAxis;
-            if (axes_ok && dn <= kDenseRatio * (int64_t)cap && dn <= kDenseMax) {
+            const int64_t box_bricks = n3[0] * n3[1] * ((int64_t)bbox[5] - bbox[2] + 2);
+            const bool axes_ok = n3[0] <= kDenseAxis && n3[1] <= kDenseAxis && n3[2] * n3[1] <= kDenseZY;
+            if (axes_ok && box_bricks <= kDenseRatio * (int64_t)cap && dn <= kDenseMax) {
                 void *dd = nullptr;
-                if (alloc_dev(&dd, (size_t)dn * sizeof(uint4))) {
+                if (alloc_dev(&dd, (size_t)dn * sizeof(uint2))) {
                     bbs_free_map(m);
                     return BBS_ERR_OOM;
                 }
-                m->dense[l] = static_cast<uint4 *>(dd);
+                m->dense[l] = static_cast<uint2 *>(dd);
                 m->dense_n[l] = dn;
                 m->nx[l] = (int32_t)n3[0];
                 m->ny[l] = (int32_t)n3[1];
-                BBS_HIP(hipMemsetAsync(dd, 0, (size_t)dn * sizeof(uint4), s));
+                BBS_HIP(hipMemsetAsync(dd, 0, (size_t)dn * sizeof(uint2), s));
                 k_fill_dense<<<grid_for((int64_t)cap), kThreads, 0, s>>>(m->keys[l], m->bits[l], cap, m->dense[l],
                                                                          bbox[0], bbox[1], bbox[2], m->nx[l], m->ny[l]);
                 BBS_HIP(hipGetLastError());

@@ -486,25 +486,26 @@ __device__ void score_items(State *st, const ScoreArgs &A, const MapView &map, c
             // issued before any result is used.  Per axis, w = floor(R s / r)
             // + (group base - 4 box minimum) 2^l is the level-0 coordinate of
             // the level-l voxel relative to the box (adding a multiple of 2^l
-            // commutes with the floor of the shift): w >> (l + 2) is the brick,
-            // clamped into the grid's empty border layer when outside the box
-            // (a negative w is a large unsigned value), and bits l, l+1 of w
-            // the voxel inside it.  The eight counts are bit-sliced into two
-            // 64-bit words, members 0..3 of the window bits 0, 5, 25, 30 and
-            // members 4..7 of bits 1, 6, 26, 31, in fields of at least 5 bits,
-            // folded every kFold rounds.
+            // commutes with the floor of the shift): w >> (l + 2) is the x or y
+            // brick and w >> l the z voxel, clamped into the grid's empty
+            // border layer when outside the box (a negative w is a large
+            // unsigned value), and bits l, l+1 of w the x or y voxel inside
+            // the brick, which picks the 32-bit window of the column.  The
+            // eight counts are bit-sliced into two 64-bit words, members 0..3
+            // of the window bits 0, 5, 25, 30 and members 4..7 of bits 1, 6,
+            // 26, 31, in fields of at least 5 bits, folded every kFold rounds.
             constexpr int kFold = 31 / kUnroll;
             constexpr uint32_t kSliceA = 0x42000021u;          // window bits 0, 5, 25, 30
             constexpr uint32_t kSliceB = kSliceA << 1;         // window bits 1, 6, 26, 31
             uint64_t acc_a = 0, acc_b = 0;
             int rounds = 0;
-            const uint4 *__restrict__ dense = lv.dense;
+            const uint2 *__restrict__ dense = lv.dense;
             const uint32_t nx = (uint32_t)lv.nx, ny = (uint32_t)lv.ny;
-            const uint32_t lim[3] = {ex + 1, ey + 1, ez + 1};   // border layer index per axis
+            const uint32_t lim[3] = {ex + 1, ey + 1, 4u * (ez + 1)};   // border layer index per axis
             const int32_t scale = 1 << level;
             const int32_t off[3] = {(bx - 4 * lv.bmin[0]) * scale, (by - 4 * lv.bmin[1]) * scale,
                                     (bz - 4 * lv.bmin[2]) * scale};
-            const uint32_t sh = (uint32_t)level + 2u;
+            const uint32_t sh[3] = {(uint32_t)level + 2u, (uint32_t)level + 2u, (uint32_t)level};
             auto fold = [&]() {
                 c0 += (int)(acc_a & 31u);
                 c2 += (int)((acc_a >> 5) & 0xFFFFFu);
@@ -530,7 +531,7 @@ __device__ void score_items(State *st, const ScoreArgs &A, const MapView &map, c
                 uint32_t idx[kUnroll], i0[kUnroll];
 #pragma unroll
                 for (int u = 0; u < kUnroll; ++u) {
-                    uint32_t rb[3], f[3];
+                    uint32_t rb[3], f[2];
 #pragma unroll
                     for (int row = 0; row < 3; ++row) {
                         float t0 = R[3 * row + 0] * sx[u];
@@ -543,28 +544,20 @@ __device__ void score_items(State *st, const ScoreArgs &A, const MapView &map, c
                         int32_t fl;
                         asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(fl) : "v"(q));
                         const int32_t w = fl + off[row];
-                        rb[row] = min((uint32_t)(w >> sh), lim[row]);
-                        f[row] = __builtin_amdgcn_ubfe((uint32_t)w, (uint32_t)level, 2u);
+                        rb[row] = min((uint32_t)(w >> sh[row]), lim[row]);
+                        if (row < 2) f[row] = __builtin_amdgcn_ubfe((uint32_t)w, (uint32_t)level, 2u);
                     }
-                    // box dimensions <= 4096 and <= 2^27 entries: 24-bit products are exact
+                    // z voxels x y bricks <= 2^24, x bricks <= 4096: 24-bit products are exact
                     idx[u] = __umul24(__umul24(rb[2], ny) + rb[1], nx) + rb[0];
-                    i0[u] = (f[2] * 5u + f[1]) * 5u + f[0];   // 0 .. 93
+                    i0[u] = f[1] * 5u + f[0];   // 0 .. 18
                 }
-                uint4 bits[kUnroll];
+                uint2 bits[kUnroll];
 #pragma unroll
-                for (int u = 0; u < kUnroll; ++u)     // grid entries < 2^27: byte offset < 2^31
-                    bits[u] = *reinterpret_cast<const uint4 *>(reinterpret_cast<const char *>(dense) + idx[u] * 16u);
-                // keep every mask whole in registers: one 16-byte load per point,
-                // never a load split by which words the window needs
-#pragma unroll
-                for (int u = 0; u < kUnroll; ++u)
-                    asm volatile("" : "+v"(bits[u].x), "+v"(bits[u].y), "+v"(bits[u].z), "+v"(bits[u].w));
+                for (int u = 0; u < kUnroll; ++u)     // grid entries <= 2^28: byte offset < 2^31
+                    bits[u] = *reinterpret_cast<const uint2 *>(reinterpret_cast<const char *>(dense) + idx[u] * 8u);
 #pragma unroll
                 for (int u = 0; u < kUnroll; ++u) {
-                    const uint32_t word = i0[u] >> 5;
-                    const uint32_t lo = word == 0 ? bits[u].x : (word == 1 ? bits[u].y : bits[u].z);
-                    const uint32_t hi = word == 0 ? bits[u].y : (word == 1 ? bits[u].z : bits[u].w);
-                    const uint32_t win = __builtin_amdgcn_alignbit(hi, lo, i0[u] & 31u);
+                    const uint32_t win = __builtin_amdgcn_alignbit(bits[u].y, bits[u].x, i0[u]);
                     // member j = 4 jx + 2 jy + jz sits at window bit 25 jz + 5 jy + jx
                     acc_a += (uint64_t)(win & kSliceA);
                     acc_b += (uint64_t)(win & kSliceB);
