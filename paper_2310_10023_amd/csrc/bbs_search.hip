@@ -28,6 +28,7 @@ namespace {
 
 constexpr int kScoreThreads = 256;
 constexpr int kUnroll = 4;                       // scan points in flight per thread in the scoring loop
+constexpr int kScanPad = 1024 * kUnroll;          // scan padding: the largest scoring round (1024 threads)
 constexpr int kTileGroups = 32;                  // push tile: 32 groups = 256 node slots
 constexpr int kTileSlots = kTileGroups * 8;
 constexpr int kSerialThreads = 1024;
@@ -359,6 +360,14 @@ __device__ inline int32_t ld_agent(const int32_t *p)
     return __hip_atomic_load(const_cast<int32_t *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// a * b + c for a, b < 2^24 (the full-rate 24-bit multiply-add)
+__device__ inline uint32_t mad24(uint32_t a, uint32_t b, uint32_t c)
+{
+    uint32_t d;
+    asm("v_mad_u32_u24 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
+    return d;
+}
+
 __device__ inline int bucket_of(int score, int level, const SearchConst &C)
 {
     return (C.K - score) * (C.levels + 1) + level;
@@ -426,6 +435,7 @@ struct ScoreSmem {
     int sq[kTileSlots];
     int sm[NT / 64];
     int s_last;
+    int s_next;
 };
 
 struct ScoreArgs {
@@ -437,9 +447,22 @@ struct ScoreArgs {
     int32_t *tile_done;        // NULL: no tile pass
     int32_t *q_arr, *rank_arr, *hist;
     uint32_t *qmask;           // bit q: some tile of the batch holds a child of bucket q
+    int32_t *ticket;           // NULL: items round-robin; else [0] next item ticket, [1] workgroups
+                               // done (both 0 between launches)
 };
 
-template <bool POW2, int NT>
+// A rotated coordinate in level-0 cells, as p / r: RM 0 divides (correctly
+// rounded), RM 1 multiplies by 1 / r (exact for a power-of-two r), RM 2 is
+// r = 1 (p itself).
+template <int RM>
+__device__ inline float scale_to_cells(float p, const SearchConst &C)
+{
+    if (RM == 2) return p;
+    if (RM == 1) return p * C.inv_r;
+    return p / C.r;
+}
+
+template <int RM, int NT>
 __device__ void score_items(State *st, const ScoreArgs &A, const MapView &map, const SearchConst &C,
                             ScoreSmem<NT> &sh)
 {
@@ -455,14 +478,38 @@ __device__ void score_items(State *st, const ScoreArgs &A, const MapView &map, c
     if (n_groups <= 0) return;
     const int K = C.K;
     constexpr int kStep = NT * kUnroll;                 // points of one round of the workgroup
-    int S = (C.score_items + n_groups - 1) / n_groups;
-    S = max(1, min(S, (K + kStep - 1) / kStep));
-    // slices are whole rounds, so only the last one is ragged; its tail runs
-    // over the scan padding (points that fall outside every box)
-    const int chunk = ((K + S - 1) / S + kStep - 1) / kStep * kStep;
-    const int64_t n_items = (int64_t)n_groups * S;
-    for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
-        const int g = (int)(item / S), sp = (int)(item % S);
+    const int max_s = (K + kStep - 1) / kStep;
+    // Work items.  The grid is as large as the device holds at once.  Groups
+    // run whole in full rounds of the grid; the groups of the last, partial
+    // round are split into point slices so that they fill the grid once more
+    // (or all groups are split score_items / n_groups ways when that asks for
+    // more).  Items go round-robin over the workgroups, or, with a ticket
+    // counter, to whichever workgroup asks next.
+    const int P = (int)gridDim.x;
+    const int s_min = min(max_s, max(1, (C.score_items + n_groups - 1) / n_groups));
+    const int n_full = s_min > 1 ? 0 : n_groups - n_groups % P;
+    const int s_tail = s_min > 1 ? s_min : min(max_s, max(1, P / max(1, n_groups - n_full)));
+    const int64_t n_items = n_full + (int64_t)(n_groups - n_full) * s_tail;
+    int32_t *ticket = A.ticket;
+    int64_t item = blockIdx.x;
+    while (item < n_items) {
+        // the next item's ticket, drawn now so that its latency is hidden
+        int nxt = 0;
+        if (ticket && threadIdx.x == 0) nxt = atomicAdd(&ticket[0], 1);
+        int g, sp, S;
+        if (item < n_full) {
+            g = (int)item;
+            sp = 0;
+            S = 1;
+        } else {
+            const int j = (int)(item - n_full);
+            g = n_full + j / s_tail;
+            sp = j % s_tail;
+            S = s_tail;
+        }
+        // slices are whole rounds, so only the last one is ragged; its tail runs
+        // over the scan padding (points that fall outside every box)
+        const int chunk = ((K + S - 1) / S + kStep - 1) / kStep * kStep;
         const int k_begin = min(K, sp * chunk), k_end = min(K, k_begin + chunk);
         // the group is the same for every lane of the item: keep it in scalar registers
         const uint4 Gv = groups[g];
@@ -538,7 +585,7 @@ __device__ void score_items(State *st, const ScoreArgs &A, const MapView &map, c
                         float t1 = R[3 * row + 1] * sy[u];
                         float t2 = R[3 * row + 2] * sz[u];
                         float p = (t0 + t1) + t2;
-                        float q = POW2 ? p * C.inv_r : p / C.r;
+                        float q = scale_to_cells<RM>(p, C);
                         // floor and convert in one instruction (equal to floorf then
                         // conversion for the finite, in-range q here; denormals kept)
                         int32_t fl;
@@ -548,7 +595,7 @@ __device__ void score_items(State *st, const ScoreArgs &A, const MapView &map, c
                         if (row < 2) f[row] = __builtin_amdgcn_ubfe((uint32_t)w, (uint32_t)level, 2u);
                     }
                     // z voxels x y bricks <= 2^24, x bricks <= 4096: 24-bit products are exact
-                    idx[u] = __umul24(__umul24(rb[2], ny) + rb[1], nx) + rb[0];
+                    idx[u] = mad24(mad24(rb[2], ny, rb[1]), nx, rb[0]);
                     i0[u] = f[1] * 5u + f[0];   // 0 .. 18
                 }
                 uint2 bits[kUnroll];
@@ -589,7 +636,7 @@ __device__ void score_items(State *st, const ScoreArgs &A, const MapView &map, c
                             float t1 = R[3 * row + 1] * sy;
                             float t2 = R[3 * row + 2] * sz;
                             float p = (t0 + t1) + t2;
-                            float q = POW2 ? p * C.inv_r : p / C.r;
+                            float q = scale_to_cells<RM>(p, C);
                             w[row] = ((int32_t)floorf(q) >> level);
                         }
                         const int32_t wx = w[0] + bx, wy = w[1] + by, wz = w[2] + bz;
@@ -664,28 +711,43 @@ __device__ void score_items(State *st, const ScoreArgs &A, const MapView &map, c
             asm volatile("" ::"v"(old));          // keep the returning form of the atomic
         }
         __syncthreads();
-        if (!tile_done) continue;
-        // the last workgroup to finish a tile sorts it into queue buckets
-        const int t = g / kTileGroups;
-        if (threadIdx.x == 0) {
-            const int in_tile = min(kTileGroups, n_groups - t * kTileGroups) * S;
-            const int prev = atomicAdd(&tile_done[t], 1);
-            sh.s_last = (prev == in_tile - 1);
+        if (tile_done) {
+            // the last workgroup to finish a tile sorts it into queue buckets
+            const int t = g / kTileGroups;
+            if (threadIdx.x == 0) {
+                const int t0 = t * kTileGroups, te = min(n_groups, t0 + kTileGroups);
+                const int whole = min(max(n_full - t0, 0), te - t0);
+                const int in_tile = whole + (te - t0 - whole) * s_tail;
+                const int prev = atomicAdd(&tile_done[t], 1);
+                sh.s_last = (prev == in_tile - 1);
+            }
+            __syncthreads();
+            if (sh.s_last) {
+                tile_pass<NT>(t, groups, scores, st, C, n_groups, A.q_arr, A.rank_arr, A.hist, A.qmask, sh.sq, sh.sm);
+                if (threadIdx.x == 0) __hip_atomic_store(&tile_done[t], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
         }
-        __syncthreads();
-        if (sh.s_last) {
-            tile_pass<NT>(t, groups, scores, st, C, n_groups, A.q_arr, A.rank_arr, A.hist, A.qmask, sh.sq, sh.sm);
-            if (threadIdx.x == 0) __hip_atomic_store(&tile_done[t], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (ticket) {
+            if (threadIdx.x == 0) sh.s_next = nxt;
+            __syncthreads();
+            item = (int64_t)P + sh.s_next;
+        } else {
+            item += P;
         }
-        __syncthreads();
+    }
+    // Every workgroup has drawn its last ticket: the last one to get here
+    // rewinds the counters for the next launch.
+    if (ticket && threadIdx.x == 0 && atomicAdd(&ticket[1], 1) == P - 1) {
+        __hip_atomic_store(&ticket[0], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&ticket[1], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
-template <bool POW2>
+template <int RM>
 __global__ __launch_bounds__(kScoreThreads) void k_score(State *st, ScoreArgs A, MapView map, SearchConst C)
 {
     __shared__ ScoreSmem<kScoreThreads> sh;
-    score_items<POW2, kScoreThreads>(st, A, map, C, sh);
+    score_items<RM, kScoreThreads>(st, A, map, C, sh);
 }
 
 // ------------------------------------------------------------------ initial set
@@ -1254,6 +1316,7 @@ __global__ __launch_bounds__(kSerialThreads) void k_serial(State *st, SearchCons
 
 constexpr int kPersistThreads = 1024;   // as wide as k_serial: the serial phase runs in workgroup 0
 constexpr unsigned kSpinLimit = 1u << 26;
+static_assert(kPersistThreads * kUnroll <= kScanPad, "scan padding must cover a whole scoring round");
 
 // Grid-wide barrier for a cooperative launch: arrive on bar[0], wait for the
 // generation in bar[1] to move.  The wait is bounded: on timeout the error
@@ -1290,7 +1353,7 @@ __device__ bool grid_sync(unsigned *bar, int32_t *err, int *s_ok)
 
 // The whole search loop in one cooperative launch: every workgroup scores
 // the pending batch, then workgroup 0 pushes it and gathers the next one.
-template <bool POW2>
+template <int RM>
 __global__ __launch_bounds__(kPersistThreads) void k_persistent(State *st, ScoreArgs A, MapView map, SearchConst C,
                                                                 Bucket *bk, uint4 *groups, int32_t *scores,
                                                                 PushBufs B, unsigned *bar, int32_t max_iters)
@@ -1300,7 +1363,7 @@ __global__ __launch_bounds__(kPersistThreads) void k_persistent(State *st, Score
     __shared__ int s_ok;
     for (int it = 0; it < max_iters; ++it) {
         if (ld_agent(&st->done)) break;
-        score_items<POW2, kPersistThreads>(st, A, map, C, ssh);
+        score_items<RM, kPersistThreads>(st, A, map, C, ssh);
         if (!grid_sync(bar, &st->error, &s_ok)) break;
         if (blockIdx.x == 0) serial_body<kPersistThreads>(st, C, bk, groups, scores, B, 1, sh);
         if (!grid_sync(bar, &st->error, &s_ok)) break;
@@ -1521,6 +1584,9 @@ struct bbs_workspace {
     int64_t rank_arr_n = 0;
     int32_t *tile_done = nullptr;
     int64_t tile_done_n = 0;
+    int32_t *ticket = nullptr;   // scoring item tickets (2 counters, zero between launches)
+    int64_t ticket_n = 0;
+    int32_t score_grid[3] = {0, 0, 0};   // resident k_score workgroups, per division mode
     float *scan = nullptr;
     int64_t scan_n = 0;
     float *scan_aos = nullptr;
@@ -1556,7 +1622,7 @@ namespace {
 void free_ws(bbs_workspace *w)
 {
     void *ptrs[] = {w->arena, w->chunk_next, w->buckets, w->hist, w->totals, w->pT, w->pf, w->pc0, w->groups, w->scores,
-                    w->q_arr, w->rank_arr, w->tile_done, w->scan, w->scan_aos, w->scan_tmp, w->mkeys, w->mhist,
+                    w->q_arr, w->rank_arr, w->tile_done, w->ticket, w->scan, w->scan_aos, w->scan_tmp, w->mkeys, w->mhist,
                     w->trig, w->state, w->maxsq, w->beam, w->prior, w->dstate, w->bar, w->qmask, w->qlist};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -1625,10 +1691,11 @@ struct Setup {
     SearchConst C;
     hipStream_t s;
     bool pow2;
+    int rmode;                // scoring's division by r: 0 divide, 1 multiply by 1 / r, 2 r = 1
     int64_t kpad;             // scan arrays' stride: K rounded up to whole scoring rounds
+    int32_t score_grid;       // k_score workgroups: as many as the device holds at once
 };
 
-constexpr int kScanPad = 4096;  // the largest scoring round (1024 threads x kUnroll points)
 
 // Upload the scan, derive d_max, the grid and the cos/sin tables.
 bbs_status setup_search(const bbs_map *m, bbs_workspace *ws, const float *scan, int64_t k, int on_device,
@@ -1643,6 +1710,10 @@ bbs_status setup_search(const bbs_map *m, bbs_workspace *ws, const float *scan, 
             return fail(BBS_ERR_INVALID_ARG, "bbs_localize: search range must be finite with min <= max");
     if (batch < 1 || batch > (1 << 24)) return fail(BBS_ERR_INVALID_ARG, "bbs_localize: batch_size must be in [1, 2^24]");
     S.s = s;
+    if (!ws->ticket) {
+        if (ensure(ws->ticket, ws->ticket_n, 2)) return BBS_ERR_OOM;
+        BBS_HIP(hipMemsetAsync(ws->ticket, 0, 2 * sizeof(int32_t), s));
+    }
     const int64_t kp = (k + kScanPad - 1) / kScanPad * kScanPad;
     S.kpad = kp;
     if (ensure(ws->scan, ws->scan_n, 3 * kp) || ensure(ws->scan_tmp, ws->scan_tmp_n, 3 * k) ||
@@ -1709,6 +1780,19 @@ bbs_status setup_search(const bbs_map *m, bbs_workspace *ws, const float *scan, 
     C.batch = batch;
     C.r = g.r;
     S.pow2 = is_pow2_float(g.r);
+    S.rmode = g.r == 1.0f ? 2 : (S.pow2 ? 1 : 0);
+    int32_t &sg = ws->score_grid[S.rmode];
+    if (sg == 0) {
+        int dev = 0, cus = 0, per_cu = 0;
+        BBS_HIP(hipGetDevice(&dev));
+        BBS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        const void *fn = S.rmode == 2   ? reinterpret_cast<const void *>(&k_score<2>)
+                         : S.rmode == 1 ? reinterpret_cast<const void *>(&k_score<1>)
+                                        : reinterpret_cast<const void *>(&k_score<0>);
+        BBS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kScoreThreads, 0));
+        sg = std::max(1, cus * std::max(1, per_cu));
+    }
+    S.score_grid = sg;
     C.inv_r = 1.0f / g.r;
     C.r_pow2 = S.pow2 ? 1 : 0;
     C.score_items = 2048;
@@ -1732,6 +1816,7 @@ ScoreArgs score_args(const Setup &S, bbs_workspace *ws, int32_t n_fixed, bool ti
     A.rank_arr = ws->rank_arr;
     A.hist = ws->hist;
     A.qmask = ws->qmask;
+    A.ticket = nullptr;
     return A;
 }
 
@@ -1740,8 +1825,9 @@ void launch_score(const Setup &S, const bbs_map *m, bbs_workspace *ws, State *st
 {
     const ScoreArgs A = score_args(S, ws, n_fixed, tile_pass);
     const MapView v = m->view();
-    if (S.pow2) k_score<true><<<grid, kScoreThreads, 0, S.s>>>(st, A, v, S.C);
-    else k_score<false><<<grid, kScoreThreads, 0, S.s>>>(st, A, v, S.C);
+    if (S.rmode == 2) k_score<2><<<grid, kScoreThreads, 0, S.s>>>(st, A, v, S.C);
+    else if (S.rmode == 1) k_score<1><<<grid, kScoreThreads, 0, S.s>>>(st, A, v, S.C);
+    else k_score<0><<<grid, kScoreThreads, 0, S.s>>>(st, A, v, S.C);
 }
 
 int64_t max_children(const Grid &g)
@@ -1934,6 +2020,7 @@ extern "C" bbs_status bbs_localize(const bbs_map *map, bbs_workspace *ws, const 
         BBS_HIP(hipMemsetAsync(ws->qmask, 0, (size_t)ws->qmask_n * 4, s));
         BBS_HIP(hipMemsetAsync(ws->hist, 0, (size_t)ws->hist_n * 4, s));
         BBS_HIP(hipMemsetAsync(ws->tile_done, 0, (size_t)ws->tile_done_n * 4, s));
+        BBS_HIP(hipMemsetAsync(ws->ticket, 0, 2 * sizeof(int32_t), s));
         ws->hist_dirty = false;
     }
     k_fill_buckets<<<grid_for(qn, 256, 4096), 256, 0, s>>>(ws->buckets, (int32_t)qn);
@@ -1958,7 +2045,7 @@ extern "C" bbs_status bbs_localize(const bbs_map *map, bbs_workspace *ws, const 
         }
         return hipEventRecord(ws->ev[i], s);
     };
-    const int score_grid = 4096;
+    const int score_grid = S.score_grid;
     PushBufs B;
     B.q_arr = ws->q_arr;
     B.rank_arr = ws->rank_arr;
@@ -2090,11 +2177,13 @@ extern "C" bbs_status bbs_localize(const bbs_map *map, bbs_workspace *ws, const 
         int dev = 0, cus = 0, per_cu = 0;
         BBS_HIP(hipGetDevice(&dev));
         BBS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-        const void *fn = S.pow2 ? reinterpret_cast<const void *>(&k_persistent<true>)
-                                : reinterpret_cast<const void *>(&k_persistent<false>);
+        const void *fn = S.rmode == 2   ? reinterpret_cast<const void *>(&k_persistent<2>)
+                         : S.rmode == 1 ? reinterpret_cast<const void *>(&k_persistent<1>)
+                                        : reinterpret_cast<const void *>(&k_persistent<0>);
         hipError_t oe = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kPersistThreads, 0);
         if (oe == hipSuccess && per_cu > 0) {
             ScoreArgs A = score_args(S, ws, 0, true);
+            A.ticket = ws->ticket;            // items to whichever workgroup asks next
             MapView v = map->view();
             SearchConst Cv = C;
             State *stp = ws->state;
@@ -2271,7 +2360,7 @@ extern "C" bbs_status bbs_score_nodes(const bbs_map *map, const float *scan_xyz,
     if (ensure(ws->groups, ws->groups_n, n) || ensure(ws->scores, ws->scores_n, 8 * n)) return BBS_ERR_OOM;
     BBS_HIP(hipMemcpyAsync(ws->groups, groups.data(), (size_t)n * sizeof(uint4), hipMemcpyHostToDevice, s));
     BBS_HIP(hipMemsetAsync(ws->scores, 0, (size_t)n * 8 * sizeof(int32_t), s));
-    launch_score(S, map, ws, nullptr, (int32_t)n, 4096, false);
+    launch_score(S, map, ws, nullptr, (int32_t)n, S.score_grid, false);
     BBS_HIP(hipGetLastError());
     std::vector<int32_t> all((size_t)n * 8);
     BBS_HIP(hipMemcpyAsync(all.data(), ws->scores, all.size() * 4, hipMemcpyDeviceToHost, s));
