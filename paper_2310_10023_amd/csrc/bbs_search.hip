@@ -27,6 +27,10 @@ namespace bbs {
 namespace {
 
 constexpr int kScoreThreads = 256;
+// Resident scoring workgroups per CU: the kernel's scalar registers allow six
+// (the occupancy query, which reports seven, does not see that; workgroups
+// launched beyond six per CU only start once the first ones finish).
+constexpr int kScoreWgPerCu = 6;
 constexpr int kUnroll = 4;                       // scan points in flight per thread in the scoring loop
 constexpr int kScanPad = 1024 * kUnroll;          // scan padding: the largest scoring round (1024 threads)
 constexpr int kTileGroups = 32;                  // push tile: 32 groups = 256 node slots
@@ -494,6 +498,8 @@ __device__ void score_items(State *st, const ScoreArgs &A, const MapView &map, c
     int64_t item = blockIdx.x;
     while (item < n_items) {
         // the next item's ticket, drawn now so that its latency is hidden
+        // behind the item (one atomic counter for the whole grid: used by
+        // the persistent loop, whose grid is one workgroup per CU)
         int nxt = 0;
         if (ticket && threadIdx.x == 0) nxt = atomicAdd(&ticket[0], 1);
         int g, sp, S;
@@ -552,7 +558,7 @@ __device__ void score_items(State *st, const ScoreArgs &A, const MapView &map, c
             const int32_t scale = 1 << level;
             const int32_t off[3] = {(bx - 4 * lv.bmin[0]) * scale, (by - 4 * lv.bmin[1]) * scale,
                                     (bz - 4 * lv.bmin[2]) * scale};
-            const uint32_t sh[3] = {(uint32_t)level + 2u, (uint32_t)level + 2u, (uint32_t)level};
+            const uint32_t shr[3] = {(uint32_t)level + 2u, (uint32_t)level + 2u, (uint32_t)level};
             auto fold = [&]() {
                 c0 += (int)(acc_a & 31u);
                 c2 += (int)((acc_a >> 5) & 0xFFFFFu);
@@ -591,7 +597,7 @@ __device__ void score_items(State *st, const ScoreArgs &A, const MapView &map, c
                         int32_t fl;
                         asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(fl) : "v"(q));
                         const int32_t w = fl + off[row];
-                        rb[row] = min((uint32_t)(w >> sh[row]), lim[row]);
+                        rb[row] = min((uint32_t)(w >> shr[row]), lim[row]);
                         if (row < 2) f[row] = __builtin_amdgcn_ubfe((uint32_t)w, (uint32_t)level, 2u);
                     }
                     // z voxels x y bricks <= 2^24, x bricks <= 4096: 24-bit products are exact
@@ -1790,7 +1796,7 @@ bbs_status setup_search(const bbs_map *m, bbs_workspace *ws, const float *scan, 
                          : S.rmode == 1 ? reinterpret_cast<const void *>(&k_score<1>)
                                         : reinterpret_cast<const void *>(&k_score<0>);
         BBS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kScoreThreads, 0));
-        sg = std::max(1, cus * std::max(1, per_cu));
+        sg = std::max(1, cus * std::max(1, std::min(per_cu, kScoreWgPerCu)));
     }
     S.score_grid = sg;
     C.inv_r = 1.0f / g.r;
