@@ -379,18 +379,21 @@ __device__ inline int bucket_of(int score, int level, const SearchConst &C)
 
 // One tile of 32 groups (256 node slots) of a scored batch: the queue bucket
 // of every kept child (score >= best), its rank among the tile's earlier
-// children of the same bucket, and the tile's count per bucket.  Run by a
+// children of the same bucket, and the tile's count per bucket.  The kept
+// children are listed compactly in slot order (bucket, rank, packed node)
+// with their number, since most children of a batch are pruned.  Run by a
 // whole workgroup of NT >= 256 threads; thread s < 256 handles slot s.
 template <int NT>
 __device__ void tile_pass(int t, const uint4 *groups, int32_t *scores, State *st, const SearchConst &C,
-                          int n_groups, int32_t *q_arr, int32_t *rank_arr, int32_t *hist, uint32_t *qmask, int *sq,
-                          int *sm)
+                          int n_groups, int32_t *kq, int32_t *krank, uint4 *knode, int32_t *kcnt, int32_t *hist,
+                          uint32_t *qmask, int *sq, int *sm)
 {
     const int s = threadIdx.x;
     const bool slot = s < kTileSlots;
     const int g = t * kTileGroups + s / 8, j = s & 7;
     const int best = ld_agent(&st->best);
     int q = -1;
+    uint4 child = make_uint4(0u, 0u, 0u, 0u);
     if (slot && g < n_groups) {
         const uint4 G = groups[g];
         const uint32_t mask = (G.w >> 8) & 0xFF;
@@ -401,7 +404,12 @@ __device__ void tile_pass(int t, const uint4 *groups, int32_t *scores, State *st
             asm volatile("v_mov_b32 %0, 0" : "=v"(zero));
             const int sc = __hip_atomic_fetch_add(&scores[8 * (int64_t)g + j], zero, __ATOMIC_RELAXED,
                                                   __HIP_MEMORY_SCOPE_AGENT);
-            if (sc >= best) q = bucket_of(sc, (int)(G.w & 0xFF), C);
+            if (sc >= best) {
+                q = bucket_of(sc, (int)(G.w & 0xFF), C);
+                const int jx = (j >> 2) & 1, jy = (j >> 1) & 1, jz = j & 1;
+                child = make_uint4(pack16(lo16s(G.x) + jx, hi16s(G.x) + jy), pack16(lo16s(G.y) + jz, hi16u(G.y)),
+                                   G.z, G.w & 0xFFu);
+            }
         }
     }
     if (slot) sq[s] = q;
@@ -414,10 +422,6 @@ __device__ void tile_pass(int t, const uint4 *groups, int32_t *scores, State *st
             rank += e & (i < s);
         }
     }
-    if (slot) {
-        q_arr[(int64_t)t * kTileSlots + s] = q;
-        rank_arr[(int64_t)t * kTileSlots + s] = rank;
-    }
     if (q >= 0 && rank == 0) {
         hist[(int64_t)t * C.q_count + q] = cnt;
         atomicOr(&qmask[q >> 5], 1u << (q & 31));
@@ -425,7 +429,14 @@ __device__ void tile_pass(int t, const uint4 *groups, int32_t *scores, State *st
     const int qmn = block_min_int<NT>(q >= 0 ? q : INT_MAX, sm);
     const int qmx = -block_min_int<NT>(q >= 0 ? -q : INT_MAX, sm);
     int tot;
-    (void)block_scan_incl<NT>(q >= 0 ? 1 : 0, sm, &tot);
+    const int kin = block_scan_incl<NT>(q >= 0 ? 1 : 0, sm, &tot);
+    if (q >= 0) {
+        const int64_t k = (int64_t)t * kTileSlots + kin - 1;
+        kq[k] = q;
+        krank[k] = rank;
+        knode[k] = child;
+    }
+    if (threadIdx.x == 0) kcnt[t] = tot;
     if (threadIdx.x == 0 && tot > 0) {
         atomicMin(&st->q_min, qmn);
         atomicMax(&st->q_max, qmx);
@@ -449,7 +460,9 @@ struct ScoreArgs {
     const double2 *trig;
     int32_t *scores;
     int32_t *tile_done;        // NULL: no tile pass
-    int32_t *q_arr, *rank_arr, *hist;
+    int32_t *q_arr, *rank_arr, *hist;   // kept children per tile: bucket, rank; tile x bucket counts
+    uint4 *knode;              // kept children per tile: packed node
+    int32_t *kcnt;             // kept children per tile: number
     uint32_t *qmask;           // bit q: some tile of the batch holds a child of bucket q
     int32_t *ticket;           // NULL: items round-robin; else [0] next item ticket, [1] workgroups
                                // done (both 0 between launches)
@@ -729,7 +742,8 @@ __device__ void score_items(State *st, const ScoreArgs &A, const MapView &map, c
             }
             __syncthreads();
             if (sh.s_last) {
-                tile_pass<NT>(t, groups, scores, st, C, n_groups, A.q_arr, A.rank_arr, A.hist, A.qmask, sh.sq, sh.sm);
+                tile_pass<NT>(t, groups, scores, st, C, n_groups, A.q_arr, A.rank_arr, A.knode, A.kcnt, A.hist, A.qmask,
+                              sh.sq, sh.sm);
                 if (threadIdx.x == 0) __hip_atomic_store(&tile_done[t], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
         }
@@ -813,6 +827,9 @@ __device__ inline void bucket_space(const Bucket &b, int cnt, int &T, int &f, in
 
 struct PushBufs {
     int32_t *q_arr, *rank_arr, *hist, *totals, *pT, *pf, *pc0, *chunk_next;
+    int32_t *hbase;            // tile x bucket: first rank of the tile's children in the bucket
+    uint4 *knode;
+    int32_t *kcnt;
     uint4 *arena;
     uint32_t *qmask;           // occupied buckets of the batch (set by the tile passes, cleared here)
     int32_t *qlist;            // the occupied buckets in order
@@ -824,7 +841,7 @@ struct PushBufs {
 // kept child is written to its slot and the histogram is cleared.
 template <int NT>
 __device__ void push_finish(State *st, const SearchConst &C, Bucket *bk, const uint4 *groups, const PushBufs &B,
-                            int *sm)
+                            int *sm, int *blk)
 {
     const int tid = threadIdx.x;
     const int q_min = st->q_min, q_max = st->q_max;
@@ -854,22 +871,63 @@ __device__ void push_finish(State *st, const SearchConst &C, Bucket *bk, const u
         n_occ += tot;
     }
     __syncthreads();
-    // per-bucket prefix over tiles (tile-major histogram; loads in blocks of 16 tiles)
-    for (int i = tid; i < n_occ; i += NT) {
-        const int q = B.qlist[i];
-        int acc = 0;
-        for (int t0 = 0; t0 < n_tiles; t0 += 16) {
-            int v[16];
+    // per-bucket prefix over tiles (tile-major histogram, in blocks of 16 tiles)
+    const int n_blk = (n_tiles + 15) / 16;
+    if (n_occ * n_blk <= NT) {
+        // one (bucket, block) pair per thread: every load in one round, block
+        // sums scanned per bucket in LDS, the counts rewritten from registers
+        const int pidx = tid, i = pidx / n_blk, j = pidx - i * n_blk;
+        const bool act = pidx < n_occ * n_blk;
+        const int q = act ? B.qlist[i] : 0;
+        int v[16], sum = 0;
 #pragma unroll
-            for (int u = 0; u < 16; ++u) v[u] = (t0 + u < n_tiles) ? B.hist[(int64_t)(t0 + u) * C.q_count + q] : 0;
+        for (int u = 0; u < 16; ++u) {
+            const int t = j * 16 + u;
+            v[u] = (act && t < n_tiles) ? B.hist[(int64_t)t * C.q_count + q] : 0;
+            sum += v[u];
+        }
+        if (act) blk[pidx] = sum;
+        __syncthreads();
+        if (tid < n_occ) {
+            int acc = 0;
+            for (int jj = 0; jj < n_blk; ++jj) {
+                const int x = blk[tid * n_blk + jj];
+                blk[tid * n_blk + jj] = acc;
+                acc += x;
+            }
+            B.totals[tid] = acc;
+        }
+        __syncthreads();
+        if (act) {
+            int acc = blk[pidx];
 #pragma unroll
             for (int u = 0; u < 16; ++u)
                 if (v[u]) {
-                    B.hist[(int64_t)(t0 + u) * C.q_count + q] = acc;
+                    const int64_t h = (int64_t)(j * 16 + u) * C.q_count + q;
+                    B.hbase[h] = acc;
+                    B.hist[h] = 0;
                     acc += v[u];
                 }
         }
-        B.totals[i] = acc;
+    } else {
+        for (int i = tid; i < n_occ; i += NT) {
+            const int q = B.qlist[i];
+            int acc = 0;
+            for (int t0 = 0; t0 < n_tiles; t0 += 16) {
+                int v[16];
+#pragma unroll
+                for (int u = 0; u < 16; ++u) v[u] = (t0 + u < n_tiles) ? B.hist[(int64_t)(t0 + u) * C.q_count + q] : 0;
+#pragma unroll
+                for (int u = 0; u < 16; ++u)
+                    if (v[u]) {
+                        const int64_t h = (int64_t)(t0 + u) * C.q_count + q;
+                        B.hbase[h] = acc;
+                        B.hist[h] = 0;
+                        acc += v[u];
+                    }
+            }
+            B.totals[i] = acc;
+        }
     }
     __syncthreads();
     const uint64_t tp1 = __builtin_amdgcn_s_memrealtime();
@@ -936,62 +994,38 @@ __device__ void push_finish(State *st, const SearchConst &C, Bucket *bk, const u
         st->t_push_prefix += (int64_t)(tp1 - tp0);
         st->t_push_alloc += (int64_t)(__builtin_amdgcn_s_memrealtime() - tp1);
     }
-    // scatter: the child of rank r in its bucket fills the tail chunk first
-    const int n_slots = n_tiles * kTileSlots;
-    constexpr int kU = 4;                       // slots in flight per thread
-    for (int i0 = tid; i0 < n_slots; i0 += kU * NT) {
-        int qv[kU], rk[kU];
-#pragma unroll
-        for (int u = 0; u < kU; ++u) {
-            const int i = i0 + u * NT;
-            qv[u] = i < n_slots ? B.q_arr[i] : -1;
-            rk[u] = i < n_slots ? B.rank_arr[i] : 0;
-        }
-        int base[kU], Tc[kU], fc[kU], c0[kU];
-        uint4 G[kU];
-#pragma unroll
-        for (int u = 0; u < kU; ++u) {
-            const int i = i0 + u * NT;
-            const bool ok = qv[u] >= 0;
-            const int q = ok ? qv[u] : q_min;             // safe indices for empty slots
-            const int t = ok ? i / kTileSlots : 0;
-            const int g = ok ? t * kTileGroups + (i % kTileSlots) / 8 : 0;
-            base[u] = B.hist[(int64_t)t * C.q_count + q];
-            Tc[u] = B.pT[q - q_min];
-            fc[u] = B.pf[q - q_min];
-            c0[u] = B.pc0[q - q_min];
-            G[u] = groups[g];
-        }
-#pragma unroll
-        for (int u = 0; u < kU; ++u) {
-            if (qv[u] < 0) continue;
-            const int i = i0 + u * NT;
-            const int j = i & 7;
-            const int r = base[u] + rk[u];
-            const int space = Tc[u] >= 0 ? kChunk - fc[u] : 0;
+    // scatter: the child of rank r in its bucket fills the tail chunk first.
+    // Kept children only, from the tiles' compact lists, NT tiles at a time.
+    for (int c0t = 0; c0t < n_tiles; c0t += NT) {
+        const int nt_c = min(NT, n_tiles - c0t);
+        const int kc = tid < nt_c ? B.kcnt[c0t + tid] : 0;
+        int E;
+        const int kincl = block_scan_incl<NT>(kc, sm, &E);
+        if (tid < nt_c) blk[tid] = kincl;
+        __syncthreads();
+        for (int e = tid; e < E; e += NT) {
+            int lo = 0, hi = nt_c - 1;                // the tile holding kept child e
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (blk[mid] > e) hi = mid;
+                else lo = mid + 1;
+            }
+            const int t = c0t + lo;
+            const int64_t k = (int64_t)t * kTileSlots + e - (lo > 0 ? blk[lo - 1] : 0);
+            const int q = B.q_arr[k];
+            const int r = B.hbase[(int64_t)t * C.q_count + q] + B.rank_arr[k];
+            const uint4 node = B.knode[k];
+            const int Tc = B.pT[q - q_min], fc = B.pf[q - q_min];
+            const int space = Tc >= 0 ? kChunk - fc : 0;
             int64_t pos;
-            if (r < space) pos = (int64_t)Tc[u] * kChunk + fc[u] + r;
+            if (r < space) pos = (int64_t)Tc * kChunk + fc + r;
             else {
                 const int r2 = r - space;
-                pos = (int64_t)(c0[u] + r2 / kChunk) * kChunk + (r2 % kChunk);
+                pos = (int64_t)(B.pc0[q - q_min] + r2 / kChunk) * kChunk + (r2 % kChunk);
             }
-            const int jx = (j >> 2) & 1, jy = (j >> 1) & 1, jz = j & 1;
-            const int x = lo16s(G[u].x) + jx, y = hi16s(G[u].x) + jy, z = lo16s(G[u].y) + jz;
-            B.arena[pos] = make_uint4(pack16(x, y), pack16(z, hi16u(G[u].y)), G[u].z, G[u].w & 0xFFu);
+            B.arena[pos] = node;
         }
-    }
-    __syncthreads();
-    for (int i0 = tid; i0 < n_slots; i0 += kU * NT) {
-        int qv[kU], rk[kU];
-#pragma unroll
-        for (int u = 0; u < kU; ++u) {
-            const int i = i0 + u * NT;
-            qv[u] = i < n_slots ? B.q_arr[i] : -1;
-            rk[u] = i < n_slots ? B.rank_arr[i] : 1;
-        }
-#pragma unroll
-        for (int u = 0; u < kU; ++u)
-            if (qv[u] >= 0 && rk[u] == 0) B.hist[(int64_t)((i0 + u * NT) / kTileSlots) * C.q_count + qv[u]] = 0;
+        __syncthreads();
     }
     if (tid == 0) {
         st->chunk_top = chunk_top + (int)total_new;
@@ -1297,7 +1331,7 @@ __device__ void serial_body(State *st, const SearchConst &C, Bucket *bk, uint4 *
 {
     if (ld_agent(&st->done)) return;
     const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
-    if (ld_agent(&st->batch)) push_finish<NT>(st, C, bk, groups, B, sh.sm);
+    if (ld_agent(&st->batch)) push_finish<NT>(st, C, bk, groups, B, sh.sm, sh.g.pre);
     __syncthreads();
     const uint64_t t1 = __builtin_amdgcn_s_memrealtime();
     if (threadIdx.x == 0) st->t_push += (int64_t)(t1 - t0);
@@ -1584,6 +1618,12 @@ struct bbs_workspace {
     int64_t groups_n = 0;
     int32_t *scores = nullptr;
     int64_t scores_n = 0;
+    int32_t *hbase = nullptr;
+    int64_t hbase_n = 0;
+    uint4 *knode = nullptr;
+    int64_t knode_n = 0;
+    int32_t *kcnt = nullptr;
+    int64_t kcnt_n = 0;
     int32_t *q_arr = nullptr;
     int64_t q_arr_n = 0;
     int32_t *rank_arr = nullptr;
@@ -1628,7 +1668,7 @@ namespace {
 void free_ws(bbs_workspace *w)
 {
     void *ptrs[] = {w->arena, w->chunk_next, w->buckets, w->hist, w->totals, w->pT, w->pf, w->pc0, w->groups, w->scores,
-                    w->q_arr, w->rank_arr, w->tile_done, w->ticket, w->scan, w->scan_aos, w->scan_tmp, w->mkeys, w->mhist,
+                    w->q_arr, w->rank_arr, w->hbase, w->knode, w->kcnt, w->tile_done, w->ticket, w->scan, w->scan_aos, w->scan_tmp, w->mkeys, w->mhist,
                     w->trig, w->state, w->maxsq, w->beam, w->prior, w->dstate, w->bar, w->qmask, w->qlist};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -1820,6 +1860,8 @@ ScoreArgs score_args(const Setup &S, bbs_workspace *ws, int32_t n_fixed, bool ti
     A.tile_done = tile_pass ? ws->tile_done : nullptr;
     A.q_arr = ws->q_arr;
     A.rank_arr = ws->rank_arr;
+    A.knode = ws->knode;
+    A.kcnt = ws->kcnt;
     A.hist = ws->hist;
     A.qmask = ws->qmask;
     A.ticket = nullptr;
@@ -2003,7 +2045,8 @@ extern "C" bbs_status bbs_localize(const bbs_map *map, bbs_workspace *ws, const 
     const int64_t qn = std::max<int32_t>(C.q_count, 1);
     const int64_t chunk_cap = std::max<int64_t>(ws->queue_nodes / kChunk, 16);
     if (ensure(ws->groups, ws->groups_n, cap_groups) || ensure(ws->scores, ws->scores_n, 8 * cap_groups) ||
-        ensure(ws->q_arr, ws->q_arr_n, n_tiles * kTileSlots) ||
+        ensure(ws->q_arr, ws->q_arr_n, n_tiles * kTileSlots) || ensure(ws->knode, ws->knode_n, n_tiles * kTileSlots) ||
+        ensure(ws->kcnt, ws->kcnt_n, n_tiles) || ensure(ws->hbase, ws->hbase_n, n_tiles * qn) ||
         ensure(ws->rank_arr, ws->rank_arr_n, n_tiles * kTileSlots) || ensure(ws->totals, ws->totals_n, qn) ||
         ensure(ws->pT, ws->pT_n, qn) || ensure(ws->pf, ws->pf_n, qn) || ensure(ws->pc0, ws->pc0_n, qn) ||
         ensure(ws->buckets, ws->buckets_n, qn) || ensure(ws->arena, ws->arena_n, chunk_cap * kChunk) ||
@@ -2064,6 +2107,9 @@ extern "C" bbs_status bbs_localize(const bbs_map *map, bbs_workspace *ws, const 
     B.pc0 = ws->pc0;
     B.chunk_next = ws->chunk_next;
     B.arena = ws->arena;
+    B.hbase = ws->hbase;
+    B.knode = ws->knode;
+    B.kcnt = ws->kcnt;
     auto serial = [&](int do_gather) {
         k_serial<<<1, kSerialThreads, 0, s>>>(ws->state, C, ws->buckets, ws->groups, ws->scores, B, do_gather);
     };
