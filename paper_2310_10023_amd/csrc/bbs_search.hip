@@ -159,10 +159,43 @@ inline int grid_for(int64_t n, int threads, int cap)
 
 // ------------------------------------------------------------------ block helpers
 
+// Inclusive scans over the 64 lanes of a wave with DPP lane moves (row
+// shifts by 1, 2, 4, 8 inside each row of 16 lanes, then the row-15 and
+// row-31 broadcasts to the later rows): six VALU steps, no LDS round trips.
+// A lane whose source lies outside its row, or a row left out by the row
+// mask, takes the identity.
+__device__ inline int wave_scan_add(int v)
+{
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);   // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);   // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);   // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);   // row_shr:8
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);   // row_bcast:15 to rows 1, 3
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);   // row_bcast:31 to rows 2, 3
+    return v;
+}
+
+__device__ inline int wave_scan_min(int v)
+{
+    v = min(v, __builtin_amdgcn_update_dpp(INT_MAX, v, 0x111, 0xf, 0xf, false));
+    v = min(v, __builtin_amdgcn_update_dpp(INT_MAX, v, 0x112, 0xf, 0xf, false));
+    v = min(v, __builtin_amdgcn_update_dpp(INT_MAX, v, 0x114, 0xf, 0xf, false));
+    v = min(v, __builtin_amdgcn_update_dpp(INT_MAX, v, 0x118, 0xf, 0xf, false));
+    v = min(v, __builtin_amdgcn_update_dpp(INT_MAX, v, 0x142, 0xa, 0xf, false));
+    v = min(v, __builtin_amdgcn_update_dpp(INT_MAX, v, 0x143, 0xc, 0xf, false));
+    return v;
+}
+
+// Sum over the wave, the same in every lane (all 64 lanes active).
+__device__ inline int wave_sum(int v)
+{
+    return __builtin_amdgcn_readlane(wave_scan_add(v), 63);
+}
+
 template <int N>
 __device__ inline int block_min_int(int v, int *sm)
 {
-    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+    v = __builtin_amdgcn_readlane(wave_scan_min(v), 63);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     __syncthreads();
     if (lane == 0) sm[wave] = v;
@@ -177,10 +210,7 @@ template <int N>
 __device__ inline int block_scan_incl(int v, int *sm, int *total)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int o = 1; o < 64; o <<= 1) {
-        int t = __shfl_up(v, o);
-        if (lane >= o) v += t;
-    }
+    v = wave_scan_add(v);
     __syncthreads();
     if (lane == 63) sm[wave] = v;
     __syncthreads();
@@ -710,8 +740,7 @@ __device__ void score_items(State *st, const ScoreArgs &A, const MapView &map, c
         }
         int c[8] = {c0, c1, c2, c3, c4, c5, c6, c7};
 #pragma unroll
-        for (int j = 0; j < 8; ++j)
-            for (int o = 32; o > 0; o >>= 1) c[j] += __shfl_xor(c[j], o);
+        for (int j = 0; j < 8; ++j) c[j] = wave_sum(c[j]);
         const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
         if (lane == 0)
             for (int j = 0; j < 8; ++j) red[wave][j] = c[j];
