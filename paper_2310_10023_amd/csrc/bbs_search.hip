@@ -30,7 +30,7 @@ constexpr int kScoreThreads = 256;
 // Resident scoring workgroups per CU: the kernel's scalar registers allow six
 // (the occupancy query, which reports seven, does not see that; workgroups
 // launched beyond six per CU only start once the first ones finish).
-constexpr int kScoreWgPerCu = 6;
+constexpr int kScoreWgPerCu = 5;
 constexpr int kUnroll = 4;                       // scan points in flight per thread in the scoring loop
 constexpr int kScanPad = 1024 * kUnroll;          // scan padding: the largest scoring round (1024 threads)
 constexpr int kTileGroups = 32;                  // push tile: 32 groups = 256 node slots
@@ -476,7 +476,7 @@ __device__ void tile_pass(int t, const uint4 *groups, int32_t *scores, State *st
 
 template <int NT>
 struct ScoreSmem {
-    int red[NT / 64][8];
+    int red[NT / 64][16];
     int sq[kTileSlots];
     int sm[NT / 64];
     int s_last;
@@ -509,6 +509,208 @@ __device__ inline float scale_to_cells(float p, const SearchConst &C)
     return p / C.r;
 }
 
+// Constants of one group for the dense-grid loop (uniform over the workgroup).
+struct DenseGroup {
+    float R[9];
+    const uint2 *dense;
+    uint32_t nx, ny;
+    uint32_t lim[3];          // border layer index per axis
+    int32_t off[3];           // (group base - 4 box minimum) 2^l per axis
+    uint32_t level;
+};
+
+// Dense-grid scoring of the points [k_begin, k_end) against NG groups at once:
+// each thread keeps KU points in flight and tests every loaded point against
+// every group, so the scan is read once for all of them.
+//
+// Branch-free: every scan and grid load of a round is issued before any
+// result is used.  Per axis, w = floor(R s / r) + (group base - 4 box
+// minimum) 2^l is the level-0 coordinate of the level-l voxel relative to the
+// box (adding a multiple of 2^l commutes with the floor of the shift):
+// w >> (l + 2) is the x or y brick and w >> l the z voxel, clamped into the
+// grid's empty border layer when outside the box (a negative w is a large
+// unsigned value), and bits l, l+1 of w the x or y voxel inside the brick,
+// which picks the 32-bit window of the column.  The eight counts of a group
+// are bit-sliced into two 64-bit words, members 0..3 of the window bits 0, 5,
+// 25, 30 and members 4..7 of bits 1, 6, 26, 31, in fields of at least 5 bits,
+// folded every kFold rounds.
+template <int RM, int NT, int NG, int KU>
+__device__ inline void dense_loop(const float *__restrict__ X, const float *__restrict__ Y,
+                                  const float *__restrict__ Z, int k_begin, int k_end, const SearchConst &C,
+                                  const DenseGroup (&dg)[NG], int (&cnt)[NG][8])
+{
+    constexpr int kStepL = NT * KU;
+    constexpr int kFold = 31 / KU;
+    constexpr uint32_t kSliceA = 0x42000021u;          // window bits 0, 5, 25, 30
+    constexpr uint32_t kSliceB = kSliceA << 1;         // window bits 1, 6, 26, 31
+    uint64_t acc_a[NG], acc_b[NG];
+#pragma unroll
+    for (int g = 0; g < NG; ++g) acc_a[g] = acc_b[g] = 0;
+    int rounds = 0;
+    auto fold = [&]() {
+#pragma unroll
+        for (int g = 0; g < NG; ++g) {
+            cnt[g][0] += (int)(acc_a[g] & 31u);
+            cnt[g][2] += (int)((acc_a[g] >> 5) & 0xFFFFFu);
+            cnt[g][1] += (int)((acc_a[g] >> 25) & 31u);
+            cnt[g][3] += (int)(acc_a[g] >> 30);
+            cnt[g][4] += (int)((acc_b[g] >> 1) & 31u);
+            cnt[g][6] += (int)((acc_b[g] >> 6) & 0xFFFFFu);
+            cnt[g][5] += (int)((acc_b[g] >> 26) & 31u);
+            cnt[g][7] += (int)(acc_b[g] >> 31);
+            acc_a[g] = acc_b[g] = 0;
+        }
+    };
+    for (int kb = k_begin + (int)threadIdx.x; kb < k_end; kb += kStepL) {
+        // 32-bit byte offsets (K <= 2^24), one per round; the KU points sit
+        // at fixed distances from it
+        const uint32_t koff = (uint32_t)kb * 4u;
+        float sx[KU], sy[KU], sz[KU];
+#pragma unroll
+        for (int u = 0; u < KU; ++u) {
+            sx[u] = *reinterpret_cast<const float *>(reinterpret_cast<const char *>(X) + koff + u * NT * 4);
+            sy[u] = *reinterpret_cast<const float *>(reinterpret_cast<const char *>(Y) + koff + u * NT * 4);
+            sz[u] = *reinterpret_cast<const float *>(reinterpret_cast<const char *>(Z) + koff + u * NT * 4);
+        }
+        uint32_t idx[NG][KU], i0[NG][KU];
+#pragma unroll
+        for (int g = 0; g < NG; ++g)
+#pragma unroll
+            for (int u = 0; u < KU; ++u) {
+                uint32_t rb[3], f[2];
+#pragma unroll
+                for (int row = 0; row < 3; ++row) {
+                    float t0 = dg[g].R[3 * row + 0] * sx[u];
+                    float t1 = dg[g].R[3 * row + 1] * sy[u];
+                    float t2 = dg[g].R[3 * row + 2] * sz[u];
+                    float p = (t0 + t1) + t2;
+                    float q = scale_to_cells<RM>(p, C);
+                    // floor and convert in one instruction (equal to floorf then
+                    // conversion for the finite, in-range q here; denormals kept)
+                    int32_t fl;
+                    asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(fl) : "v"(q));
+                    const int32_t w = fl + dg[g].off[row];
+                    const uint32_t shr = row < 2 ? dg[g].level + 2u : dg[g].level;
+                    rb[row] = min((uint32_t)(w >> shr), dg[g].lim[row]);
+                    if (row < 2) f[row] = __builtin_amdgcn_ubfe((uint32_t)w, dg[g].level, 2u);
+                }
+                // z voxels x y bricks <= 2^24, x bricks <= 4096: 24-bit products are exact
+                idx[g][u] = mad24(mad24(rb[2], dg[g].ny, rb[1]), dg[g].nx, rb[0]);
+                i0[g][u] = f[1] * 5u + f[0];   // 0 .. 18
+            }
+        uint2 bits[NG][KU];
+#pragma unroll
+        for (int g = 0; g < NG; ++g)
+#pragma unroll
+            for (int u = 0; u < KU; ++u)     // grid entries <= 2^28: byte offset < 2^31
+                bits[g][u] =
+                    *reinterpret_cast<const uint2 *>(reinterpret_cast<const char *>(dg[g].dense) + idx[g][u] * 8u);
+#pragma unroll
+        for (int g = 0; g < NG; ++g)
+#pragma unroll
+            for (int u = 0; u < KU; ++u) {
+                const uint32_t win = __builtin_amdgcn_alignbit(bits[g][u].y, bits[g][u].x, i0[g][u]);
+                // member j = 4 jx + 2 jy + jz sits at window bit 25 jz + 5 jy + jx
+                acc_a[g] += (uint64_t)(win & kSliceA);
+                acc_b[g] += (uint64_t)(win & kSliceB);
+            }
+        if (++rounds == kFold) {
+            fold();
+            rounds = 0;
+        }
+    }
+    fold();
+}
+
+// Hash-table scoring of the points [k_begin, k_end) against one group (a
+// level without a dense grid): the brick key is probed with linear probing,
+// kUnroll points per thread in flight.
+template <int RM, int NT>
+__device__ inline void hash_loop(const float *__restrict__ X, const float *__restrict__ Y,
+                                 const float *__restrict__ Z, int k_begin, int k_end, const SearchConst &C,
+                                 const LevelView &lv, const float (&R)[9], int bx, int by, int bz, int level,
+                                 int (&cnt)[8])
+{
+    const uint2 *__restrict__ keys = lv.keys;
+    const uint4 *__restrict__ bitsv = lv.bits;
+    const uint32_t cap_mask = lv.cap_mask;
+    const uint32_t ex = (uint32_t)(lv.bmax[0] - lv.bmin[0]);
+    const uint32_t ey = (uint32_t)(lv.bmax[1] - lv.bmin[1]);
+    const uint32_t ez = (uint32_t)(lv.bmax[2] - lv.bmin[2]);
+    for (int kb = k_begin + (int)threadIdx.x; kb < k_end; kb += NT * kUnroll) {
+        uint32_t h[kUnroll], klo[kUnroll], khi[kUnroll];
+        int i0[kUnroll];
+        int state[kUnroll];   // 0: miss, 1: probing, 2: found
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const int k = kb + u * NT;
+            state[u] = 0;
+            h[u] = 0;
+            klo[u] = khi[u] = 0;
+            i0[u] = 0;
+            if (k < k_end) {
+                const float sx = X[k], sy = Y[k], sz = Z[k];
+                int32_t w[3];
+#pragma unroll
+                for (int row = 0; row < 3; ++row) {
+                    float t0 = R[3 * row + 0] * sx;
+                    float t1 = R[3 * row + 1] * sy;
+                    float t2 = R[3 * row + 2] * sz;
+                    float p = (t0 + t1) + t2;
+                    float q = scale_to_cells<RM>(p, C);
+                    w[row] = ((int32_t)floorf(q) >> level);
+                }
+                const int32_t wx = w[0] + bx, wy = w[1] + by, wz = w[2] + bz;
+                const int32_t Bx = wx >> 2, By = wy >> 2, Bz = wz >> 2;
+                const uint32_t rx = (uint32_t)(Bx - lv.bmin[0]), ry = (uint32_t)(By - lv.bmin[1]),
+                               rz = (uint32_t)(Bz - lv.bmin[2]);
+                if (rx <= ex && ry <= ey && rz <= ez) {
+                    i0[u] = ((wz & 3) * 5 + (wy & 3)) * 5 + (wx & 3);   // 0 .. 93
+                    state[u] = 1;
+                    klo[u] = brick_key_lo(Bx, By, Bz);
+                    khi[u] = brick_key_hi(Bx, By, Bz);
+                    h[u] = brick_hash(Bx, By, Bz) & cap_mask;
+                }
+            }
+        }
+        for (;;) {
+            bool again = false;
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                if (state[u] == 1) {
+                    const uint2 kk = keys[h[u]];
+                    if (kk.x == klo[u] && kk.y == khi[u]) state[u] = 2;
+                    else if (kk.x == kEmptyLo && kk.y == kEmptyHi) state[u] = 0;
+                    else {
+                        h[u] = (h[u] + 1) & cap_mask;
+                        again = true;
+                    }
+                }
+            }
+            if (!again) break;
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            if (state[u] == 2) {
+                const uint4 bits = bitsv[h[u]];
+                const int word = i0[u] >> 5;
+                const uint32_t lo = word == 0 ? bits.x : (word == 1 ? bits.y : bits.z);
+                const uint32_t hi = word == 0 ? bits.y : (word == 1 ? bits.z : bits.w);
+                const uint32_t win = __builtin_amdgcn_alignbit(hi, lo, (uint32_t)(i0[u] & 31));
+                // member j = 4 jx + 2 jy + jz sits at window bit 25 jz + 5 jy + jx
+                cnt[0] += (win >> 0) & 1u;
+                cnt[1] += (win >> 25) & 1u;
+                cnt[2] += (win >> 5) & 1u;
+                cnt[3] += (win >> 30) & 1u;
+                cnt[4] += (win >> 1) & 1u;
+                cnt[5] += (win >> 26) & 1u;
+                cnt[6] += (win >> 6) & 1u;
+                cnt[7] += (win >> 31) & 1u;
+            }
+        }
+    }
+}
+
 template <int RM, int NT>
 __device__ void score_items(State *st, const ScoreArgs &A, const MapView &map, const SearchConst &C,
                             ScoreSmem<NT> &sh)
@@ -526,17 +728,18 @@ __device__ void score_items(State *st, const ScoreArgs &A, const MapView &map, c
     const int K = C.K;
     constexpr int kStep = NT * kUnroll;                 // points of one round of the workgroup
     const int max_s = (K + kStep - 1) / kStep;
-    // Work items.  The grid is as large as the device holds at once.  Groups
-    // run whole in full rounds of the grid; the groups of the last, partial
-    // round are split into point slices so that they fill the grid once more
-    // (or all groups are split score_items / n_groups ways when that asks for
-    // more).  Items go round-robin over the workgroups, or, with a ticket
-    // counter, to whichever workgroup asks next.
+    // Work items.  A large batch is scored two groups to an item, so that a
+    // workgroup reads every scan point once for both and pays the per-item
+    // latency (group, rotations, count reduction, atomics) once per pair; a
+    // batch too small to fill the grid is split score_items / n_groups ways
+    // into point slices of single groups.  The grid is as large as the device
+    // holds at once; items go round-robin over the workgroups, or, with a
+    // ticket counter, to whichever workgroup asks next.
     const int P = (int)gridDim.x;
     const int s_min = min(max_s, max(1, (C.score_items + n_groups - 1) / n_groups));
-    const int n_full = s_min > 1 ? 0 : n_groups - n_groups % P;
-    const int s_tail = s_min > 1 ? s_min : min(max_s, max(1, P / max(1, n_groups - n_full)));
-    const int64_t n_items = n_full + (int64_t)(n_groups - n_full) * s_tail;
+    const bool pairs = s_min == 1;
+    const int S = pairs ? 1 : s_min;
+    const int64_t n_items = pairs ? (n_groups + 1) / 2 : (int64_t)n_groups * S;
     int32_t *ticket = A.ticket;
     int64_t item = blockIdx.x;
     while (item < n_items) {
@@ -545,205 +748,88 @@ __device__ void score_items(State *st, const ScoreArgs &A, const MapView &map, c
         // the persistent loop, whose grid is one workgroup per CU)
         int nxt = 0;
         if (ticket && threadIdx.x == 0) nxt = atomicAdd(&ticket[0], 1);
-        int g, sp, S;
-        if (item < n_full) {
-            g = (int)item;
-            sp = 0;
-            S = 1;
+        int gs[2], ng, k_begin, k_end;
+        if (pairs) {
+            gs[0] = 2 * (int)item;
+            ng = gs[0] + 1 < n_groups ? 2 : 1;
+            gs[1] = gs[0] + ng - 1;
+            k_begin = 0;
+            k_end = K;
         } else {
-            const int j = (int)(item - n_full);
-            g = n_full + j / s_tail;
-            sp = j % s_tail;
-            S = s_tail;
+            gs[0] = gs[1] = (int)(item / S);
+            ng = 1;
+            const int sp = (int)(item % S);
+            // slices are whole rounds, so only the last one is ragged; its tail
+            // runs over the scan padding (points that fall outside every box)
+            const int chunk = ((K + S - 1) / S + kStep - 1) / kStep * kStep;
+            k_begin = min(K, sp * chunk);
+            k_end = min(K, k_begin + chunk);
         }
-        // slices are whole rounds, so only the last one is ragged; its tail runs
-        // over the scan padding (points that fall outside every box)
-        const int chunk = ((K + S - 1) / S + kStep - 1) / kStep * kStep;
-        const int k_begin = min(K, sp * chunk), k_end = min(K, k_begin + chunk);
-        // the group is the same for every lane of the item: keep it in scalar registers
-        const uint4 Gv = groups[g];
-        const uint4 G = make_uint4(__builtin_amdgcn_readfirstlane(Gv.x), __builtin_amdgcn_readfirstlane(Gv.y),
-                                   __builtin_amdgcn_readfirstlane(Gv.z), __builtin_amdgcn_readfirstlane(Gv.w));
-        const int level = (int)(G.w & 0xFF);
-        const int bx = lo16s(G.x), by = hi16s(G.x), bz = lo16s(G.y);
-        float R[9];
-        rotation(trig, C, level, hi16u(G.y), lo16u(G.z), hi16u(G.z), R);
-        const LevelView lv = map.lv[level];
-        const uint2 *__restrict__ keys = lv.keys;
-        const bool use_dense = lv.dense != nullptr;      // uniform over the workgroup
-        const uint4 *__restrict__ bitsv = lv.bits;
-        const uint32_t cap_mask = lv.cap_mask;
-        const uint32_t ex = (uint32_t)(lv.bmax[0] - lv.bmin[0]);
-        const uint32_t ey = (uint32_t)(lv.bmax[1] - lv.bmin[1]);
-        const uint32_t ez = (uint32_t)(lv.bmax[2] - lv.bmin[2]);
-        int c0 = 0, c1 = 0, c2 = 0, c3 = 0, c4 = 0, c5 = 0, c6 = 0, c7 = 0;
-        if (use_dense) {
-            // Branch-free: every scan and grid load of the kUnroll points is
-            // issued before any result is used.  Per axis, w = floor(R s / r)
-            // + (group base - 4 box minimum) 2^l is the level-0 coordinate of
-            // the level-l voxel relative to the box (adding a multiple of 2^l
-            // commutes with the floor of the shift): w >> (l + 2) is the x or y
-            // brick and w >> l the z voxel, clamped into the grid's empty
-            // border layer when outside the box (a negative w is a large
-            // unsigned value), and bits l, l+1 of w the x or y voxel inside
-            // the brick, which picks the 32-bit window of the column.  The
-            // eight counts are bit-sliced into two 64-bit words, members 0..3
-            // of the window bits 0, 5, 25, 30 and members 4..7 of bits 1, 6,
-            // 26, 31, in fields of at least 5 bits, folded every kFold rounds.
-            constexpr int kFold = 31 / kUnroll;
-            constexpr uint32_t kSliceA = 0x42000021u;          // window bits 0, 5, 25, 30
-            constexpr uint32_t kSliceB = kSliceA << 1;         // window bits 1, 6, 26, 31
-            uint64_t acc_a = 0, acc_b = 0;
-            int rounds = 0;
-            const uint2 *__restrict__ dense = lv.dense;
-            const uint32_t nx = (uint32_t)lv.nx, ny = (uint32_t)lv.ny;
-            const uint32_t lim[3] = {ex + 1, ey + 1, 4u * (ez + 1)};   // border layer index per axis
+        // the groups are the same for every lane of the item: scalar registers
+        DenseGroup dg[2];
+        int lvl[2], base[2][3];
+        bool dense[2];
+        float R[2][9];
+#pragma unroll
+        for (int gi = 0; gi < 2; ++gi) {
+            const uint4 Gv = groups[gs[gi]];
+            const uint4 G = make_uint4(__builtin_amdgcn_readfirstlane(Gv.x), __builtin_amdgcn_readfirstlane(Gv.y),
+                                       __builtin_amdgcn_readfirstlane(Gv.z), __builtin_amdgcn_readfirstlane(Gv.w));
+            const int level = (int)(G.w & 0xFF);
+            lvl[gi] = level;
+            base[gi][0] = lo16s(G.x);
+            base[gi][1] = hi16s(G.x);
+            base[gi][2] = lo16s(G.y);
+            rotation(trig, C, level, hi16u(G.y), lo16u(G.z), hi16u(G.z), R[gi]);
+            const LevelView &lv = map.lv[level];
+            dense[gi] = lv.dense != nullptr;
+#pragma unroll
+            for (int e = 0; e < 9; ++e) dg[gi].R[e] = R[gi][e];
+            dg[gi].dense = lv.dense;
+            dg[gi].nx = (uint32_t)lv.nx;
+            dg[gi].ny = (uint32_t)lv.ny;
+            dg[gi].lim[0] = (uint32_t)(lv.bmax[0] - lv.bmin[0]) + 1u;
+            dg[gi].lim[1] = (uint32_t)(lv.bmax[1] - lv.bmin[1]) + 1u;
+            dg[gi].lim[2] = 4u * ((uint32_t)(lv.bmax[2] - lv.bmin[2]) + 1u);
             const int32_t scale = 1 << level;
-            const int32_t off[3] = {(bx - 4 * lv.bmin[0]) * scale, (by - 4 * lv.bmin[1]) * scale,
-                                    (bz - 4 * lv.bmin[2]) * scale};
-            const uint32_t shr[3] = {(uint32_t)level + 2u, (uint32_t)level + 2u, (uint32_t)level};
-            auto fold = [&]() {
-                c0 += (int)(acc_a & 31u);
-                c2 += (int)((acc_a >> 5) & 0xFFFFFu);
-                c1 += (int)((acc_a >> 25) & 31u);
-                c3 += (int)(acc_a >> 30);
-                c4 += (int)((acc_b >> 1) & 31u);
-                c6 += (int)((acc_b >> 6) & 0xFFFFFu);
-                c5 += (int)((acc_b >> 26) & 31u);
-                c7 += (int)(acc_b >> 31);
-                acc_a = acc_b = 0;
-            };
-            for (int kb = k_begin + (int)threadIdx.x; kb < k_end; kb += kStep) {
-                // 32-bit byte offsets (K <= 2^24), one per round; the kUnroll
-                // points sit at fixed distances from it
-                const uint32_t koff = (uint32_t)kb * 4u;
-                float sx[kUnroll], sy[kUnroll], sz[kUnroll];
 #pragma unroll
-                for (int u = 0; u < kUnroll; ++u) {
-                    sx[u] = *reinterpret_cast<const float *>(reinterpret_cast<const char *>(X) + koff + u * NT * 4);
-                    sy[u] = *reinterpret_cast<const float *>(reinterpret_cast<const char *>(Y) + koff + u * NT * 4);
-                    sz[u] = *reinterpret_cast<const float *>(reinterpret_cast<const char *>(Z) + koff + u * NT * 4);
-                }
-                uint32_t idx[kUnroll], i0[kUnroll];
+            for (int a = 0; a < 3; ++a) dg[gi].off[a] = (base[gi][a] - 4 * lv.bmin[a]) * scale;
+            dg[gi].level = (uint32_t)level;
+        }
+        int cnt[2][8];
 #pragma unroll
-                for (int u = 0; u < kUnroll; ++u) {
-                    uint32_t rb[3], f[2];
+        for (int gi = 0; gi < 2; ++gi)
 #pragma unroll
-                    for (int row = 0; row < 3; ++row) {
-                        float t0 = R[3 * row + 0] * sx[u];
-                        float t1 = R[3 * row + 1] * sy[u];
-                        float t2 = R[3 * row + 2] * sz[u];
-                        float p = (t0 + t1) + t2;
-                        float q = scale_to_cells<RM>(p, C);
-                        // floor and convert in one instruction (equal to floorf then
-                        // conversion for the finite, in-range q here; denormals kept)
-                        int32_t fl;
-                        asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(fl) : "v"(q));
-                        const int32_t w = fl + off[row];
-                        rb[row] = min((uint32_t)(w >> shr[row]), lim[row]);
-                        if (row < 2) f[row] = __builtin_amdgcn_ubfe((uint32_t)w, (uint32_t)level, 2u);
-                    }
-                    // z voxels x y bricks <= 2^24, x bricks <= 4096: 24-bit products are exact
-                    idx[u] = mad24(mad24(rb[2], ny, rb[1]), nx, rb[0]);
-                    i0[u] = f[1] * 5u + f[0];   // 0 .. 18
-                }
-                uint2 bits[kUnroll];
-#pragma unroll
-                for (int u = 0; u < kUnroll; ++u)     // grid entries <= 2^28: byte offset < 2^31
-                    bits[u] = *reinterpret_cast<const uint2 *>(reinterpret_cast<const char *>(dense) + idx[u] * 8u);
-#pragma unroll
-                for (int u = 0; u < kUnroll; ++u) {
-                    const uint32_t win = __builtin_amdgcn_alignbit(bits[u].y, bits[u].x, i0[u]);
-                    // member j = 4 jx + 2 jy + jz sits at window bit 25 jz + 5 jy + jx
-                    acc_a += (uint64_t)(win & kSliceA);
-                    acc_b += (uint64_t)(win & kSliceB);
-                }
-                if (++rounds == kFold) {
-                    fold();
-                    rounds = 0;
-                }
-            }
-            fold();
+            for (int j = 0; j < 8; ++j) cnt[gi][j] = 0;
+        if (ng == 2 && dense[0] && dense[1]) {
+            dense_loop<RM, NT, 2, kUnroll / 2>(X, Y, Z, k_begin, k_end, C, dg, cnt);
         } else {
-            for (int kb = k_begin + (int)threadIdx.x; kb < k_end; kb += NT * kUnroll) {
-                uint32_t h[kUnroll], klo[kUnroll], khi[kUnroll];
-                int i0[kUnroll];
-                int state[kUnroll];   // 0: miss, 1: probing, 2: found
-    #pragma unroll
-                for (int u = 0; u < kUnroll; ++u) {
-                    const int k = kb + u * NT;
-                    state[u] = 0;
-                    h[u] = 0;
-                    klo[u] = khi[u] = 0;
-                    i0[u] = 0;
-                    if (k < k_end) {
-                        const float sx = X[k], sy = Y[k], sz = Z[k];
-                        int32_t w[3];
-    #pragma unroll
-                        for (int row = 0; row < 3; ++row) {
-                            float t0 = R[3 * row + 0] * sx;
-                            float t1 = R[3 * row + 1] * sy;
-                            float t2 = R[3 * row + 2] * sz;
-                            float p = (t0 + t1) + t2;
-                            float q = scale_to_cells<RM>(p, C);
-                            w[row] = ((int32_t)floorf(q) >> level);
-                        }
-                        const int32_t wx = w[0] + bx, wy = w[1] + by, wz = w[2] + bz;
-                        const int32_t Bx = wx >> 2, By = wy >> 2, Bz = wz >> 2;
-                        const uint32_t rx = (uint32_t)(Bx - lv.bmin[0]), ry = (uint32_t)(By - lv.bmin[1]),
-                                       rz = (uint32_t)(Bz - lv.bmin[2]);
-                        if (rx <= ex && ry <= ey && rz <= ez) {
-                            i0[u] = ((wz & 3) * 5 + (wy & 3)) * 5 + (wx & 3);   // 0 .. 93
-                            state[u] = 1;
-                            klo[u] = brick_key_lo(Bx, By, Bz);
-                            khi[u] = brick_key_hi(Bx, By, Bz);
-                            h[u] = brick_hash(Bx, By, Bz) & cap_mask;
-                        }
-                    }
-                }
-                for (;;) {
-                    bool again = false;
-    #pragma unroll
-                    for (int u = 0; u < kUnroll; ++u) {
-                        if (state[u] == 1) {
-                            const uint2 kk = keys[h[u]];
-                            if (kk.x == klo[u] && kk.y == khi[u]) state[u] = 2;
-                            else if (kk.x == kEmptyLo && kk.y == kEmptyHi) state[u] = 0;
-                            else {
-                                h[u] = (h[u] + 1) & cap_mask;
-                                again = true;
-                            }
-                        }
-                    }
-                    if (!again) break;
-                }
-    #pragma unroll
-                for (int u = 0; u < kUnroll; ++u) {
-                    if (state[u] == 2) {
-                        const uint4 bits = bitsv[h[u]];
-                        const int word = i0[u] >> 5;
-                        const uint32_t lo = word == 0 ? bits.x : (word == 1 ? bits.y : bits.z);
-                        const uint32_t hi = word == 0 ? bits.y : (word == 1 ? bits.z : bits.w);
-                        const uint32_t win = __builtin_amdgcn_alignbit(hi, lo, (uint32_t)(i0[u] & 31));
-                        // member j = 4 jx + 2 jy + jz sits at window bit 25 jz + 5 jy + jx
-                        c0 += (win >> 0) & 1u;
-                        c1 += (win >> 25) & 1u;
-                        c2 += (win >> 5) & 1u;
-                        c3 += (win >> 30) & 1u;
-                        c4 += (win >> 1) & 1u;
-                        c5 += (win >> 26) & 1u;
-                        c6 += (win >> 6) & 1u;
-                        c7 += (win >> 31) & 1u;
-                    }
+#pragma unroll
+            for (int gi = 0; gi < 2; ++gi) {
+                if (gi >= ng) break;
+                if (dense[gi]) {
+                    const DenseGroup one[1] = {dg[gi]};
+                    int c1[1][8] = {{0, 0, 0, 0, 0, 0, 0, 0}};
+                    dense_loop<RM, NT, 1, kUnroll>(X, Y, Z, k_begin, k_end, C, one, c1);
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) cnt[gi][j] = c1[0][j];
+                } else {
+                    hash_loop<RM, NT>(X, Y, Z, k_begin, k_end, C, map.lv[lvl[gi]], R[gi], base[gi][0], base[gi][1],
+                                      base[gi][2], lvl[gi], cnt[gi]);
                 }
             }
         }
-        int c[8] = {c0, c1, c2, c3, c4, c5, c6, c7};
-#pragma unroll
-        for (int j = 0; j < 8; ++j) c[j] = wave_sum(c[j]);
         const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-        if (lane == 0)
-            for (int j = 0; j < 8; ++j) red[wave][j] = c[j];
+#pragma unroll
+        for (int gi = 0; gi < 2; ++gi) {
+            if (gi < ng) {
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const int v = wave_sum(cnt[gi][j]);
+                    if (lane == 0) red[wave][8 * gi + j] = v;
+                }
+            }
+        }
         __syncthreads();
         // Hand-off to the tile pass without a device-scope fence (which on this
         // GPU writes back and invalidates the XCD's L2): the scores are added
@@ -751,21 +837,22 @@ __device__ void score_items(State *st, const ScoreArgs &A, const MapView &map, c
         // wait for outstanding memory operations is over; only then is the
         // tile counter bumped, and the tile pass reads the scores with atomics
         // too, at the same coherence point.
-        if (threadIdx.x < 8) {
+        if (threadIdx.x < 8 * ng) {
             int sum = 0;
             for (int wv = 0; wv < NT / 64; ++wv) sum += red[wv][threadIdx.x];
-            const int old = __hip_atomic_fetch_add(&scores[8 * (int64_t)g + threadIdx.x], sum, __ATOMIC_RELAXED,
+            const int g = threadIdx.x >= 8 ? gs[1] : gs[0];
+            const int old = __hip_atomic_fetch_add(&scores[8 * (int64_t)g + (threadIdx.x & 7)], sum, __ATOMIC_RELAXED,
                                                    __HIP_MEMORY_SCOPE_AGENT);
             asm volatile("" ::"v"(old));          // keep the returning form of the atomic
         }
         __syncthreads();
         if (tile_done) {
             // the last workgroup to finish a tile sorts it into queue buckets
-            const int t = g / kTileGroups;
+            // (a pair never straddles two tiles: tiles hold an even number of groups)
+            const int t = gs[0] / kTileGroups;
             if (threadIdx.x == 0) {
                 const int t0 = t * kTileGroups, te = min(n_groups, t0 + kTileGroups);
-                const int whole = min(max(n_full - t0, 0), te - t0);
-                const int in_tile = whole + (te - t0 - whole) * s_tail;
+                const int in_tile = pairs ? (te - t0 + 1) / 2 : (te - t0) * S;
                 const int prev = atomicAdd(&tile_done[t], 1);
                 sh.s_last = (prev == in_tile - 1);
             }
