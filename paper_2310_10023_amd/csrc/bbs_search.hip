@@ -27,9 +27,11 @@ namespace bbs {
 namespace {
 
 constexpr int kScoreThreads = 256;
-// Resident scoring workgroups per CU: the kernel's scalar registers allow six
-// (the occupancy query, which reports seven, does not see that; workgroups
-// launched beyond six per CU only start once the first ones finish).
+// Resident scoring workgroups per CU: five (93 vector registers a lane).  The
+// grid is sized from this, not from the occupancy query alone, which counts
+// fewer registers than the hardware allots here (it reported seven workgroups
+// where six ran for an earlier version of the kernel); workgroups launched
+// beyond the resident number only start once the first ones finish.
 constexpr int kScoreWgPerCu = 5;
 constexpr int kUnroll = 4;                       // scan points in flight per thread in the scoring loop
 constexpr int kScanPad = 1024 * kUnroll;          // scan padding: the largest scoring round (1024 threads)
