@@ -1473,7 +1473,7 @@ __global__ __launch_bounds__(kSerialThreads) void k_serial(State *st, SearchCons
 // ------------------------------------------------------------------ persistent search loop
 
 constexpr int kPersistThreads = 1024;   // as wide as k_serial: the serial phase runs in workgroup 0
-constexpr unsigned kSpinLimit = 1u << 26;
+constexpr unsigned kSpinLimit = 1u << 23;
 static_assert(kPersistThreads * kUnroll <= kScanPad, "scan padding must cover a whole scoring round");
 
 // Grid-wide barrier for a cooperative launch: arrive on bar[0], wait for the
@@ -1494,7 +1494,7 @@ __device__ bool grid_sync(unsigned *bar, int32_t *err, int *s_ok)
         } else {
             unsigned spins = 0;
             while (__hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
-                __builtin_amdgcn_s_sleep(1);
+                __builtin_amdgcn_s_sleep(10);
                 if (++spins > kSpinLimit) {
                     atomicOr(err, 4);
                     ok = 0;
@@ -1776,6 +1776,8 @@ struct bbs_workspace {
     State *dstate = nullptr;
     int64_t dstate_n = 0;
     State *host_state = nullptr;   // pinned
+    State *host_state2 = nullptr;  // pinned: the second of the two in-flight search-loop checks
+    hipEvent_t sync_ev[2] = {nullptr, nullptr};
     std::vector<hipEvent_t> ev;
     bool hist_dirty = true;
 };
@@ -1791,6 +1793,9 @@ void free_ws(bbs_workspace *w)
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (w->host_state) (void)hipHostFree(w->host_state);
+    if (w->host_state2) (void)hipHostFree(w->host_state2);
+    for (hipEvent_t e : w->sync_ev)
+        if (e) (void)hipEventDestroy(e);
     for (hipEvent_t e : w->ev) (void)hipEventDestroy(e);
     if (w->own_stream) (void)hipStreamDestroy(w->own_stream);
     delete w;
@@ -2077,6 +2082,7 @@ extern "C" bbs_status bbs_workspace_create(int64_t max_queue_nodes, bbs_workspac
     (void)hipGetDevice(&w->device);
     w->queue_nodes = max_queue_nodes ? max_queue_nodes : kDefaultQueueNodes;
     hipError_t e = hipHostMalloc((void **)&w->host_state, sizeof(State), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&w->host_state2, sizeof(State), hipHostMallocDefault);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         free_ws(w);
@@ -2086,6 +2092,13 @@ extern "C" bbs_status bbs_workspace_create(int64_t max_queue_nodes, bbs_workspac
     if (e != hipSuccess) {
         free_ws(w);
         return hip_fail(e, "hipStreamCreateWithFlags");
+    }
+    for (hipEvent_t &ev : w->sync_ev) {
+        e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            free_ws(w);
+            return hip_fail(e, "hipEventCreateWithFlags");
+        }
     }
     *out = w;
     return BBS_OK;
@@ -2417,27 +2430,45 @@ extern "C" bbs_status bbs_localize(const bbs_map *map, bbs_workspace *ws, const 
     }
 
     // search loop; every iteration before the last pops at least one node, so
-    // the cap only guards against a broken queue
+    // the cap only guards against a broken queue.  Groups of kItersPerSync
+    // iterations go out two at a time: the next group is queued before the
+    // host reads the state after the previous one, so the device never waits
+    // for that check.  Iterations queued after the search is done return at
+    // once, and the state after the last group is the final one.
     const int64_t max_iters = (int64_t)1 << 26;
-    int64_t iters = 0;
-    for (;;) {
-        if (persistent_used || graph_used) break;
-        if (iters >= max_iters) {
-            ws->hist_dirty = true;
-            return fail(BBS_ERR_INTERNAL, "bbs_localize: search did not terminate");
+    if (!persistent_used && !graph_used && !init_done) {
+        State *slot[2] = {ws->host_state, ws->host_state2};
+        auto issue = [&](int k) -> bbs_status {
+            for (int it = 0; it < kItersPerSync; ++it) {
+                if (prof) BBS_HIP(record(ev_used++));
+                launch_score(S, map, ws, ws->state, 0, score_grid, true);
+                if (prof) BBS_HIP(record(ev_used++));
+                serial(1);
+            }
+            BBS_HIP(hipGetLastError());
+            BBS_HIP(hipMemcpyAsync(slot[k], ws->state, sizeof(State), hipMemcpyDeviceToHost, s));
+            BBS_HIP(hipEventRecord(ws->sync_ev[k], s));
+            return BBS_OK;
+        };
+        bbs_status ist = issue(0);
+        if (ist) return ist;
+        int64_t iters = kItersPerSync;
+        for (int cur = 0;; cur = 1 - cur) {
+            if (iters >= max_iters) {
+                BBS_HIP(hipStreamSynchronize(s));
+                ws->hist_dirty = true;
+                return fail(BBS_ERR_INTERNAL, "bbs_localize: search did not terminate");
+            }
+            ist = issue(1 - cur);
+            if (ist) return ist;
+            iters += kItersPerSync;
+            BBS_HIP(hipEventSynchronize(ws->sync_ev[cur]));
+            if (slot[cur]->done || slot[cur]->error) {
+                BBS_HIP(hipEventSynchronize(ws->sync_ev[1 - cur]));
+                if (slot[1 - cur] != ws->host_state) *ws->host_state = *slot[1 - cur];
+                break;
+            }
         }
-        iters += kItersPerSync;
-        if (init_done) break;
-        for (int it = 0; it < kItersPerSync; ++it) {
-            if (prof) BBS_HIP(record(ev_used++));
-            launch_score(S, map, ws, ws->state, 0, score_grid, true);
-            if (prof) BBS_HIP(record(ev_used++));
-            serial(1);
-        }
-        BBS_HIP(hipGetLastError());
-        BBS_HIP(hipMemcpyAsync(ws->host_state, ws->state, sizeof(State), hipMemcpyDeviceToHost, s));
-        BBS_HIP(hipStreamSynchronize(s));
-        if (ws->host_state->done || ws->host_state->error) break;
     }
     const State &fs = *ws->host_state;
     if (fs.error) {
