@@ -34,6 +34,11 @@ VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 # ALU work per (node, scan point): 15 fp32 ops of the 3x3 transform and 3 floors,
 # shared by the 8 translational siblings of a rotation, plus ~10 integer ops
 OPS_PER_NODE_POINT = 18 / 8 + 10
+# The timed localizations bracket every PROFILE_EVERY-th scoring launch with a
+# pair of HIP events on the library's stream; the mean of those launches gives
+# the kernel's duration.  Bracketing every launch added about 9 % to the
+# localization time (each event pair adds queue time between the kernels).
+PROFILE_EVERY = 8
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_score_city_traffic.md")
 WEIGHTS = os.path.join(ROOT, "paper_2310_10023_amd", "proposal_weights.npz")
 SCORE_SRC = os.path.join(ROOT, "paper_2310_10023_amd", "csrc", "bbs_search.hip")
@@ -148,13 +153,14 @@ def main():
     dev = {s: torch.from_numpy(v.points).cuda() for s, v in scans.items()}
     ws = bbs.Workspace()
     for s in warm_seeds:
-        bbs.localize(gmap, dev[s], lo, hi, T, batch_size=args.batch, profile=True, workspace=ws)
+        bbs.localize(gmap, dev[s], lo, hi, T, batch_size=args.batch, profile=PROFILE_EVERY, workspace=ws)
     torch.cuda.synchronize()
 
     results = []
     t0 = time.perf_counter()
     for s in seeds:
-        results.append(bbs.localize(gmap, dev[s], lo, hi, T, batch_size=args.batch, profile=True, workspace=ws))
+        results.append(bbs.localize(gmap, dev[s], lo, hi, T, batch_size=args.batch, profile=PROFILE_EVERY,
+                                    workspace=ws))
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     print(f"[bench] timed {len(seeds)} localizations in {elapsed:.3f} s", file=sys.stderr, flush=True)

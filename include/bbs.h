@@ -55,8 +55,8 @@ typedef struct {
                                  (Alg. 2); default 10000 as in Sec. IV */
     int32_t translation_only; /* 1: angular grids at leaf resolution on every level
                                  (Table I "Trans." branching); 0: roto-translational */
-    int32_t profile;          /* 1: time every scoring launch with HIP events (fills
-                                 score_kernel_ms / score_launches of the result) */
+    int32_t profile;          /* P >= 1: time every P-th scoring launch with HIP events (fills
+                                 score_kernel_ms / score_launches of the result); 0: off */
     int32_t seed_beam;        /* with a prior: width W of the seed beam.  Starting from the W best
                                  initial nodes reaching the threshold, every beam node is
                                  branched, all children scored, and the W best children
@@ -94,8 +94,9 @@ typedef struct {
     int64_t leaves_accepted;  /* leaf pops with score >= the running best */
     int64_t initial_size;     /* valid nodes at the top level */
     int64_t initial_kept;     /* of those, nodes with score >= score_threshold */
-    double score_kernel_ms;   /* summed duration of the scoring launches (profile = 1) */
-    int64_t score_launches;   /* number of scoring launches (profile = 1) */
+    double score_kernel_ms;   /* duration of the scoring launches (profile >= 1): the sum, or
+                                 with profile = P > 1 the mean of the timed ones times their number */
+    int64_t score_launches;   /* number of scoring launches (profile >= 1) */
     int64_t score_pairs;      /* sum over scored nodes of K (node-point membership tests) */
     int64_t score_groups;     /* scored groups of translational siblings sharing a rotation */
     double phase_ms[4];       /* set-up, initial set, search loop, total (host clock) */

@@ -260,7 +260,7 @@ class Workspace:
 
 
 def localize(bmap: Map, scan, rmin, rmax, score_threshold: int, *, batch_size: int = 10000,
-             translation_only: bool = False, profile: bool = False, workspace: Workspace | None = None,
+             translation_only: bool = False, profile: int = 0, workspace: Workspace | None = None,
              stream=None, prior=None, seed_beam: int = 0, persistent: bool = False,
              score_items: int = 0, graph: bool = False) -> dict:
     """Global localization of one scan (Alg. 2 on the GPU).  Returns the result

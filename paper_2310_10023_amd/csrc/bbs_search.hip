@@ -2214,7 +2214,9 @@ extern "C" bbs_status bbs_localize(const bbs_map *map, bbs_workspace *ws, const 
     h.q_max = -1;
     BBS_HIP(hipMemcpyAsync(ws->state, &h, sizeof(State), hipMemcpyHostToDevice, s));
 
-    const bool prof = o.profile != 0;
+    const bool prof = o.profile > 0;
+    const int64_t prof_every = prof ? o.profile : 1;   // time every prof_every-th scoring launch
+    int64_t score_li = 0;                                // scoring launches issued so far
     int64_t ev_used = 0;
     auto record = [&](int64_t i) -> hipError_t {
         while ((int64_t)ws->ev.size() <= i) {
@@ -2285,9 +2287,10 @@ extern "C" bbs_status bbs_localize(const bbs_map *map, bbs_workspace *ws, const 
             k_enum_initial<<<grid_for(cnt, 256, 4096), 256, 0, s>>>(ws->groups, ws->scores, g0, cnt, C, P0[0], P0[1],
                                                                      P0[2], PN[1], PN[2], ws->state);
         }
-        if (prof) BBS_HIP(record(ev_used++));
+        const bool timed = prof && score_li++ % prof_every == 0;
+        if (timed) BBS_HIP(record(ev_used++));
         launch_score(S, map, ws, ws->state, 0, score_grid, true);
-        if (prof) BBS_HIP(record(ev_used++));
+        if (timed) BBS_HIP(record(ev_used++));
         if (beam_w > 0) {
             std::vector<int32_t> sc((size_t)cnt * 8);
             BBS_HIP(hipMemcpyAsync(sc.data(), ws->scores, sc.size() * 4, hipMemcpyDeviceToHost, s));
@@ -2440,9 +2443,10 @@ extern "C" bbs_status bbs_localize(const bbs_map *map, bbs_workspace *ws, const 
         State *slot[2] = {ws->host_state, ws->host_state2};
         auto issue = [&](int k) -> bbs_status {
             for (int it = 0; it < kItersPerSync; ++it) {
-                if (prof) BBS_HIP(record(ev_used++));
+                const bool timed = prof && score_li++ % prof_every == 0;
+                if (timed) BBS_HIP(record(ev_used++));
                 launch_score(S, map, ws, ws->state, 0, score_grid, true);
-                if (prof) BBS_HIP(record(ev_used++));
+                if (timed) BBS_HIP(record(ev_used++));
                 serial(1);
             }
             BBS_HIP(hipGetLastError());
@@ -2506,14 +2510,18 @@ extern "C" bbs_status bbs_localize(const bbs_map *map, bbs_workspace *ws, const 
     out->score_groups = n_init_groups + fs.groups_scored;
     if (prof) {
         // every iteration before the one that found the queue exhausted scored a batch
+        // (event pair i brackets launch i * prof_every; the total is the mean
+        // of the timed launches times the number of launches)
         int64_t launches = init_chunks + (persistent_used ? 0 : fs.flushes);
         double total = 0.0;
-        for (int64_t i = 0; i < launches && 2 * i + 1 < ev_used; ++i) {
+        int64_t timed = 0;
+        for (int64_t i = 0; i * prof_every < launches && 2 * i + 1 < ev_used; ++i) {
             float ms = 0.0f;
             BBS_HIP(hipEventElapsedTime(&ms, ws->ev[2 * i], ws->ev[2 * i + 1]));
             total += ms;
+            ++timed;
         }
-        out->score_kernel_ms = total;
+        out->score_kernel_ms = timed > 0 ? total / (double)timed * (double)launches : 0.0;
         out->score_launches = launches;
     }
     out->phase_ms[0] = t_setup;
