@@ -492,7 +492,7 @@ struct ScoreArgs {
     const double2 *trig;
     int32_t *scores;
     int32_t *tile_done;        // NULL: no tile pass
-    int32_t *q_arr, *rank_arr, *hist;   // kept children per tile: bucket, rank; tile x bucket counts
+    int32_t *kq, *krank, *hist;  // kept children per tile: bucket, rank; tile x bucket counts
     uint4 *knode;              // kept children per tile: packed node
     int32_t *kcnt;             // kept children per tile: number
     uint32_t *qmask;           // bit q: some tile of the batch holds a child of bucket q
@@ -860,7 +860,7 @@ __device__ void score_items(State *st, const ScoreArgs &A, const MapView &map, c
             }
             __syncthreads();
             if (sh.s_last) {
-                tile_pass<NT>(t, groups, scores, st, C, n_groups, A.q_arr, A.rank_arr, A.knode, A.kcnt, A.hist, A.qmask,
+                tile_pass<NT>(t, groups, scores, st, C, n_groups, A.kq, A.krank, A.knode, A.kcnt, A.hist, A.qmask,
                               sh.sq, sh.sm);
                 if (threadIdx.x == 0) __hip_atomic_store(&tile_done[t], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
@@ -944,7 +944,7 @@ __device__ inline void bucket_space(const Bucket &b, int cnt, int &T, int &f, in
 }
 
 struct PushBufs {
-    int32_t *q_arr, *rank_arr, *hist, *totals, *pT, *pf, *pc0, *chunk_next;
+    int32_t *kq, *krank, *hist, *totals, *pT, *pf, *pc0, *chunk_next;
     int32_t *hbase;            // tile x bucket: first rank of the tile's children in the bucket
     uint4 *knode;
     int32_t *kcnt;
@@ -1130,8 +1130,8 @@ __device__ void push_finish(State *st, const SearchConst &C, Bucket *bk, const u
             }
             const int t = c0t + lo;
             const int64_t k = (int64_t)t * kTileSlots + e - (lo > 0 ? blk[lo - 1] : 0);
-            const int q = B.q_arr[k];
-            const int r = B.hbase[(int64_t)t * C.q_count + q] + B.rank_arr[k];
+            const int q = B.kq[k];
+            const int r = B.hbase[(int64_t)t * C.q_count + q] + B.krank[k];
             const uint4 node = B.knode[k];
             const int Tc = B.pT[q - q_min], fc = B.pf[q - q_min];
             const int space = Tc >= 0 ? kChunk - fc : 0;
@@ -1742,10 +1742,10 @@ struct bbs_workspace {
     int64_t knode_n = 0;
     int32_t *kcnt = nullptr;
     int64_t kcnt_n = 0;
-    int32_t *q_arr = nullptr;
-    int64_t q_arr_n = 0;
-    int32_t *rank_arr = nullptr;
-    int64_t rank_arr_n = 0;
+    int32_t *kq = nullptr;
+    int64_t kq_n = 0;
+    int32_t *krank = nullptr;
+    int64_t krank_n = 0;
     int32_t *tile_done = nullptr;
     int64_t tile_done_n = 0;
     int32_t *ticket = nullptr;   // scoring item tickets (2 counters, zero between launches)
@@ -1787,9 +1787,11 @@ namespace {
 
 void free_ws(bbs_workspace *w)
 {
-    void *ptrs[] = {w->arena, w->chunk_next, w->buckets, w->hist, w->totals, w->pT, w->pf, w->pc0, w->groups, w->scores,
-                    w->q_arr, w->rank_arr, w->hbase, w->knode, w->kcnt, w->tile_done, w->ticket, w->scan, w->scan_aos, w->scan_tmp, w->mkeys, w->mhist,
-                    w->trig, w->state, w->maxsq, w->beam, w->prior, w->dstate, w->bar, w->qmask, w->qlist};
+    void *ptrs[] = {w->arena,   w->chunk_next, w->buckets, w->hist,     w->totals,  w->pT,    w->pf,
+                    w->pc0,     w->groups,     w->scores,  w->kq,       w->krank,   w->hbase, w->knode,
+                    w->kcnt,    w->tile_done,  w->ticket,  w->scan,     w->scan_aos, w->scan_tmp, w->mkeys,
+                    w->mhist,   w->trig,       w->state,   w->maxsq,    w->beam,    w->prior, w->dstate,
+                    w->bar,     w->qmask,      w->qlist};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (w->host_state) (void)hipHostFree(w->host_state);
@@ -1981,8 +1983,8 @@ ScoreArgs score_args(const Setup &S, bbs_workspace *ws, int32_t n_fixed, bool ti
     A.trig = ws->trig;
     A.scores = ws->scores;
     A.tile_done = tile_pass ? ws->tile_done : nullptr;
-    A.q_arr = ws->q_arr;
-    A.rank_arr = ws->rank_arr;
+    A.kq = ws->kq;
+    A.krank = ws->krank;
     A.knode = ws->knode;
     A.kcnt = ws->kcnt;
     A.hist = ws->hist;
@@ -2176,9 +2178,9 @@ extern "C" bbs_status bbs_localize(const bbs_map *map, bbs_workspace *ws, const 
     const int64_t qn = std::max<int32_t>(C.q_count, 1);
     const int64_t chunk_cap = std::max<int64_t>(ws->queue_nodes / kChunk, 16);
     if (ensure(ws->groups, ws->groups_n, cap_groups) || ensure(ws->scores, ws->scores_n, 8 * cap_groups) ||
-        ensure(ws->q_arr, ws->q_arr_n, n_tiles * kTileSlots) || ensure(ws->knode, ws->knode_n, n_tiles * kTileSlots) ||
+        ensure(ws->kq, ws->kq_n, n_tiles * kTileSlots) || ensure(ws->knode, ws->knode_n, n_tiles * kTileSlots) ||
         ensure(ws->kcnt, ws->kcnt_n, n_tiles) || ensure(ws->hbase, ws->hbase_n, n_tiles * qn) ||
-        ensure(ws->rank_arr, ws->rank_arr_n, n_tiles * kTileSlots) || ensure(ws->totals, ws->totals_n, qn) ||
+        ensure(ws->krank, ws->krank_n, n_tiles * kTileSlots) || ensure(ws->totals, ws->totals_n, qn) ||
         ensure(ws->pT, ws->pT_n, qn) || ensure(ws->pf, ws->pf_n, qn) || ensure(ws->pc0, ws->pc0_n, qn) ||
         ensure(ws->buckets, ws->buckets_n, qn) || ensure(ws->arena, ws->arena_n, chunk_cap * kChunk) ||
         ensure(ws->chunk_next, ws->chunk_next_n, chunk_cap) ||
@@ -2229,8 +2231,8 @@ extern "C" bbs_status bbs_localize(const bbs_map *map, bbs_workspace *ws, const 
     };
     const int score_grid = S.score_grid;
     PushBufs B;
-    B.q_arr = ws->q_arr;
-    B.rank_arr = ws->rank_arr;
+    B.kq = ws->kq;
+    B.krank = ws->krank;
     B.hist = ws->hist;
     B.qmask = ws->qmask;
     B.qlist = ws->qlist;

@@ -215,6 +215,23 @@ def test_localize_device_scan_and_determinism(room):
     compare(b, want)
 
 
+def test_localize_profile_sampling(room):
+    """Timing every launch or every 4th changes nothing in the result; both
+    report every scoring launch and a positive duration."""
+    say("localize with launch timing")
+    scene, g, o = room
+    sc = synth.scan_scene(scene, 2, 2000, z=1.5, z_jitter=0.25, rp_deg=2.0)
+    lo, hi = synth.search_range_room()
+    T = synth.threshold_95(2000)
+    want = oracle.Search(o, sc.points, lo, hi).localize(T, batch=64, threads=8)
+    ws = bbs.Workspace()
+    runs = [bbs.localize(g, sc.points, lo, hi, T, batch_size=64, workspace=ws, profile=p) for p in (0, 1, 4)]
+    for r in runs:
+        compare(r, want)
+    assert runs[1]["score_launches"] == runs[2]["score_launches"] > 4
+    assert runs[1]["score_kernel_ms"] > 0 and runs[2]["score_kernel_ms"] > 0
+
+
 @pytest.mark.parametrize("batch", [64, 10000])
 def test_localize_persistent_equals_oracle(room, batch):
     """The persistent cooperative kernel runs the same schedule."""
