@@ -839,12 +839,15 @@ __device__ void score_items(State *st, const ScoreArgs &A, const MapView &map, c
         // wait for outstanding memory operations is over; only then is the
         // tile counter bumped, and the tile pass reads the scores with atomics
         // too, at the same coherence point.
+        // (a pair holds its groups whole, so it stores their counts; the
+        // slices of a group add theirs to scores zeroed by the batch's producer)
         if (threadIdx.x < 8 * ng) {
             int sum = 0;
             for (int wv = 0; wv < NT / 64; ++wv) sum += red[wv][threadIdx.x];
             const int g = threadIdx.x >= 8 ? gs[1] : gs[0];
-            const int old = __hip_atomic_fetch_add(&scores[8 * (int64_t)g + (threadIdx.x & 7)], sum, __ATOMIC_RELAXED,
-                                                   __HIP_MEMORY_SCOPE_AGENT);
+            int32_t *dst = &scores[8 * (int64_t)g + (threadIdx.x & 7)];
+            const int old = pairs ? __hip_atomic_exchange(dst, sum, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                  : __hip_atomic_fetch_add(dst, sum, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             asm volatile("" ::"v"(old));          // keep the returning form of the atomic
         }
         __syncthreads();
@@ -1409,7 +1412,10 @@ __device__ void gather(State *st, Bucket *bk, const int32_t *chunk_next, const u
         }
     }
     __syncthreads();
-    for (int i = tid; i < 8 * ngrp; i += NT) scores[i] = 0;
+    // a batch of at least score_items groups is scored in pairs, which store
+    // their counts; a smaller one in slices that add to zeroed scores
+    if (ngrp < C.score_items)
+        for (int i = tid; i < 8 * ngrp; i += NT) scores[i] = 0;
     if (tid == 0) {
         st->best = best;
         st->have_match = have;
