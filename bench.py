@@ -109,7 +109,7 @@ def main():
     ap.add_argument("--tuned-queries", type=int, default=20)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
+        print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported "
               "(the multi-GPU sharding is a design note, not an implemented path)", file=sys.stderr)
         sys.exit(2)
 
