@@ -1157,7 +1157,18 @@ __device__ void push_finish(State *st, const SearchConst &C, Bucket *bk, const u
 
 // ------------------------------------------------------------------ gather + branch
 
-__device__ inline void child_counts(const SearchConst &C, const int32_t t[3], const int32_t ang[3], int level,
+// Per-level grid tables (the members of SearchConst of the same names); the
+// gather keeps a copy in LDS, since each lane indexes them by its own node's
+// level.
+struct LevelTables {
+    int32_t n[3][kMaxLevels];
+    int32_t a[3][kMaxLevels];
+    int32_t tlo[3][kMaxLevels];
+    int32_t thi[3][kMaxLevels];
+};
+
+template <class Tab>
+__device__ inline void child_counts(const Tab &C, const int32_t t[3], const int32_t ang[3], int level,
                                     int rc[3], uint32_t &tmask, int &n_nodes, int &n_groups)
 {
     const int cl = level - 1;
@@ -1204,6 +1215,7 @@ struct GatherSmem {
     int lq[NT];               // listed buckets (bucket index), in queue order
     Bucket lb[NT];            // their current head / tail
     int pre[NT];              // window: inclusive prefix of segment lengths
+    LevelTables lt;           // the grid tables, indexed per lane by level
     int s_last[2];
     int s_end;
     int s_cut;
@@ -1230,6 +1242,14 @@ __device__ void gather(State *st, Bucket *bk, const int32_t *chunk_next, const u
     int ngrp = 0;
     int64_t expanded = 0, leaves = 0;
     bool cut = false;
+    for (int i = tid; i < 3 * kMaxLevels; i += NT) {
+        const int ax = i / kMaxLevels, l = i % kMaxLevels;
+        sh.lt.n[ax][l] = C.n[ax][l];
+        sh.lt.a[ax][l] = C.a[ax][l];
+        sh.lt.tlo[ax][l] = C.tlo[ax][l];
+        sh.lt.thi[ax][l] = C.thi[ax][l];
+    }
+    __syncthreads();
     while (!cut && best <= C.K) {
         int qlim = min((C.K - best) * Lp1 + C.levels, C.q_count - 1);
         if (q > qlim) break;
@@ -1330,7 +1350,7 @@ __device__ void gather(State *st, Bucket *bk, const int32_t *chunk_next, const u
                     const Bucket bj = sh.lb[e + j];
                     level = sh.lq[e + j] % Lp1;
                     node_unpack(arena[(int64_t)bj.head_chunk * kChunk + bj.head_off + (tid - base)], t3, ang, lv);
-                    child_counts(C, t3, ang, level, rc, tmask, nn, ng);
+                    child_counts(sh.lt, t3, ang, level, rc, tmask, nn, ng);
                 }
                 int incl_n, incl_g;
                 if (C.max_children <= 64) {
@@ -1358,9 +1378,9 @@ __device__ void gather(State *st, Bucket *bk, const int32_t *chunk_next, const u
                     for (int ja = 0; ja < rc[0]; ++ja)
                         for (int jb = 0; jb < rc[1]; ++jb)
                             for (int jg = 0; jg < rc[2]; ++jg) {
-                                const int ra = C.a[0][level] * ang[0] + ja;
-                                const int rb = C.a[1][level] * ang[1] + jb;
-                                const int rg = C.a[2][level] * ang[2] + jg;
+                                const int ra = sh.lt.a[0][level] * ang[0] + ja;
+                                const int rb = sh.lt.a[1][level] * ang[1] + jb;
+                                const int rg = sh.lt.a[2][level] * ang[2] + jg;
                                 groups[gi++] = make_uint4(pack16(2 * t3[0], 2 * t3[1]), pack16(2 * t3[2], ra),
                                                           pack16(rb, rg), (uint32_t)(level - 1) | (tmask << 8));
                             }
