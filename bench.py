@@ -47,7 +47,7 @@ SCORE_SRC = os.path.join(ROOT, "paper_2310_10023_amd", "csrc", "bbs_search.hip")
 def score_kernel_sha() -> str:
     """Hash of the scoring kernel's source (its section of the search source)."""
     text = open(SCORE_SRC).read()
-    m = re.search(r"// -+ scoring \(Eq\. eq:3Dupperbound\)\n.*?// -+ initial set", text, flags=re.S)
+    m = re.search(r"// -+ scoring \(Eq\. \(12\), Sec\. III-C\)\n.*?// -+ initial set", text, flags=re.S)
     return hashlib.sha256((m.group(0) if m else text).encode()).hexdigest()[:16]
 
 

@@ -173,7 +173,7 @@ void bbs_workspace_free(bbs_workspace *ws);
 /*
  * Global localization of one scan: batched best-first branch and bound
  * (Alg. 2, Sec. III-E) over the roto-translational tree (Sec. III-D), node
- * score = upper bound of Eq. (eq:3Dupperbound).
+ * score = upper bound of Eq. (12).
  *   map, ws         map and workspace (ws NULL: a temporary workspace is used)
  *   scan_xyz, k     scan S (k >= 1), host or device (scan_on_device)
  *   range           search ranges (min <= max per axis, finite)
@@ -189,7 +189,7 @@ bbs_status bbs_localize(const bbs_map *map, bbs_workspace *ws, const float *scan
                         const bbs_options *opt, bbs_result *out);
 
 /*
- * Score arbitrary nodes with the device scoring kernel (Eq. (eq:3Dupperbound)).
+ * Score arbitrary nodes with the device scoring kernel (Eq. (12)).
  *   nodes           n host records of 7 int32: level, c_x, c_y, c_z, i_roll,
  *                   i_pitch, i_yaw (angle indices of that level's grid)
  *   scores          n host int32 outputs

@@ -5,9 +5,11 @@ library is checked against.  Only the test suite, the smoke check and the
 CPU-baseline leg of the benchmark may import this package; the library itself
 never does, and the two share no code.
 
-Parity pins for each function live in `tests/test_oracle_*.py`.  Parts with no
-external pin (the exact node counts of the search schedule) are marked
-"parity unpinned" there.
+Parity pins for each function live in `tests/test_oracle_*.py`: the node
+counters and pop order of the search schedule are pinned by hand-traced
+instances (`tests/golden/schedule_hand.json`).  The learned prior's trained
+weights are the one part with no pin ("parity unpinned": any weights are
+valid; only the ordering rules that use them are pinned).
 """
 from __future__ import annotations
 
@@ -19,18 +21,29 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "bbs_oracle.c")
-_LIB = os.path.join(_HERE, "liboracle_bbs.so")
+# BBS_ORACLE_LIB names another build of this source to load instead (the
+# mutation tests load deliberately broken copies this way, in a subprocess)
+_LIB_OVERRIDE = os.environ.get("BBS_ORACLE_LIB")
+_LIB = _LIB_OVERRIDE or os.path.join(_HERE, "liboracle_bbs.so")
 
 MAX_LEVELS = 16
 
 
+def compile_source(src: str, out: str) -> str:
+    """Compile an oracle source file with gcc (-O2, no FP contraction, no fast math)."""
+    tmp = out + ".tmp"
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
+                           "-fopenmp", "-fPIC", "-shared", "-Wall", "-o", tmp, src, "-lm"])
+    os.replace(tmp, out)
+    return out
+
+
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (-O2, no FP contraction, no fast math)."""
+    """Compile the oracle in place."""
+    if _LIB_OVERRIDE:
+        return _LIB
     if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
-                               "-fopenmp", "-fPIC", "-shared", "-Wall", "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _LIB)
+        compile_source(_SRC, _LIB)
     return _LIB
 
 
@@ -48,7 +61,7 @@ class Result(C.Structure):
                 ("flushes", C.c_int64), ("leaves_accepted", C.c_int64), ("initial_size", C.c_int64),
                 ("initial_kept", C.c_int64), ("bound_checks", C.c_int64), ("bound_violations", C.c_int64),
                 ("violation_excess_sum", C.c_double), ("prior_used", C.c_int32), ("seeded", C.c_int32),
-                ("seed_score", C.c_int32), ("pad", C.c_int32)]
+                ("seed_score", C.c_int32), ("pad", C.c_int32), ("events", C.c_int64)]
 
     def as_dict(self):
         return {"found": self.found, "score": self.score, "leaf": list(self.leaf),
@@ -67,7 +80,7 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        if not _LIB_OVERRIDE and (not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC)):
             build()
         L = C.CDLL(_LIB)
         P, I32, I64, F = C.c_void_p, C.c_int32, C.c_int64, C.c_float
@@ -86,7 +99,8 @@ def lib():
         L.orc_score.argtypes = [P, P, I64, C.POINTER(Grid), I32, I32, I32, I32, I32, I32, I32]
         L.orc_score.restype = I32
         L.orc_score_nodes.argtypes = [P, P, I64, C.POINTER(Grid), P, I64, P, I32]
-        L.orc_localize.argtypes = [P, P, I64, C.POINTER(Grid), I32, I64, I32, I64, C.POINTER(Result), P, I64, P, I32]
+        L.orc_localize.argtypes = [P, P, I64, C.POINTER(Grid), I32, I64, I32, I64, C.POINTER(Result), P, I64, P, I32,
+                                   P, I64]
         L.orc_localize.restype = C.c_int
         L.orc_bruteforce.argtypes = [P, P, I64, C.POINTER(Grid), I32, I32, C.POINTER(Result)]
         L.orc_bruteforce.restype = C.c_int
@@ -223,23 +237,38 @@ class Search:
         nd = _i32(node).reshape(7)
         return float(lib().orc_prior_key(C.byref(self.grid), pr.ctypes.data, nd.ctypes.data))
 
+    EVENT_KINDS = ("prune", "leaf", "branch", "flush")
+
     def localize(self, threshold: int, batch: int = 10000, threads: int = 1, max_scored: int = 0,
-                 trace_cap: int = 0, prior=None, seed_beam: int = 0) -> dict:
+                 trace_cap: int = 0, prior=None, seed_beam: int = 0, events_cap: int = 0) -> dict:
         """Alg. 2.  prior: optional 1088 float logits (64 yaw bins, then 32 x 32
         translation cells) that order the initial set; a seed beam of width
-        `seed_beam` ranked by (score, prior key) may seed the incumbent."""
+        `seed_beam` ranked by (score, prior key) may seed the incumbent.
+        trace_cap > 0 adds the flush sizes; events_cap > 0 adds the search
+        loop's events in order: ("prune" | "leaf" | "branch", node, score) for
+        every pop, node = (level, x, y, z, roll, pitch, yaw), and ("flush",
+        number of nodes scored)."""
         res = Result()
         tr = np.zeros(max(trace_cap, 1), dtype=np.int64)
+        ev = np.zeros((max(events_cap, 1), 9), dtype=np.int32)
         pr = None if prior is None else np.ascontiguousarray(prior, dtype=np.float32).reshape(1088)
         rc = lib().orc_localize(self.map.handle, self.scan.ctypes.data, self.k, C.byref(self.grid), int(threshold),
                                 int(batch), int(threads), int(max_scored), C.byref(res),
                                 tr.ctypes.data if trace_cap else None, int(trace_cap),
-                                pr.ctypes.data if pr is not None else None, int(seed_beam))
+                                pr.ctypes.data if pr is not None else None, int(seed_beam),
+                                ev.ctypes.data if events_cap else None, int(events_cap))
         if rc != 0:
             raise OracleError(f"orc_localize failed ({rc})")
         d = res.as_dict()
         if trace_cap:
             d["flush_sizes"] = tr[:min(trace_cap, res.flushes)].tolist()
+        if events_cap:
+            out = []
+            for e in ev[:min(events_cap, res.events)].tolist():
+                kind = self.EVENT_KINDS[e[0]]
+                out.append([kind, e[8]] if kind == "flush" else [kind, e[1:8], e[8]])
+            d["events"] = out
+            d["events_total"] = int(res.events)
         return d
 
     def bruteforce(self, threshold: int, threads: int = 1) -> dict:

@@ -10,10 +10,10 @@
  *
  * Every function follows the paper's text in the order it states things:
  *   - multi-resolution voxel map and its dilation ........ Sec. III-C
- *   - node score = upper bound, Eq. (eq:3Dupperbound) ..... Sec. III-C
+ *   - node score = upper bound, Eq. (12) .................. Sec. III-C
  *   - rotational step delta(r), Eq. (2) ................... Sec. III-B
- *   - per-level step delta'(r_l), divisions a ............. Sec. III-D
- *   - roto-translational branching ........................ Sec. III-D
+ *   - per-level step delta'(r_l) Eq. (13), divisions a Eq. (15) Sec. III-D
+ *   - roto-translational branching, Eq. (14) .............. Sec. III-D
  *   - best-first batched search, Alg. 2 ................... Sec. III-E
  * Where the paper is silent the reading used is stated at the point of use.
  *
@@ -326,7 +326,7 @@ static int node_valid(const orc_grid *g, int l, const int32_t t[3], const int32_
     return 1;
 }
 
-/* ------------------------------------------------------------------ score (Eq. eq:3Dupperbound) */
+/* ------------------------------------------------------------------ score (Eq. (12), Sec. III-C) */
 
 /*
  * score(c) = sum_k H^{c_l}(T_{x_c} s_k).
@@ -459,6 +459,7 @@ typedef struct {
     double violation_excess_sum;             /* sum of (child - parent) / parent */
     int32_t prior_used, seeded;              /* the prior ordered the initial set; the seed beam set the incumbent */
     int32_t seed_score, pad;
+    int64_t events;                          /* search events logged (see orc_localize) */
 } orc_result;
 
 /*
@@ -708,9 +709,31 @@ out:
  * in descending prior key (ties in enumeration order), and a seed beam of
  * width beam_width may set the incumbent before the loop starts.
  */
+/* Event log of the search loop (tests only): 9 int32 per event, kind then the
+ * node (level, x, y, z, roll, pitch, yaw) and its score.  Kinds: a popped node
+ * that is pruned, an accepted leaf, a branched node; and a flush, whose
+ * "score" field holds the number of nodes scored. */
+enum { ORC_EV_PRUNE = 0, ORC_EV_LEAF = 1, ORC_EV_BRANCH = 2, ORC_EV_FLUSH = 3 };
+
+static void log_event(int32_t *ev, int64_t cap, orc_result *res, int kind, const orc_node *c, int32_t value)
+{
+    if (ev && res->events < cap) {
+        int32_t *e = ev + 9 * res->events;
+        e[0] = kind;
+        e[1] = c ? c->level : -1;
+        for (int ax = 0; ax < 3; ++ax) {
+            e[2 + ax] = c ? c->t[ax] : 0;
+            e[5 + ax] = c ? c->ang[ax] : 0;
+        }
+        e[8] = value;
+    }
+    res->events++;
+}
+
 int orc_localize(const orc_map *m, const float *scan, int64_t k, const orc_grid *g, int32_t threshold,
                  int64_t batch, int32_t threads, int64_t max_scored, orc_result *res,
-                 int64_t *trace_flush, int64_t trace_cap, const float *prior, int32_t beam_width)
+                 int64_t *trace_flush, int64_t trace_cap, const float *prior, int32_t beam_width,
+                 int32_t *events, int64_t events_cap)
 {
     memset(res, 0, sizeof(*res));
     if (!m || !scan || k < 1 || batch < 1 || g->levels != m->levels) return ORC_ERR_ARG;
@@ -798,13 +821,18 @@ int orc_localize(const orc_map *m, const float *scan, int64_t k, const orc_grid 
             flush = 1;                                     /* termination flush */
         } else {
             orc_node c = heap_pop(&heap);
-            if (c.score < best) continue;                  /* pruned */
+            if (c.score < best) {                          /* pruned */
+                log_event(events, events_cap, res, ORC_EV_PRUNE, &c, c.score);
+                continue;
+            }
             if (c.level == 0) {
+                log_event(events, events_cap, res, ORC_EV_LEAF, &c, c.score);
                 res->leaves_accepted++;
                 if (!have_match || c.score > best || leaf_lex_less(&c, &match)) match = c;
                 have_match = 1;
                 best = c.score;
             } else {
+                log_event(events, events_cap, res, ORC_EV_BRANCH, &c, c.score);
                 res->nodes_expanded++;
                 if ((rc = branch(g, &c, &pending))) goto done;
             }
@@ -813,6 +841,7 @@ int orc_localize(const orc_map *m, const float *scan, int64_t k, const orc_grid 
         if (flush) {
             score_vec(m, scan, k, g, &pending, threads);
             if (trace_flush && res->flushes < trace_cap) trace_flush[res->flushes] = pending.n;
+            log_event(events, events_cap, res, ORC_EV_FLUSH, NULL, (int32_t)pending.n);
             res->flushes++;
             res->nodes_scored += pending.n;
             for (int64_t i = 0; i < pending.n; ++i) {

@@ -1,7 +1,7 @@
 // Batched best-first branch and bound on the device (Sec. III-D, III-E).
 //
 // One search iteration ("flush" of Alg. 2) is two kernels on one stream:
-//   k_score   the node score of Eq. (eq:3Dupperbound) for every pending node;
+//   k_score   the node score of Eq. (12) for every pending node;
 //             the last workgroup to finish a tile of 32 groups also sorts
 //             that tile's kept children by queue bucket (stable ranks);
 //   k_serial  one workgroup: finishes the stable counting sort of the batch
@@ -377,7 +377,7 @@ __device__ inline void rotation(const double2 *trig, const SearchConst &C, int l
     R[8] = (float)(cb * ca);
 }
 
-// ------------------------------------------------------------------ scoring (Eq. eq:3Dupperbound)
+// ------------------------------------------------------------------ scoring (Eq. (12), Sec. III-C)
 
 // Scores the eight translational siblings of each group against D_level.
 // For scan point s and the group's rotation R, the level-l voxel of node

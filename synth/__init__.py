@@ -20,7 +20,7 @@ import numpy as np
 
 __all__ = [
     "Scene", "Scan", "room_scene", "city_scene", "scan_scene", "rotation_zyx",
-    "search_range_room", "search_range_city", "threshold_95", "tiny_scene",
+    "search_range_room", "search_range_city", "threshold_95", "tiny_scene", "city_query", "room_query",
 ]
 
 
@@ -364,6 +364,20 @@ def scan_scene(scene: Scene, seed: int, n_points: int, *, z: float, z_jitter: fl
     idx = rng.choice(len(pts_s), size=n_points, replace=replace)
     pts = pts_s[idx] + (rng.normal(0.0, noise, size=(n_points, 3)) if noise > 0 else 0.0)
     return Scan(points=pts.astype(np.float32), pose=pose, seed=seed)
+
+
+def city_query(scene: Scene, seed: int, n_points: int, voxel: float = 0.5) -> Scan:
+    """A query scan of the city workload: 64 beams over -25..+15 deg, 2048
+    azimuths, 100 m range, from a street position at 1.8 m with roll and pitch
+    U(-3, 3) deg and uniform yaw, voxel-thinned at `voxel` metres, trimmed to
+    `n_points`, N(0, 0.02 m) noise."""
+    return scan_scene(scene, seed, n_points, z=1.8, rp_deg=3.0, n_beams=64, n_az=2048, voxel=voxel)
+
+
+def room_query(scene: Scene, seed: int, n_points: int = 2000) -> Scan:
+    """A query scan of the indoor workload: 32 beams x 1024 azimuths from
+    z = 1.5 +- 0.25 m with roll and pitch U(-2, 2) deg and uniform yaw."""
+    return scan_scene(scene, seed, n_points, z=1.5, z_jitter=0.25, rp_deg=2.0)
 
 
 # --------------------------------------------------------------------------- tiny

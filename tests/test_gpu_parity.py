@@ -77,7 +77,7 @@ def test_map_from_device_tensor():
         np.testing.assert_array_equal(g.dump_level(l), sorted_rows(o.level_keys(l)))
 
 
-# ------------------------------------------------------------------ score (Eq. eq:3Dupperbound)
+# ------------------------------------------------------------------ score (Eq. (12), Sec. III-C)
 
 def random_nodes(s, rng, n, levels):
     rows = []

@@ -1,4 +1,4 @@
-"""Pins for the oracle's node score, the upper bound of Eq. (eq:3Dupperbound):
+"""Pins for the oracle's node score, the upper bound of Eq. (12):
 score(c) = sum_k H^{c_l}(T_{x_c} s_k).
 
 Two independent pins:

@@ -11,8 +11,8 @@
     nothing and branches nothing.
   * Known-pose recovery on noise-free scans, and the paper's success criterion
     (2.0 m, 0.05 rad, Sec. IV) on noisy scans of the room.
-  * Schedule invariants of the node counters.  The exact node counts of the
-    schedule have no external pin (the paper prints none): parity unpinned.
+  * Schedule invariants of the node counters.  The exact counts and pop order
+    are pinned on hand-traced instances in test_oracle_schedule.py.
 """
 import math
 
