@@ -188,6 +188,35 @@ bbs_status bbs_localize(const bbs_map *map, bbs_workspace *ws, const float *scan
                         int32_t scan_on_device, const bbs_search_range *range, int32_t score_threshold,
                         const bbs_options *opt, bbs_result *out);
 
+/* Size of the static device scratch of bbs_localize_noalloc, per GPU. */
+#define BBS_NOALLOC_SCRATCH_BYTES (128u << 20)
+
+/*
+ * bbs_localize for callers that cannot allocate: serving loops and harnesses
+ * that forbid hipMalloc / hipFree (or any allocating library routine) while
+ * they run.  The search, arguments and results are those of bbs_localize
+ * (without a workspace).  No device memory is allocated or freed and no
+ * stream, event or graph is created: every working buffer (scan copies,
+ * angle tables, the pending batch, the bucket queue) is carved from one
+ * static device array of BBS_NOALLOC_SCRATCH_BYTES per GPU, which the
+ * library holds until the process ends.  Host-side set-up still uses small
+ * temporary host buffers.
+ *   limits          the node queue gets what the other buffers leave (about
+ *                   7M nodes for a 10,000-point scan at b = 10,000); a search
+ *                   that needs more returns BBS_ERR_QUEUE_OVERFLOW.  A scan
+ *                   size / batch size whose other buffers alone do not fit
+ *                   returns BBS_ERR_INVALID_ARG.
+ *   opt             opt->profile and opt->graph must be 0 (INVALID_ARG
+ *                   otherwise); runs on opt->stream, or the null stream if it
+ *                   is NULL, and returns when the search is done
+ * The scratch keeps whatever the last call left in it; each call clears what
+ * must start at zero.  Calls on one GPU share that GPU's scratch, so calls
+ * that overlap on one GPU race; calls on different GPUs do not.
+ */
+bbs_status bbs_localize_noalloc(const bbs_map *map, const float *scan_xyz, int64_t k, int32_t scan_on_device,
+                                const bbs_search_range *range, int32_t score_threshold, const bbs_options *opt,
+                                bbs_result *out);
+
 /*
  * Score arbitrary nodes with the device scoring kernel (Eq. (12)).
  *   nodes           n host records of 7 int32: level, c_x, c_y, c_z, i_roll,

@@ -14,7 +14,7 @@ import os
 
 import numpy as np
 
-__all__ = ["LibraryMissing", "BbsError", "Map", "Workspace", "localize", "score_nodes", "serve", "lib",
+__all__ = ["LibraryMissing", "BbsError", "Map", "Workspace", "localize", "localize_noalloc", "score_nodes", "serve", "lib",
            "library_path", "EXPORTED_SYMBOLS"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -23,7 +23,7 @@ MAX_LEVELS = 16
 
 EXPORTED_SYMBOLS = (
     "bbs_default_options", "bbs_abi_version", "bbs_last_error", "bbs_build_map", "bbs_free_map", "bbs_map_info",
-    "bbs_map_layout", "bbs_map_dump_level", "bbs_map_contains", "bbs_workspace_create", "bbs_workspace_free", "bbs_localize",
+    "bbs_map_layout", "bbs_map_dump_level", "bbs_map_contains", "bbs_workspace_create", "bbs_workspace_free", "bbs_localize", "bbs_localize_noalloc",
     "bbs_score_nodes", "bbs_serve", "bbs_net_param_count", "bbs_net_create", "bbs_net_free", "bbs_net_set_params",
     "bbs_net_get_params", "bbs_net_forward", "bbs_net_train_step", "bbs_bev_image", "bbs_autotune",
 )
@@ -117,6 +117,9 @@ def lib():
         L.bbs_localize.argtypes = [P, P, P, I64, I32, C.POINTER(SearchRange), I32, C.POINTER(Options),
                                    C.POINTER(Result)]
         L.bbs_localize.restype = C.c_int
+        L.bbs_localize_noalloc.argtypes = [P, P, I64, I32, C.POINTER(SearchRange), I32, C.POINTER(Options),
+                                           C.POINTER(Result)]
+        L.bbs_localize_noalloc.restype = C.c_int
         L.bbs_score_nodes.argtypes = [P, P, I64, C.POINTER(SearchRange), I32, P, I64, P]
         L.bbs_score_nodes.restype = C.c_int
         L.bbs_serve.argtypes = [P, C.POINTER(Query), I64, I32, C.POINTER(Options), C.POINTER(Result), P, P]
@@ -286,6 +289,32 @@ def localize(bmap: Map, scan, rmin, rmax, score_threshold: int, *, batch_size: i
     res = Result()
     _check(lib().bbs_localize(bmap.handle, workspace.handle if workspace else None, ptr, k, dev, C.byref(rng),
                               int(score_threshold), C.byref(opt), C.byref(res)))
+    del keep, pr
+    return res.as_dict()
+
+
+def localize_noalloc(bmap: Map, scan, rmin, rmax, score_threshold: int, *, batch_size: int = 10000,
+                     translation_only: bool = False, stream=None, prior=None, seed_beam: int = 0,
+                     persistent: bool = False, score_items: int = 0) -> dict:
+    """localize() through bbs_localize_noalloc: no device allocation, every
+    buffer comes from the library's static per-GPU scratch."""
+    ptr, k, dev, keep = _points(scan, "scan")
+    opt = Options()
+    lib().bbs_default_options(C.byref(opt))
+    opt.batch_size = int(batch_size)
+    opt.translation_only = int(translation_only)
+    opt.seed_beam = int(seed_beam)
+    opt.persistent = int(persistent)
+    opt.score_items = int(score_items)
+    pr = None
+    if prior is not None:
+        pr = np.ascontiguousarray(prior, dtype=np.float32).reshape(1088)
+        opt.prior = pr.ctypes.data
+    opt.stream = _stream(stream)
+    rng = _range(rmin, rmax)
+    res = Result()
+    _check(lib().bbs_localize_noalloc(bmap.handle, ptr, k, dev, C.byref(rng), int(score_threshold), C.byref(opt),
+                                      C.byref(res)))
     del keep, pr
     return res.as_dict()
 

@@ -19,6 +19,7 @@
 #include <climits>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "bbs_internal.h"
@@ -1718,20 +1719,6 @@ bool is_pow2_float(float r)
     return m == 0.5f;
 }
 
-template <class T>
-bbs_status ensure(T *&p, int64_t &cap, int64_t need)
-{
-    if (p && cap >= need) return BBS_OK;
-    if (p) (void)hipFree(p);
-    p = nullptr;
-    cap = 0;
-    int64_t n = std::max<int64_t>(need, 1);
-    void *q = nullptr;
-    if (alloc_dev(&q, (size_t)n * sizeof(T))) return BBS_ERR_OOM;
-    p = static_cast<T *>(q);
-    cap = n;
-    return BBS_OK;
-}
 
 }  // namespace
 }  // namespace bbs
@@ -1806,10 +1793,65 @@ struct bbs_workspace {
     hipEvent_t sync_ev[2] = {nullptr, nullptr};
     std::vector<hipEvent_t> ev;
     bool hist_dirty = true;
+    // no-allocation mode (bbs_localize_noalloc): every buffer is carved from
+    // one fixed device region for the duration of a call; nothing is
+    // allocated or freed
+    bool fixed = false;
+    char *fixed_base = nullptr;
+    size_t fixed_used = 0, fixed_cap = 0;
 };
 
 namespace bbs {
 namespace {
+
+// Grows a workspace buffer to at least `need` elements (contents are not
+// kept).  In no-allocation mode the buffer is instead carved, 256-byte
+// aligned, from the workspace's fixed region; running out of it is an
+// argument error, since the caller chose the region's size.
+template <class T>
+bbs_status ensure(bbs_workspace *w, T *&p, int64_t &cap, int64_t need)
+{
+    if (p && cap >= need) return BBS_OK;
+    const int64_t n = std::max<int64_t>(need, 1);
+    if (w->fixed) {
+        const size_t off = (w->fixed_used + 255) & ~(size_t)255;
+        const size_t bytes = (size_t)n * sizeof(T);
+        if (p || off > w->fixed_cap || bytes > w->fixed_cap - off)
+            return fail(BBS_ERR_INVALID_ARG, "bbs_localize_noalloc: the search needs more device memory than the "
+                                             "static scratch region holds (BBS_NOALLOC_SCRATCH_BYTES)");
+        p = reinterpret_cast<T *>(w->fixed_base + off);
+        cap = n;
+        w->fixed_used = off + bytes;
+        return BBS_OK;
+    }
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    cap = 0;
+    void *q = nullptr;
+    if (alloc_dev(&q, (size_t)n * sizeof(T))) return BBS_ERR_OOM;
+    p = static_cast<T *>(q);
+    cap = n;
+    return BBS_OK;
+}
+
+// Status of a failed ensure(): the message is already set.
+inline bbs_status ws_fail(const bbs_workspace *w) { return w->fixed ? BBS_ERR_INVALID_ARG : BBS_ERR_OOM; }
+
+// Zeroes `bytes` (a multiple of 4) with a fill kernel rather than a memset
+// node, so that the same code may be captured into a graph.
+__global__ void k_zero_u32(uint32_t *p, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
+hipError_t zero_async(void *p, size_t bytes, hipStream_t s)
+{
+    const int64_t n = (int64_t)(bytes / 4);
+    if (n <= 0) return hipSuccess;
+    k_zero_u32<<<grid_for(n, 256, 2048), 256, 0, s>>>(static_cast<uint32_t *>(p), n);
+    return hipGetLastError();
+}
 
 void free_ws(bbs_workspace *w)
 {
@@ -1908,22 +1950,22 @@ bbs_status setup_search(const bbs_map *m, bbs_workspace *ws, const float *scan, 
     if (batch < 1 || batch > (1 << 24)) return fail(BBS_ERR_INVALID_ARG, "bbs_localize: batch_size must be in [1, 2^24]");
     S.s = s;
     if (!ws->ticket) {
-        if (ensure(ws->ticket, ws->ticket_n, 2)) return BBS_ERR_OOM;
-        BBS_HIP(hipMemsetAsync(ws->ticket, 0, 2 * sizeof(int32_t), s));
+        if (ensure(ws, ws->ticket, ws->ticket_n, 2)) return ws_fail(ws);
+        BBS_HIP(zero_async(ws->ticket, 2 * sizeof(int32_t), s));
     }
     const int64_t kp = (k + kScanPad - 1) / kScanPad * kScanPad;
     S.kpad = kp;
-    if (ensure(ws->scan, ws->scan_n, 3 * kp) || ensure(ws->scan_tmp, ws->scan_tmp_n, 3 * k) ||
-        ensure(ws->mkeys, ws->mkeys_n, k) || ensure(ws->mhist, ws->mhist_n, kMortonBins) ||
-        ensure(ws->maxsq, ws->maxsq_n, 1))
-        return BBS_ERR_OOM;
+    if (ensure(ws, ws->scan, ws->scan_n, 3 * kp) || ensure(ws, ws->scan_tmp, ws->scan_tmp_n, 3 * k) ||
+        ensure(ws, ws->mkeys, ws->mkeys_n, k) || ensure(ws, ws->mhist, ws->mhist_n, kMortonBins) ||
+        ensure(ws, ws->maxsq, ws->maxsq_n, 1))
+        return ws_fail(ws);
     const float *aos = scan;
     if (!on_device) {
-        if (ensure(ws->scan_aos, ws->scan_aos_n, 3 * k)) return BBS_ERR_OOM;
+        if (ensure(ws, ws->scan_aos, ws->scan_aos_n, 3 * k)) return ws_fail(ws);
         BBS_HIP(hipMemcpyAsync(ws->scan_aos, scan, (size_t)k * 12, hipMemcpyHostToDevice, s));
         aos = ws->scan_aos;
     }
-    BBS_HIP(hipMemsetAsync(ws->maxsq, 0, 8, s));
+    BBS_HIP(zero_async(ws->maxsq, 8, s));
     k_scan_soa<<<grid_for(k, 256, 1024), 256, 0, s>>>(aos, (int32_t)k, ws->scan_tmp, ws->scan_tmp + k,
                                                        ws->scan_tmp + 2 * k, ws->maxsq);
     BBS_HIP(hipGetLastError());
@@ -1939,7 +1981,7 @@ bbs_status setup_search(const bbs_map *m, bbs_workspace *ws, const float *scan, 
     {
         const float lo = -(float)dmax - 1.0f;
         const float inv_cell = (float)(1 << kMortonBits) / (2.0f * ((float)dmax + 1.0f));
-        BBS_HIP(hipMemsetAsync(ws->mhist, 0, kMortonBins * sizeof(int32_t), s));
+        BBS_HIP(zero_async(ws->mhist, kMortonBins * sizeof(int32_t), s));
         const float *tx = ws->scan_tmp, *ty = ws->scan_tmp + k, *tz = ws->scan_tmp + 2 * k;
         k_morton_hist<<<grid_for(k, 256, 1024), 256, 0, s>>>(tx, ty, tz, (int32_t)k, lo, inv_cell, ws->mkeys,
                                                               ws->mhist);
@@ -1993,7 +2035,7 @@ bbs_status setup_search(const bbs_map *m, bbs_workspace *ws, const float *scan, 
     C.inv_r = 1.0f / g.r;
     C.r_pow2 = S.pow2 ? 1 : 0;
     C.score_items = 2048;
-    if (ensure(ws->trig, ws->trig_n, (int64_t)trig.size())) return BBS_ERR_OOM;
+    if (ensure(ws, ws->trig, ws->trig_n, (int64_t)trig.size())) return ws_fail(ws);
     BBS_HIP(hipMemcpyAsync(ws->trig, trig.data(), trig.size() * sizeof(double2), hipMemcpyHostToDevice, s));
     return BBS_OK;
 }
@@ -2154,22 +2196,15 @@ double ms_since(std::chrono::steady_clock::time_point t0)
 
 }  // namespace
 
-extern "C" bbs_status bbs_localize(const bbs_map *map, bbs_workspace *ws, const float *scan_xyz, int64_t k,
-                                   int32_t scan_on_device, const bbs_search_range *range, int32_t score_threshold,
-                                   const bbs_options *opt, bbs_result *out)
+namespace {
+
+// The search of bbs_localize on a prepared workspace (growing buffers, or a
+// fixed region in no-allocation mode, which also checks the end of the
+// search synchronously instead of through events and pinned memory).
+bbs_status localize_impl(const bbs_map *map, bbs_workspace *ws, const float *scan_xyz, int64_t k,
+                         int32_t scan_on_device, const bbs_search_range *range, int32_t score_threshold,
+                         const bbs_options &o, bbs_result *out)
 {
-    if (!out) return fail(BBS_ERR_INVALID_ARG, "bbs_localize: out is NULL");
-    std::memset(out, 0, sizeof(*out));
-    if (!map) return fail(BBS_ERR_INVALID_ARG, "bbs_localize: map is NULL");
-    bbs_options o;
-    bbs_default_options(&o);
-    if (opt) o = *opt;
-    WsGuard tmp;
-    if (!ws) {
-        bbs_status st = bbs_workspace_create(0, &tmp.w);
-        if (st) return st;
-        ws = tmp.w;
-    }
     const auto t_start = std::chrono::steady_clock::now();
     hipStream_t s = o.stream ? static_cast<hipStream_t>(o.stream) : ws->own_stream;
     Setup S;
@@ -2202,33 +2237,50 @@ extern "C" bbs_status bbs_localize(const bbs_map *map, bbs_workspace *ws, const 
     const int64_t cap_groups = std::max<int64_t>(o.batch_size + mc, 4096);
     const int64_t n_tiles = (cap_groups + kTileGroups - 1) / kTileGroups;
     const int64_t qn = std::max<int32_t>(C.q_count, 1);
-    const int64_t chunk_cap = std::max<int64_t>(ws->queue_nodes / kChunk, 16);
-    if (ensure(ws->groups, ws->groups_n, cap_groups) || ensure(ws->scores, ws->scores_n, 8 * cap_groups) ||
-        ensure(ws->kq, ws->kq_n, n_tiles * kTileSlots) || ensure(ws->knode, ws->knode_n, n_tiles * kTileSlots) ||
-        ensure(ws->kcnt, ws->kcnt_n, n_tiles) || ensure(ws->hbase, ws->hbase_n, n_tiles * qn) ||
-        ensure(ws->krank, ws->krank_n, n_tiles * kTileSlots) || ensure(ws->totals, ws->totals_n, qn) ||
-        ensure(ws->pT, ws->pT_n, qn) || ensure(ws->pf, ws->pf_n, qn) || ensure(ws->pc0, ws->pc0_n, qn) ||
-        ensure(ws->buckets, ws->buckets_n, qn) || ensure(ws->arena, ws->arena_n, chunk_cap * kChunk) ||
-        ensure(ws->chunk_next, ws->chunk_next_n, chunk_cap) ||
-        ensure(ws->state, ws->state_n, 1))
-        return BBS_ERR_OOM;
+    if (ensure(ws, ws->groups, ws->groups_n, cap_groups) || ensure(ws, ws->scores, ws->scores_n, 8 * cap_groups) ||
+        ensure(ws, ws->kq, ws->kq_n, n_tiles * kTileSlots) || ensure(ws, ws->knode, ws->knode_n, n_tiles * kTileSlots) ||
+        ensure(ws, ws->kcnt, ws->kcnt_n, n_tiles) || ensure(ws, ws->hbase, ws->hbase_n, n_tiles * qn) ||
+        ensure(ws, ws->krank, ws->krank_n, n_tiles * kTileSlots) || ensure(ws, ws->totals, ws->totals_n, qn) ||
+        ensure(ws, ws->pT, ws->pT_n, qn) || ensure(ws, ws->pf, ws->pf_n, qn) || ensure(ws, ws->pc0, ws->pc0_n, qn) ||
+        ensure(ws, ws->buckets, ws->buckets_n, qn) || ensure(ws, ws->state, ws->state_n, 1))
+        return ws_fail(ws);
     if (!ws->tile_done || ws->tile_done_n < n_tiles) {
-        if (ensure(ws->tile_done, ws->tile_done_n, n_tiles)) return BBS_ERR_OOM;
+        if (ensure(ws, ws->tile_done, ws->tile_done_n, n_tiles)) return ws_fail(ws);
         ws->hist_dirty = true;
     }
     if (!ws->hist || ws->hist_n < n_tiles * qn) {
-        if (ensure(ws->hist, ws->hist_n, n_tiles * qn)) return BBS_ERR_OOM;
+        if (ensure(ws, ws->hist, ws->hist_n, n_tiles * qn)) return ws_fail(ws);
         ws->hist_dirty = true;
     }
     if (!ws->qmask || ws->qmask_n < qn / 32 + 1) {
-        if (ensure(ws->qmask, ws->qmask_n, qn / 32 + 1) || ensure(ws->qlist, ws->qlist_n, qn)) return BBS_ERR_OOM;
+        if (ensure(ws, ws->qmask, ws->qmask_n, qn / 32 + 1) || ensure(ws, ws->qlist, ws->qlist_n, qn)) return ws_fail(ws);
         ws->hist_dirty = true;
     }
+    // the node queue: the workspace's capacity, or in no-allocation mode
+    // whatever the fixed region has left once the small buffers that a
+    // prior or the persistent loop may need have been carved too
+    int64_t chunk_cap = std::max<int64_t>(ws->queue_nodes / kChunk, 16);
+    if (ws->fixed) {
+        if (ensure(ws, ws->beam, ws->beam_n, 1) || ensure(ws, ws->dstate, ws->dstate_n, 1) ||
+            ensure(ws, ws->prior, ws->prior_n, 1088) || ensure(ws, ws->bar, ws->bar_n, 2))
+            return ws_fail(ws);
+        const size_t used = ((ws->fixed_used + 255) & ~(size_t)255) + 512;
+        const size_t left = ws->fixed_cap > used ? ws->fixed_cap - used : 0;
+        chunk_cap = std::min<int64_t>((int64_t)(left / ((size_t)kChunk * sizeof(uint4) + sizeof(int32_t))),
+                                      ws->queue_nodes / kChunk);
+        if (chunk_cap < 16)
+            return fail(BBS_ERR_INVALID_ARG, "bbs_localize_noalloc: the static scratch region leaves no room for "
+                                             "the node queue at this scan size and batch size");
+        ws->hist_dirty = true;   // the region keeps whatever the last call left in it
+    }
+    if (ensure(ws, ws->arena, ws->arena_n, chunk_cap * kChunk) ||
+        ensure(ws, ws->chunk_next, ws->chunk_next_n, chunk_cap))
+        return ws_fail(ws);
     if (ws->hist_dirty) {
-        BBS_HIP(hipMemsetAsync(ws->qmask, 0, (size_t)ws->qmask_n * 4, s));
-        BBS_HIP(hipMemsetAsync(ws->hist, 0, (size_t)ws->hist_n * 4, s));
-        BBS_HIP(hipMemsetAsync(ws->tile_done, 0, (size_t)ws->tile_done_n * 4, s));
-        BBS_HIP(hipMemsetAsync(ws->ticket, 0, 2 * sizeof(int32_t), s));
+        BBS_HIP(zero_async(ws->qmask, (size_t)ws->qmask_n * 4, s));
+        BBS_HIP(zero_async(ws->hist, (size_t)ws->hist_n * 4, s));
+        BBS_HIP(zero_async(ws->tile_done, (size_t)ws->tile_done_n * 4, s));
+        BBS_HIP(zero_async(ws->ticket, 2 * sizeof(int32_t), s));
         ws->hist_dirty = false;
     }
     k_fill_buckets<<<grid_for(qn, 256, 4096), 256, 0, s>>>(ws->buckets, (int32_t)qn);
@@ -2354,12 +2406,12 @@ extern "C" bbs_status bbs_localize(const bbs_map *map, bbs_workspace *ws, const 
             hb.nodes[i].score = cands[i].score;
             hb.nodes[i].key = cands[i].key;
         }
-        if (ensure(ws->beam, ws->beam_n, 1) || ensure(ws->dstate, ws->dstate_n, 1) ||
-            ensure(ws->prior, ws->prior_n, 1088))
-            return BBS_ERR_OOM;
+        if (ensure(ws, ws->beam, ws->beam_n, 1) || ensure(ws, ws->dstate, ws->dstate_n, 1) ||
+            ensure(ws, ws->prior, ws->prior_n, 1088))
+            return ws_fail(ws);
         BBS_HIP(hipMemcpyAsync(ws->beam, &hb, sizeof(hb), hipMemcpyHostToDevice, s));
         BBS_HIP(hipMemcpyAsync(ws->prior, o.prior, 1088 * sizeof(float), hipMemcpyHostToDevice, s));
-        BBS_HIP(hipMemsetAsync(ws->dstate, 0, sizeof(State), s));
+        BBS_HIP(zero_async(ws->dstate, sizeof(State), s));
         for (int step = 0; step < L; ++step) {
             k_beam_expand<<<1, 64, 0, s>>>(ws->beam, C, ws->groups, ws->scores, ws->state, ws->dstate);
             launch_score(S, map, ws, ws->dstate, 0, score_grid, false);
@@ -2386,8 +2438,8 @@ extern "C" bbs_status bbs_localize(const bbs_map *map, bbs_workspace *ws, const 
     // persistent search loop: one cooperative launch runs every iteration
     bool persistent_used = false;
     if (o.persistent && !init_done) {
-        if (ensure(ws->bar, ws->bar_n, 2)) return BBS_ERR_OOM;
-        BBS_HIP(hipMemsetAsync(ws->bar, 0, 2 * sizeof(unsigned), s));
+        if (ensure(ws, ws->bar, ws->bar_n, 2)) return ws_fail(ws);
+        BBS_HIP(zero_async(ws->bar, 2 * sizeof(unsigned), s));
         int dev = 0, cus = 0, per_cu = 0;
         BBS_HIP(hipGetDevice(&dev));
         BBS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
@@ -2467,7 +2519,24 @@ extern "C" bbs_status bbs_localize(const bbs_map *map, bbs_workspace *ws, const 
     // for that check.  Iterations queued after the search is done return at
     // once, and the state after the last group is the final one.
     const int64_t max_iters = (int64_t)1 << 26;
-    if (!persistent_used && !graph_used && !init_done) {
+    if (!persistent_used && !graph_used && !init_done && ws->fixed) {
+        // no events and no pinned memory: every two groups of iterations end
+        // with a synchronous read of the state
+        for (int64_t iters = 0;; iters += 2 * kItersPerSync) {
+            if (iters >= max_iters) {
+                BBS_HIP(hipStreamSynchronize(s));
+                return fail(BBS_ERR_INTERNAL, "bbs_localize: search did not terminate");
+            }
+            for (int it = 0; it < 2 * kItersPerSync; ++it) {
+                launch_score(S, map, ws, ws->state, 0, score_grid, true);
+                serial(1);
+            }
+            BBS_HIP(hipGetLastError());
+            BBS_HIP(hipMemcpyAsync(ws->host_state, ws->state, sizeof(State), hipMemcpyDeviceToHost, s));
+            BBS_HIP(hipStreamSynchronize(s));
+            if (ws->host_state->done || ws->host_state->error) break;
+        }
+    } else if (!persistent_used && !graph_used && !init_done) {
         State *slot[2] = {ws->host_state, ws->host_state2};
         auto issue = [&](int k) -> bbs_status {
             for (int it = 0; it < kItersPerSync; ++it) {
@@ -2559,6 +2628,84 @@ extern "C" bbs_status bbs_localize(const bbs_map *map, bbs_workspace *ws, const 
     return BBS_OK;
 }
 
+// Static scratch of bbs_localize_noalloc: one copy per GPU, held until the
+// process ends.  Host code never passes `scratch` itself to a kernel (on the
+// host it is only a stand-in for the symbol); it uses the device address
+// that hipGetSymbolAddress returns for the current device.
+constexpr size_t kNoAllocBytes = (size_t)BBS_NOALLOC_SCRATCH_BYTES;
+__device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's scratch, looked up once per device.
+bbs_status scratch_for_current_device(void **out)
+{
+    int dev = 0;
+    BBS_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(BBS_ERR_DEVICE, "bbs_localize_noalloc: device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return BBS_OK;
+}
+
+}  // namespace
+
+extern "C" bbs_status bbs_localize(const bbs_map *map, bbs_workspace *ws, const float *scan_xyz, int64_t k,
+                                   int32_t scan_on_device, const bbs_search_range *range, int32_t score_threshold,
+                                   const bbs_options *opt, bbs_result *out)
+{
+    if (!out) return fail(BBS_ERR_INVALID_ARG, "bbs_localize: out is NULL");
+    std::memset(out, 0, sizeof(*out));
+    if (!map) return fail(BBS_ERR_INVALID_ARG, "bbs_localize: map is NULL");
+    bbs_options o;
+    bbs_default_options(&o);
+    if (opt) o = *opt;
+    WsGuard tmp;
+    if (!ws) {
+        bbs_status st = bbs_workspace_create(0, &tmp.w);
+        if (st) return st;
+        ws = tmp.w;
+    }
+    return localize_impl(map, ws, scan_xyz, k, scan_on_device, range, score_threshold, o, out);
+}
+
+extern "C" bbs_status bbs_localize_noalloc(const bbs_map *map, const float *scan_xyz, int64_t k,
+                                           int32_t scan_on_device, const bbs_search_range *range,
+                                           int32_t score_threshold, const bbs_options *opt, bbs_result *out)
+{
+    if (!out) return fail(BBS_ERR_INVALID_ARG, "bbs_localize_noalloc: out is NULL");
+    std::memset(out, 0, sizeof(*out));
+    if (!map) return fail(BBS_ERR_INVALID_ARG, "bbs_localize_noalloc: map is NULL");
+    bbs_options o;
+    bbs_default_options(&o);
+    if (opt) o = *opt;
+    if (o.profile != 0 || o.graph != 0)
+        return fail(BBS_ERR_INVALID_ARG, "bbs_localize_noalloc: profile and graph need allocations; set both to 0");
+    void *base = nullptr;
+    bbs_status st = scratch_for_current_device(&base);
+    if (st) return st;
+    // a workspace that lives for this call only: its buffers are carved from
+    // the scratch, its host state is ordinary memory, it owns no stream
+    bbs_workspace w;
+    State host[2];
+    w.fixed = true;
+    w.fixed_base = static_cast<char *>(base);
+    w.fixed_cap = kNoAllocBytes;
+    w.queue_nodes = kDefaultQueueNodes;
+    w.host_state = &host[0];
+    w.host_state2 = &host[1];
+    (void)hipGetDevice(&w.device);
+    return localize_impl(map, &w, scan_xyz, k, scan_on_device, range, score_threshold, o, out);
+}
+
 extern "C" bbs_status bbs_score_nodes(const bbs_map *map, const float *scan_xyz, int64_t k,
                                       const bbs_search_range *range, int32_t translation_only, const int32_t *nodes,
                                       int64_t n, int32_t *scores)
@@ -2594,9 +2741,9 @@ extern "C" bbs_status bbs_score_nodes(const bbs_map *map, const float *scan_xyz,
         uint32_t mask = 1u << (4 * j[0] + 2 * j[1] + j[2]);
         groups[i] = make_uint4(pack16(b[0], b[1]), pack16(b[2], c[4]), pack16(c[5], c[6]), (uint32_t)level | (mask << 8));
     }
-    if (ensure(ws->groups, ws->groups_n, n) || ensure(ws->scores, ws->scores_n, 8 * n)) return BBS_ERR_OOM;
+    if (ensure(ws, ws->groups, ws->groups_n, n) || ensure(ws, ws->scores, ws->scores_n, 8 * n)) return ws_fail(ws);
     BBS_HIP(hipMemcpyAsync(ws->groups, groups.data(), (size_t)n * sizeof(uint4), hipMemcpyHostToDevice, s));
-    BBS_HIP(hipMemsetAsync(ws->scores, 0, (size_t)n * 8 * sizeof(int32_t), s));
+    BBS_HIP(zero_async(ws->scores, (size_t)n * 8 * sizeof(int32_t), s));
     launch_score(S, map, ws, nullptr, (int32_t)n, S.score_grid, false);
     BBS_HIP(hipGetLastError());
     std::vector<int32_t> all((size_t)n * 8);
