@@ -31,15 +31,22 @@ HBM_PEAK_GBS = 8000.0
 # 32-bit VALU lane-operations per second: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 # (the 157.3 TFLOP/s fp32 vector figure counts a packed FMA as 4 flops per lane-op)
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
-# ALU work per (node, scan point): 15 fp32 ops of the 3x3 transform and 3 floors,
-# shared by the 8 translational siblings of a rotation, plus ~10 integer ops
-OPS_PER_NODE_POINT = 18 / 8 + 10
+# A model of the ALU work per (node, scan point), kept for reference only: 15 fp32
+# ops of the 3x3 transform and 3 floors shared by the 8 translational siblings of
+# a rotation, plus about 10 integer ops
+MODEL_OPS_PER_NODE_POINT = 18 / 8 + 10
+# Algorithmic bytes of one lookup of the brick-column layout: the 8-byte column
+# entry answers a whole group of translational siblings for one scan point, and
+# the 12-byte scan point is read for it
+ALG_BYTES_PER_LOOKUP = 8 + 12
 # The timed localizations bracket every PROFILE_EVERY-th scoring launch with a
 # pair of HIP events on the library's stream; the mean of those launches gives
 # the kernel's duration.  Bracketing every launch added about 9 % to the
 # localization time (each event pair adds queue time between the kernels).
 PROFILE_EVERY = 8
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_score_city_traffic.md")
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_score_city_counters.md")
+GOLDEN_FILE = os.path.join(ROOT, "tests", "golden", "city_localize.json")
 WEIGHTS = os.path.join(ROOT, "paper_2310_10023_amd", "proposal_weights.npz")
 SCORE_SRC = os.path.join(ROOT, "paper_2310_10023_amd", "csrc", "bbs_search.hip")
 
@@ -51,52 +58,189 @@ def score_kernel_sha() -> str:
     return hashlib.sha256((m.group(0) if m else text).encode()).hexdigest()[:16]
 
 
-def measured_traffic():
-    """Per-launch HBM bytes of the scoring kernel from the committed counter
-    summary, or None when it is missing or was taken on other kernel code."""
+def profile_record(path):
+    """The machine-readable record of a committed profile summary, or None
+    when it is missing or was taken on other scoring-kernel code."""
     try:
-        text = open(TRAFFIC_FILE).read()
+        text = open(path).read()
         m = re.search(r"```json\n(.*?)\n```", text, flags=re.S)
         d = json.loads(m.group(1)) if m else {}
     except (OSError, ValueError):
         return None
-    if d.get("kernel_sha") != score_kernel_sha():
+    return d if d.get("kernel_sha") == score_kernel_sha() else None
+
+
+def rot_error(a, b):
+    """Angle (rad) of the relative rotation between two roll/pitch/yaw triples."""
+    import math
+
+    import numpy as np
+
+    import synth
+    Ra, Rb = synth.rotation_zyx(*a), synth.rotation_zyx(*b)
+    return math.acos(max(-1.0, min(1.0, (float(np.trace(Ra.T @ Rb)) - 1.0) / 2.0)))
+
+
+def success(result, true_pose):
+    """The success criterion of Sec. IV: translation error below 2.0 m and
+    rotation error below 0.05 rad."""
+    import numpy as np
+    if not result["found"]:
+        return False
+    p = np.array(result["pose"], np.float64)
+    return float(np.linalg.norm(p[:3] - true_pose[:3])) < 2.0 and rot_error(p[3:], true_pose[3:]) < 0.05
+
+
+def pct(v, q):
+    v = sorted(v)
+    return v[min(len(v) - 1, int(q * len(v)))] if v else None
+
+
+def golden_parity(results, seeds, k, batch):
+    """How many timed results equal the oracle's stored results (every field)."""
+    try:
+        doc = json.load(open(GOLDEN_FILE))
+    except (OSError, ValueError):
         return None
-    return d.get("bytes_per_launch")
+    case = doc.get("cases", {}).get("bench", {})
+    if case.get("k") != k or case.get("batch") != batch:
+        return None
+    q = case.get("queries", {})
+    keys = ("found", "score", "leaf", "nodes_expanded", "nodes_scored", "flushes", "leaves_accepted",
+            "initial_size", "initial_kept")
+    n = eq = 0
+    for s, r in zip(seeds, results):
+        w = q.get(str(s))
+        if w is None:
+            continue
+        n += 1
+        eq += all(r[f] == w[f] for f in keys)
+    return f"{eq}/{n} equal to {os.path.relpath(GOLDEN_FILE, ROOT)} (of {len(seeds)} timed queries)"
+
+
+def with_one_core(fn):
+    """Run fn() with this thread pinned to one host core; returns (result, core)."""
+    old = os.sched_getaffinity(0)
+    core = max(old)
+    os.sched_setaffinity(0, {core})
+    try:
+        return fn(), core
+    finally:
+        os.sched_setaffinity(0, old)
 
 
 def cpu_baseline(points, scan, lo, hi, T, batch, seconds):
-    """The oracle (unchanged) on the same workload, bounded to about `seconds`
-    of CPU work: the first nodes of the first timed query's search."""
+    """The oracle (unchanged) on the same workload, bounded to a few seconds
+    of CPU work each: the first nodes of the first timed query's search, on
+    one pinned core (single thread) and with OpenMP over each scored batch."""
     import oracle
-    threads = max(1, min(16, os.cpu_count() or 1))
     omap = oracle.Map(points, 1.0, 6)
     s = oracle.Search(omap, scan, lo, hi)
+
+    def sample(threads, secs):
+        t0 = time.perf_counter()
+        probe = s.localize(T, batch=batch, threads=threads, max_scored=1000)
+        rate = probe["nodes_scored"] / max(time.perf_counter() - t0, 1e-6)
+        budget = int(max(1000, rate * secs))
+        t0 = time.perf_counter()
+        r = s.localize(T, batch=batch, threads=threads, max_scored=budget)
+        dt = time.perf_counter() - t0
+        return r["nodes_scored"], dt
+
+    (n1, dt1), core = with_one_core(lambda: sample(1, seconds / 2))
+    threads = max(1, min(16, len(os.sched_getaffinity(0))))
+    nm, dtm = sample(threads, seconds / 2)
+    return {"value": n1 / dt1, "unit": "nodes/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {n1} nodes scored of the search of query seed 0, single thread pinned to host core "
+                      f"{core}, {dt1:.1f} s",
+            "multi_thread": {"value": nm / dtm, "unit": "nodes/s", "cores": threads,
+                             "sample": f"first {nm} nodes scored of the same search, OpenMP over each scored batch, "
+                                       f"{dtm:.1f} s"}}
+
+
+def indoor_leg(seconds):
+    """The tiny indoor configuration: room 20 x 20 x 5 m, r = 0.5 m, l_max = 4,
+    2,000-point scans, plain BnB at b = 10,000.  GPU ms per localization over
+    query seeds 0..19, and the oracle's CPU seconds per localization (single
+    thread, one pinned core) on as many of the same seeds as fit in `seconds`."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_2310_10023_amd as bbs
+    import synth
+    scene = synth.room_scene(0)
+    lo, hi = synth.search_range_room()
+    T = synth.threshold_95(2000)
+    scans = [synth.room_query(scene, s, 2000) for s in range(20)]
+    gmap = bbs.Map(torch.from_numpy(scene.points).cuda(), 0.5, 4)
+    dev = [torch.from_numpy(sc.points).cuda() for sc in scans]
+    ws = bbs.Workspace()
+    bbs.localize(gmap, dev[0], lo, hi, T, workspace=ws)
+    gpu_ms, res = [], []
+    for d in dev:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res.append(bbs.localize(gmap, d, lo, hi, T, workspace=ws))
+        torch.cuda.synchronize()
+        gpu_ms.append((time.perf_counter() - t0) * 1e3)
+    omap = oracle.Map(scene.points, 0.5, 4)
+
+    def run_oracle():
+        out = []
+        t_end = time.perf_counter() + seconds
+        for sc, g in zip(scans, res):
+            if time.perf_counter() > t_end:
+                break
+            t0 = time.perf_counter()
+            w = oracle.Search(omap, sc.points, lo, hi).localize(T, batch=10000, threads=1)
+            out.append(((time.perf_counter() - t0) * 1e3, w, g))
+        return out
+
+    runs, core = with_one_core(run_oracle)
+    keys = ("found", "score", "leaf", "nodes_expanded", "nodes_scored", "flushes")
+    cpu_ms = [m for m, _, _ in runs]
+    return {
+        "workload": f"room 20x20x5 m seed 0 ({len(scene.points)} pts), r=0.5 m, l_max=4, 2000-pt scans (query seeds "
+                    "0..19), roll/pitch +-2 deg, threshold 1900, b=10000, plain batched BnB",
+        "gpu_ms_per_localization_p50": pct(gpu_ms, 0.5), "gpu_ms_per_localization_p99": pct(gpu_ms, 0.99),
+        "gpu_ms_per_localization_mean": float(np.mean(gpu_ms)),
+        "found": f"{sum(r['found'] for r in res)}/{len(res)}",
+        "success_2m_0p05rad": f"{sum(success(r, sc.pose) for r, sc in zip(res, scans))}/{len(res)}",
+        "oracle_cpu_s_per_localization_p50": pct(cpu_ms, 0.5) / 1e3 if cpu_ms else None,
+        "oracle_cpu_s_per_localization_p99": pct(cpu_ms, 0.99) / 1e3 if cpu_ms else None,
+        "oracle_queries": len(runs), "oracle_cores": 1, "oracle_core": core,
+        "oracle_equal_to_gpu": f"{sum(all(w[f] == g[f] for f in keys) for _, w, g in runs)}/{len(runs)}",
+    }
+
+
+def timed_leg(gmap, dev, seeds, lo, hi, T, batch, ws, **kw):
+    import torch
+
+    import paper_2310_10023_amd as bbs
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    probe = s.localize(T, batch=batch, threads=threads, max_scored=2000)
-    rate = probe["nodes_scored"] / max(time.perf_counter() - t0, 1e-6)
-    budget = int(max(4000, rate * seconds))
-    t0 = time.perf_counter()
-    r = s.localize(T, batch=batch, threads=threads, max_scored=budget)
-    dt = time.perf_counter() - t0
-    return {"value": r["nodes_scored"] / dt, "unit": "nodes/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {r['nodes_scored']} nodes scored (of the search) of query seed 0, "
-                      f"{dt:.1f} s, OpenMP over each scored batch"}
+    out = [bbs.localize(gmap, dev[s], lo, hi, T, batch_size=batch, workspace=ws, **kw) for s in seeds]
+    torch.cuda.synchronize()
+    return out, time.perf_counter() - t0
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=12)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--k", type=int, default=10000, help="scan points")
     ap.add_argument("--batch", type=int, default=10000, help="b")
-    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="CPU seconds of each bounded oracle sample (city: split over 1 core and all cores; indoor)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--details", default=None, help="write per-step results to this JSON file")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 plain device copies of MIB MiB (to scale HBM byte counters) and exit")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-order comparison")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="time the plain launches only (no persistent, graph, indoor or bandwidth legs)")
     ap.add_argument("--beam", type=int, default=8, help="seed beam width of the learned-order search")
     ap.add_argument("--stream", action="store_true",
                     help="run the 256-query stream workload instead (throughput, p50/p99 latency)")
@@ -139,8 +283,7 @@ def main():
     T = synth.threshold_95(args.k)
     warm_seeds = list(range(100, 100 + args.warmup))
     seeds = list(range(args.steps))
-    scans = {s: synth.scan_scene(city, s, args.k, z=1.8, rp_deg=3.0, n_beams=64, n_az=2048, voxel=0.5)
-             for s in warm_seeds + seeds}
+    scans = {s: synth.city_query(city, s, args.k, voxel=0.5) for s in warm_seeds + seeds}
     print(f"[bench] inputs ready in {time.perf_counter() - t0:.1f} s: {len(city.points)} map points, "
           f"{len(scans)} scans of {args.k}", file=sys.stderr, flush=True)
 
@@ -156,37 +299,45 @@ def main():
         bbs.localize(gmap, dev[s], lo, hi, T, batch_size=args.batch, profile=PROFILE_EVERY, workspace=ws)
     torch.cuda.synchronize()
 
-    results = []
-    t0 = time.perf_counter()
-    for s in seeds:
-        results.append(bbs.localize(gmap, dev[s], lo, hi, T, batch_size=args.batch, profile=PROFILE_EVERY,
-                                    workspace=ws))
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+    results, elapsed = timed_leg(gmap, dev, seeds, lo, hi, T, args.batch, ws, profile=PROFILE_EVERY)
     print(f"[bench] timed {len(seeds)} localizations in {elapsed:.3f} s", file=sys.stderr, flush=True)
 
     nodes = sum(r["nodes_scored"] for r in results)
     groups = sum(r["score_groups"] for r in results)
     launches = sum(r["score_launches"] for r in results)
     kern_ms = sum(r["score_kernel_ms"] for r in results)
-    # algorithmic work of the scoring kernel per launch: ALU ops per node-point
-    # (its bound: VALU issue), and for reference the memory a one-key-per-voxel
-    # table would read (one 8-byte key per node-point test, the 12-byte scan
-    # point once per group of siblings sharing a rotation)
-    pairs = nodes * args.k
-    alg_ops = pairs * OPS_PER_NODE_POINT
-    achieved = alg_ops / (kern_ms * 1e-3) / 1e12 if kern_ms > 0 else 0.0
-    alg_bytes = nodes * args.k * 8 + groups * args.k * 12
-    hbm_alg_gbs = alg_bytes / (kern_ms * 1e-3) / 1e9 if kern_ms > 0 else 0.0
-    traffic = measured_traffic()
-    lat = sorted(r["phase_ms"][3] for r in results)
-    found = sum(r["found"] for r in results)
-    errs = []
-    for s, r in zip(seeds, results):
-        if r["found"]:
-            p = np.array(r["pose"], np.float64)
-            errs.append(float(np.linalg.norm(p[:3] - scans[s].pose[:3])))
+    t_launch = kern_ms / max(launches, 1) * 1e-3            # seconds per scoring launch
+    lookups = groups * args.k / max(launches, 1)              # group lookups per launch
+    lat = [r["phase_ms"][3] for r in results]
+    found_ms = [m for m, r in zip(lat, results) if r["found"]]
+    lost_ms = [m for m, r in zip(lat, results) if not r["found"]]
+    ok = sum(success(r, scans[s].pose) for s, r in zip(seeds, results))
 
+    cnt = profile_record(COUNTERS_FILE)
+    traffic = profile_record(TRAFFIC_FILE)
+    valu_per_lookup = cnt.get("valu_lane_instr_per_lookup") if cnt else None
+    achieved = valu_per_lookup * lookups / t_launch / 1e12 if valu_per_lookup and t_launch > 0 else None
+    roofline = {
+        "bound": "alu",
+        "achieved": achieved,
+        "peak": VALU_PEAK_TOPS,
+        "unit": "T VALU lane-instructions/s (issued: SQ_INSTS_VALU x 64 per lookup from the counter profile x live "
+                "lookups per launch / live launch time)",
+        "frac": achieved / VALU_PEAK_TOPS if achieved else None,
+        "traffic": traffic.get("bytes_per_launch") if traffic else None,
+        "traffic_unit": "HBM bytes per launch (FETCH_SIZE x2.0 + WRITE_SIZE x1.0, copy-calibrated)",
+        "kernel": "k_score",
+        "launches": launches,
+        "avg_launch_us": t_launch * 1e6,
+        "lookups_per_launch": lookups,
+        "valu_lane_instr_per_lookup": valu_per_lookup,
+        "counter_profile": os.path.relpath(COUNTERS_FILE, ROOT) if cnt else None,
+        "model_ops_per_node_point": MODEL_OPS_PER_NODE_POINT,
+        "model_frac": (nodes * args.k * MODEL_OPS_PER_NODE_POINT / (kern_ms * 1e-3) / 1e12 / VALU_PEAK_TOPS
+                       if kern_ms > 0 else None),
+        "alg_bytes_per_launch": lookups * ALG_BYTES_PER_LOOKUP,
+        "alg_gbs": lookups * ALG_BYTES_PER_LOOKUP / t_launch / 1e9 if t_launch > 0 else None,
+    }
     line = {
         "metric": METRIC,
         "value": nodes / elapsed,
@@ -206,48 +357,65 @@ def main():
                         f"threshold {T}, b={args.batch}, plain batched BnB",
             "mode": "plain",
             "ms_per_localization_mean": elapsed / len(seeds) * 1e3,
-            "ms_per_localization_p50": lat[len(lat) // 2],
+            "ms_per_localization_p50": pct(lat, 0.5),
+            "ms_per_localization_p99": pct(lat, 0.99),
+            "ms_per_localization_found_mean": float(np.mean(found_ms)) if found_ms else None,
+            "ms_per_localization_not_found_mean": float(np.mean(lost_ms)) if lost_ms else None,
             "nodes_scored_total": nodes,
-            "found": f"{found}/{len(seeds)}",
+            "nodes_expanded_total": sum(r["nodes_expanded"] for r in results),
+            "found": f"{sum(r['found'] for r in results)}/{len(seeds)}",
+            "success_2m_0p05rad": f"{ok}/{len(seeds)}",
+            "parity_vs_oracle": golden_parity(results, seeds, args.k, args.batch),
             "map_build_ms": map_ms,
             "score_kernel_ms_mean": kern_ms / len(seeds),
             "serial_push_ms_mean": sum(r["serial_ms"][0] for r in results) / len(seeds),
             "serial_gather_ms_mean": sum(r["serial_ms"][1] for r in results) / len(seeds),
-            "serial_push_prefix_ms_mean": sum(r["serial_ms"][2] for r in results) / len(seeds),
-            "serial_push_alloc_ms_mean": sum(r["serial_ms"][3] for r in results) / len(seeds),
             "iterations_mean": launches / len(seeds),
         },
-        "roofline": {
-            "bound": "alu",
-            "achieved": achieved,
-            "peak": VALU_PEAK_TOPS,
-            "unit": "Tops/s (32-bit VALU lane-operations)",
-            "frac": achieved / VALU_PEAK_TOPS,
-            "traffic": traffic,
-            "traffic_unit": "HBM bytes per launch (FETCH_SIZE x2.0 + WRITE_SIZE x1.0, copy-calibrated)",
-            "kernel": "k_score",
-            "launches": launches,
-            "avg_launch_us": kern_ms / max(launches, 1) * 1e3,
-            "alg_ops_per_launch": alg_ops / max(launches, 1),
-            "ops_per_node_point": OPS_PER_NODE_POINT,
-            "lookups_per_s": groups * args.k / (kern_ms * 1e-3) if kern_ms > 0 else 0.0,
-            "hbm_algorithmic_gbs": hbm_alg_gbs,
-            "hbm_algorithmic_frac": hbm_alg_gbs / HBM_PEAK_GBS,
-            "alg_bytes_per_launch": alg_bytes / max(launches, 1),
-        },
+        "roofline": roofline,
         "cpu_baseline": None,
     }
+    if not args.no_extra:
+        same = lambda rr: sum(a["found"] == b["found"] and a["leaf"] == b["leaf"] and a["score"] == b["score"] and
+                              a["nodes_expanded"] == b["nodes_expanded"] for a, b in zip(rr, results))
+        for mode, kw in (("persistent", {"persistent": True}), ("graph", {"graph": True})):
+            bbs.localize(gmap, dev[warm_seeds[0] if warm_seeds else 0], lo, hi, T, batch_size=args.batch,
+                         workspace=ws, **kw)
+            rr, dt = timed_leg(gmap, dev, seeds, lo, hi, T, args.batch, ws, **kw)
+            line["config"][mode] = {"ms_per_localization_mean": dt / len(seeds) * 1e3,
+                                    "nodes_per_s": sum(r["nodes_scored"] for r in rr) / dt,
+                                    "same_result_as_plain": f"{same(rr)}/{len(seeds)}"}
+            print(f"[bench] {mode}: {line['config'][mode]}", file=sys.stderr, flush=True)
+        # achievable memory rates: a streaming read of 1 GiB (HBM) and random
+        # 8-byte gathers into a table of the size of the map's level grids
+        info = gmap.info()
+        grid_bytes = sum(8 * n for n in info["dense_entries"])
+        probes = {"stream_1gib": bbs.bandwidth_probe("stream", 1 << 30),
+                  "gather_level_grids": bbs.bandwidth_probe("gather", max(grid_bytes, 1 << 16), 1 << 27)}
+        roofline["achievable"] = probes
+        roofline["alg_frac_of_gather"] = (roofline["alg_gbs"] / probes["gather_level_grids"]["gbs"]
+                                          if roofline["alg_gbs"] else None)
+        if cnt and t_launch > 0:
+            req = cnt["l2_read_req_per_lookup"] * lookups / t_launch
+            roofline["l2_read_requests_per_s"] = req
+            # one request per 8-byte gather in the probe: its load rate is the achievable request rate
+            roofline["l2_frac_of_gather_requests"] = req / (probes["gather_level_grids"]["gbs"] * 1e9 / 8)
+        if traffic and t_launch > 0:
+            roofline["hbm_gbs"] = traffic["bytes_per_launch"] / t_launch / 1e9
+            roofline["hbm_frac_of_stream"] = roofline["hbm_gbs"] / probes["stream_1gib"]["gbs"]
     learned = None
     if not args.no_learned and os.path.exists(WEIGHTS):
         learned = learned_order(gmap, dev, seeds, results, lo, hi, T, args)
         line["config"]["learned"] = learned["summary"]
     if args.details:
         with open(args.details, "w") as f:
-            json.dump({"seeds": seeds, "results": results, "pose_err_m": errs,
+            json.dump({"seeds": seeds, "results": results,
                        "learned": learned["results"] if learned else None}, f, indent=1)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(city.points, scans[seeds[0]].points, lo, hi, T, args.batch,
                                             args.cpu_seconds)
+        if not args.no_extra:
+            line["config"]["indoor"] = indoor_leg(args.cpu_seconds)
     print(json.dumps(line), flush=True)
 
 

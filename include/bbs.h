@@ -316,6 +316,22 @@ bbs_status bbs_autotune(const bbs_map *map, const bbs_query *queries, int64_t n,
                         int32_t n_b, const int32_t *score_items, int32_t n_items, const bbs_options *base,
                         bbs_tune_entry *best, bbs_tune_entry *all);
 
+/*
+ * Achievable memory rates of the current GPU (measurement only; the search
+ * never calls it): the denominators of the scoring kernel's memory roofline.
+ * Not from the paper, which reports no kernel rates.
+ *   kind 0          streaming read: every 16-byte word of a table_bytes
+ *                   buffer read once per pass (several passes), coalesced
+ *   kind 1          random gathers: `loads` independent 8-byte loads at
+ *                   hashed positions of a table of at most table_bytes (the
+ *                   largest power of two of 8-byte entries that fits)
+ *   table_bytes     in [4096, 2^36]; loads (kind 1) in [1, 2^34]
+ *   gbs, ms         useful bytes per second / 1e9 (kind 1: 8 bytes per load)
+ *                   and the kernel time, best of five timed runs (host)
+ * Allocates the table for the duration of the call.
+ */
+bbs_status bbs_bandwidth_probe(int32_t kind, int64_t table_bytes, int64_t loads, double *gbs, double *ms);
+
 #ifdef __cplusplus
 }
 #endif

@@ -26,6 +26,7 @@ EXPORTED_SYMBOLS = (
     "bbs_map_layout", "bbs_map_dump_level", "bbs_map_contains", "bbs_workspace_create", "bbs_workspace_free", "bbs_localize", "bbs_localize_noalloc",
     "bbs_score_nodes", "bbs_serve", "bbs_net_param_count", "bbs_net_create", "bbs_net_free", "bbs_net_set_params",
     "bbs_net_get_params", "bbs_net_forward", "bbs_net_train_step", "bbs_bev_image", "bbs_autotune",
+    "bbs_bandwidth_probe",
 )
 
 STATUS = {0: "OK", -1: "INVALID_ARG", -2: "OOM", -3: "DEVICE", -4: "QUEUE_OVERFLOW", -5: "INTERNAL"}
@@ -127,6 +128,8 @@ def lib():
         L.bbs_autotune.argtypes = [P, C.POINTER(Query), I64, P, I32, P, I32, C.POINTER(Options),
                                    C.POINTER(TuneEntry), P]
         L.bbs_autotune.restype = C.c_int
+        L.bbs_bandwidth_probe.argtypes = [I32, I64, I64, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.bbs_bandwidth_probe.restype = C.c_int
         _lib = L
     return _lib
 
@@ -389,3 +392,13 @@ def serve(bmap: Map, scans, ranges, thresholds, arrivals, *, workers: int = 4, b
                            t_end.ctypes.data))
     del keep
     return [res[i].as_dict() for i in range(n)], t_start[:n], t_end[:n]
+
+def bandwidth_probe(kind: str, table_bytes: int, loads: int = 1 << 26) -> dict:
+    """Achievable memory rate of the GPU: kind "stream" (coalesced read of the
+    whole table) or "gather" (random 8-byte loads into the table).  Returns
+    {"gbs": useful GB/s, "ms": kernel time, "table_bytes": ...}."""
+    gbs, ms = C.c_double(), C.c_double()
+    k = {"stream": 0, "gather": 1}[kind]
+    _check(lib().bbs_bandwidth_probe(k, int(table_bytes), int(loads), C.byref(gbs), C.byref(ms)))
+    return {"kind": kind, "gbs": gbs.value, "ms": ms.value, "table_bytes": int(table_bytes),
+            "loads": int(loads) if k == 1 else None}
