@@ -251,6 +251,13 @@ def main():
                          "and loop form (launches or persistent kernel) autotuned per scan size on separate "
                          "sample queries")
     ap.add_argument("--tuned-queries", type=int, default=20)
+    ap.add_argument("--table1", action="store_true",
+                    help="run the nine configurations of the paper's Table I (processing type x branching x search "
+                         "strategy) on the tiny indoor workload instead")
+    ap.add_argument("--table1-k", type=int, default=1000, help="scan points of the Table I workload")
+    ap.add_argument("--table1-queries", type=int, default=10)
+    ap.add_argument("--table1-cpu-seconds", type=float, default=20.0,
+                    help="CPU seconds each CPU configuration of Table I may spend (it runs as many queries as fit)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported "
@@ -277,6 +284,8 @@ def main():
         return stream_bench(args)
     if args.tuned:
         return tuned_bench(args)
+    if args.table1:
+        return table1_bench(args)
     t0 = time.perf_counter()
     city = synth.city_scene(1000)
     lo, hi = synth.search_range_city()
@@ -526,6 +535,96 @@ def tuned_bench(args):
         "config": {"workload": f"city seed 1000, scans of 5k/10k/20k pts (query seeds 0..{args.tuned_queries - 1}), "
                                "b, scoring tile and loop form (launches or persistent kernel) autotuned on seeds "
                                "300..302", "per_k": out},
+    }
+    print(json.dumps(line), flush=True)
+
+
+def table1_bench(args):
+    """Table I of the paper on synthetic maps: the nine combinations of
+    processing type (CPU one thread, CPU four threads, GPU), branching
+    (translation only, or translation and rotation) and search strategy
+    (depth first, best first), on the tiny indoor workload (room, r = 0.5 m,
+    l_max = 4) with 1,000-point scans as in the paper's experiments (Sec. IV).
+    The GPU runs every query seed; each CPU configuration (the oracle) runs as
+    many seeds as fit in --table1-cpu-seconds and reports how many it ran."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_2310_10023_amd as bbs
+    import synth
+    scene = synth.room_scene(0)
+    lo, hi = synth.search_range_room()
+    k = args.table1_k
+    T = synth.threshold_95(k)
+    n = args.table1_queries
+    scans = [synth.room_query(scene, s, k) for s in range(n)]
+    gmap = bbs.Map(torch.from_numpy(scene.points).cuda(), 0.5, 4)
+    omap = oracle.Map(scene.points, 0.5, 4)
+    dev = [torch.from_numpy(sc.points).cuda() for sc in scans]
+    ws = bbs.Workspace()
+    configs = [("c", "gpu", True, "depth_first"), ("f", "gpu", True, "best_first"), ("i", "gpu", False, "best_first"),
+               ("a", "cpu1", True, "depth_first"), ("b", "cpu4", True, "depth_first"),
+               ("d", "cpu1", True, "best_first"), ("e", "cpu4", True, "best_first"),
+               ("g", "cpu1", False, "best_first"), ("h", "cpu4", False, "best_first")]
+    rows = {}
+    gpu_res = {}
+    for name, kind, trans, strat in configs:
+        ms, res = [], []
+        if kind == "gpu":
+            bbs.localize(gmap, dev[0], lo, hi, T, workspace=ws, translation_only=trans, strategy=strat)
+            for d in dev:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                res.append(bbs.localize(gmap, d, lo, hi, T, workspace=ws, translation_only=trans, strategy=strat))
+                torch.cuda.synchronize()
+                ms.append((time.perf_counter() - t0) * 1e3)
+            gpu_res[(trans, strat)] = res
+        else:
+            threads = 1 if kind == "cpu1" else 4
+            t_end = time.perf_counter() + args.table1_cpu_seconds
+
+            def run():
+                for sc in scans:
+                    if time.perf_counter() > t_end:
+                        break
+                    t0 = time.perf_counter()
+                    s = oracle.Search(omap, sc.points, lo, hi, translation_only=trans)
+                    res.append(s.localize(T, batch=10000, threads=threads, strategy=strat))
+                    ms.append((time.perf_counter() - t0) * 1e3)
+            if threads == 1:
+                with_one_core(run)
+            else:
+                run()
+        ok = sum(success(r, sc.pose) for r, sc in zip(res, scans))
+        same = None
+        if kind != "gpu" and (trans, strat) in gpu_res:
+            keys = ("found", "score", "leaf", "nodes_expanded", "nodes_scored")
+            same = f"{sum(all(a[x] == b[x] for x in keys) for a, b in zip(res, gpu_res[(trans, strat)]))}/{len(res)}"
+        rows[name] = {"processing": {"cpu1": "CPU single-thread (1 pinned core)", "cpu4": "CPU multi-thread (4 threads)",
+                                     "gpu": "GPU"}[kind],
+                      "branching": "trans." if trans else "trans. and rot.",
+                      "strategy": "DFS" if strat == "depth_first" else "BFS",
+                      "queries": len(res), "ms_mean": float(np.mean(ms)) if ms else None,
+                      "ms_p50": pct(ms, 0.5), "success_2m_0p05rad": f"{ok}/{len(res)}",
+                      "nodes_scored_mean": float(np.mean([r["nodes_scored"] for r in res])) if res else None,
+                      "equal_to_gpu_row": same}
+        print(f"[bench] table1 ({name}): {rows[name]}", file=sys.stderr, flush=True)
+    line = {
+        "metric": METRIC + " (Table I configurations)",
+        "value": rows["i"]["ms_mean"],
+        "unit": "ms per localization (configuration (i))",
+        "n_gpus": 1,
+        "steps": n,
+        "warmup": 1,
+        "ms_per_step": rows["i"]["ms_mean"],
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded room and ray-cast scans)",
+        "config": {"workload": f"room 20x20x5 m seed 0, r=0.5 m, l_max=4, {k}-pt scans (query seeds 0..{n - 1}), "
+                               f"threshold {T}, b=10000", "table1": {c: rows[c] for c in "abcdefghi"}},
     }
     print(json.dumps(line), flush=True)
 

@@ -79,8 +79,17 @@ typedef struct {
                                  points each wave handles; 0 = default (2048) */
     int32_t graph;            /* 1: capture 8 search iterations in a hipGraph once per search
                                  and replay it (ignored with persistent or profile) */
-    int32_t reserved1;
-    int64_t reserved[1];
+    int32_t hist_min_level;   /* l >= 1: the pending groups are grouped into runs of one level
+                                 and rotation, and runs at level l or above are scored through
+                                 the scan's histogram of voxels at that level and rotation
+                                 (one lookup per distinct voxel instead of one per point; same
+                                 scores); -1: from level 0; 0 (default): off, every group is
+                                 scored point by point */
+    int32_t strategy;         /* queue order: 0 best first (Alg. 2: score descending, then level
+                                 ascending); 1 depth first (the order of Alg. 1, Table I
+                                 "DFS": level ascending, then score descending); first in
+                                 first out among equal keys, same batching and pruning */
+    int32_t reserved2;
 } bbs_options;
 
 typedef struct {
@@ -109,6 +118,13 @@ typedef struct {
     double serial_ms[4];      /* device time of the serial queue work, summed over iterations
                                  (100 MHz device clock): push, gather, and of push the
                                  bucket prefix over tiles and the chunk allocation */
+    int64_t level_groups[BBS_MAX_LEVELS]; /* groups of translational siblings scored per level,
+                                 children batches only (0 when every group is scored point
+                                 by point, see hist_min_level) */
+    int64_t hist_groups;      /* of those, groups scored through a scan histogram */
+    int64_t hist_items;       /* histogram work items */
+    int32_t hist_fallbacks;   /* histogram items whose scan had too many distinct voxels */
+    int32_t hist_off;         /* bit l: level l was switched to point-by-point scoring */
 } bbs_result;
 
 /* Fill *opt with the defaults (b = 10000, roto-translational, no profiling,

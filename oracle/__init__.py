@@ -100,7 +100,7 @@ def lib():
         L.orc_score.restype = I32
         L.orc_score_nodes.argtypes = [P, P, I64, C.POINTER(Grid), P, I64, P, I32]
         L.orc_localize.argtypes = [P, P, I64, C.POINTER(Grid), I32, I64, I32, I64, C.POINTER(Result), P, I64, P, I32,
-                                   P, I64]
+                                   P, I64, I32]
         L.orc_localize.restype = C.c_int
         L.orc_bruteforce.argtypes = [P, P, I64, C.POINTER(Grid), I32, I32, C.POINTER(Result)]
         L.orc_bruteforce.restype = C.c_int
@@ -239,9 +239,14 @@ class Search:
 
     EVENT_KINDS = ("prune", "leaf", "branch", "flush")
 
+    STRATEGIES = {"best_first": 0, "depth_first": 1}
+
     def localize(self, threshold: int, batch: int = 10000, threads: int = 1, max_scored: int = 0,
-                 trace_cap: int = 0, prior=None, seed_beam: int = 0, events_cap: int = 0) -> dict:
-        """Alg. 2.  prior: optional 1088 float logits (64 yaw bins, then 32 x 32
+                 trace_cap: int = 0, prior=None, seed_beam: int = 0, events_cap: int = 0,
+                 strategy: str = "best_first") -> dict:
+        """Alg. 2 (strategy "best_first"), or the same batched search in the
+        queue order of Alg. 1 (strategy "depth_first": deeper levels first,
+        then higher score).  prior: optional 1088 float logits (64 yaw bins, then 32 x 32
         translation cells) that order the initial set; a seed beam of width
         `seed_beam` ranked by (score, prior key) may seed the incumbent.
         trace_cap > 0 adds the flush sizes; events_cap > 0 adds the search
@@ -256,7 +261,8 @@ class Search:
                                 int(batch), int(threads), int(max_scored), C.byref(res),
                                 tr.ctypes.data if trace_cap else None, int(trace_cap),
                                 pr.ctypes.data if pr is not None else None, int(seed_beam),
-                                ev.ctypes.data if events_cap else None, int(events_cap))
+                                ev.ctypes.data if events_cap else None, int(events_cap),
+                                self.STRATEGIES[strategy])
         if rc != 0:
             raise OracleError(f"orc_localize failed ({rc})")
         d = res.as_dict()

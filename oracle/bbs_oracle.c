@@ -399,39 +399,45 @@ static int vec_push(node_vec *q, const orc_node *x)
 }
 
 /*
- * Queue order.  The paper sorts C in descending order of score (Sec. III-D,
- * Alg. 2).  Reading for ties: lower level first (the depth preference of
- * Alg. 1), then first-in first-out.
+ * Queue order.  Best-first search (Sec. III-D, Alg. 2) sorts C in descending
+ * order of score; reading for ties: lower level first (the depth preference
+ * of Alg. 1), then first-in first-out.  Depth-first search (Alg. 1, the
+ * conventional BBS) keeps the queue sorted by depth level with the maximum
+ * score popped first; reading: lower level first, then higher score, then
+ * first-in first-out.
  */
-static int before(const orc_node *a, const orc_node *b)
+enum { ORC_BEST_FIRST = 0, ORC_DEPTH_FIRST = 1 };
+
+static int before(const orc_node *a, const orc_node *b, int order)
 {
+    if (order == ORC_DEPTH_FIRST && a->level != b->level) return a->level < b->level;
     if (a->score != b->score) return a->score > b->score;
     if (a->level != b->level) return a->level < b->level;
     return a->seq < b->seq;
 }
 
-static int heap_push(node_vec *h, const orc_node *x)
+static int heap_push(node_vec *h, const orc_node *x, int order)
 {
     if (vec_push(h, x)) return ORC_ERR_OOM;
     int64_t i = h->n - 1;
     while (i > 0) {
         int64_t p = (i - 1) / 2;
-        if (!before(&h->v[i], &h->v[p])) break;
+        if (!before(&h->v[i], &h->v[p], order)) break;
         orc_node t = h->v[i]; h->v[i] = h->v[p]; h->v[p] = t;
         i = p;
     }
     return ORC_OK;
 }
 
-static orc_node heap_pop(node_vec *h)
+static orc_node heap_pop(node_vec *h, int order)
 {
     orc_node top = h->v[0];
     h->v[0] = h->v[--h->n];
     int64_t i = 0;
     for (;;) {
         int64_t l = 2 * i + 1, r = l + 1, m = i;
-        if (l < h->n && before(&h->v[l], &h->v[m])) m = l;
-        if (r < h->n && before(&h->v[r], &h->v[m])) m = r;
+        if (l < h->n && before(&h->v[l], &h->v[m], order)) m = l;
+        if (r < h->n && before(&h->v[r], &h->v[m], order)) m = r;
         if (m == i) break;
         orc_node t = h->v[i]; h->v[i] = h->v[m]; h->v[m] = t;
         i = m;
@@ -708,6 +714,10 @@ out:
  * With a finite prior (not in the paper) the initial set is scored and queued
  * in descending prior key (ties in enumeration order), and a seed beam of
  * width beam_width may set the incumbent before the loop starts.
+ * order selects the search strategy: ORC_BEST_FIRST (Alg. 2, the paper's
+ * proposal) or ORC_DEPTH_FIRST (the queue order of Alg. 1, Table I
+ * configurations (a)-(c)); both use the batching, pruning and leaf rules
+ * above, so that they differ in the pop order only.
  */
 /* Event log of the search loop (tests only): 9 int32 per event, kind then the
  * node (level, x, y, z, roll, pitch, yaw) and its score.  Kinds: a popped node
@@ -733,10 +743,11 @@ static void log_event(int32_t *ev, int64_t cap, orc_result *res, int kind, const
 int orc_localize(const orc_map *m, const float *scan, int64_t k, const orc_grid *g, int32_t threshold,
                  int64_t batch, int32_t threads, int64_t max_scored, orc_result *res,
                  int64_t *trace_flush, int64_t trace_cap, const float *prior, int32_t beam_width,
-                 int32_t *events, int64_t events_cap)
+                 int32_t *events, int64_t events_cap, int32_t order)
 {
     memset(res, 0, sizeof(*res));
     if (!m || !scan || k < 1 || batch < 1 || g->levels != m->levels) return ORC_ERR_ARG;
+    if (order != ORC_BEST_FIRST && order != ORC_DEPTH_FIRST) return ORC_ERR_ARG;
     const int L = g->levels;
     node_vec heap = {0}, pending = {0};
     int64_t seq = 0;
@@ -795,7 +806,7 @@ int orc_localize(const orc_map *m, const float *scan, int64_t k, const orc_grid 
     for (int64_t i = 0; i < pending.n; ++i) {
         if (pending.v[i].score < threshold) continue;
         pending.v[i].seq = seq++;
-        if ((rc = heap_push(&heap, &pending.v[i]))) goto done;
+        if ((rc = heap_push(&heap, &pending.v[i], order))) goto done;
         res->initial_kept++;
     }
     if (res->prior_used && beam_width > 0) {
@@ -820,7 +831,7 @@ int orc_localize(const orc_map *m, const float *scan, int64_t k, const orc_grid 
             if (pending.n == 0) break;
             flush = 1;                                     /* termination flush */
         } else {
-            orc_node c = heap_pop(&heap);
+            orc_node c = heap_pop(&heap, order);
             if (c.score < best) {                          /* pruned */
                 log_event(events, events_cap, res, ORC_EV_PRUNE, &c, c.score);
                 continue;
@@ -853,7 +864,7 @@ int orc_localize(const orc_map *m, const float *scan, int64_t k, const orc_grid 
                         (double)(ch->score - ch->parent_score) / (double)(ch->parent_score > 0 ? ch->parent_score : 1);
                 }
                 ch->seq = seq++;
-                if ((rc = heap_push(&heap, ch))) goto done;
+                if ((rc = heap_push(&heap, ch, order))) goto done;
             }
             pending.n = 0;
         }

@@ -29,6 +29,7 @@ EXPORTED_SYMBOLS = (
     "bbs_bandwidth_probe",
 )
 
+STRATEGIES = {"best_first": 0, "depth_first": 1}
 STATUS = {0: "OK", -1: "INVALID_ARG", -2: "OOM", -3: "DEVICE", -4: "QUEUE_OVERFLOW", -5: "INTERNAL"}
 
 
@@ -50,7 +51,7 @@ class Options(C.Structure):
     _fields_ = [("batch_size", C.c_int32), ("translation_only", C.c_int32), ("profile", C.c_int32),
                 ("seed_beam", C.c_int32), ("stream", C.c_void_p), ("prior", C.c_void_p),
                 ("persistent", C.c_int32), ("score_items", C.c_int32), ("graph", C.c_int32),
-                ("reserved1", C.c_int32), ("reserved", C.c_int64 * 1)]
+                ("hist_min_level", C.c_int32), ("strategy", C.c_int32), ("reserved2", C.c_int32)]
 
 
 class Result(C.Structure):
@@ -60,7 +61,9 @@ class Result(C.Structure):
                 ("score_kernel_ms", C.c_double), ("score_launches", C.c_int64), ("score_pairs", C.c_int64),
                 ("score_groups", C.c_int64), ("phase_ms", C.c_double * 4), ("prior_used", C.c_int32),
                 ("seeded", C.c_int32), ("seed_score", C.c_int32), ("persistent_used", C.c_int32),
-                ("seed_beam_used", C.c_int32), ("reserved_r", C.c_int32), ("serial_ms", C.c_double * 4)]
+                ("seed_beam_used", C.c_int32), ("reserved_r", C.c_int32), ("serial_ms", C.c_double * 4),
+                ("level_groups", C.c_int64 * MAX_LEVELS), ("hist_groups", C.c_int64), ("hist_items", C.c_int64),
+                ("hist_fallbacks", C.c_int32), ("hist_off", C.c_int32)]
 
     def as_dict(self):
         return {"found": self.found, "score": self.score, "leaf": list(self.leaf), "pose": list(self.pose),
@@ -71,7 +74,9 @@ class Result(C.Structure):
                 "score_groups": self.score_groups,
                 "phase_ms": list(self.phase_ms), "prior_used": self.prior_used, "seeded": self.seeded,
                 "seed_score": self.seed_score, "persistent_used": self.persistent_used,
-                "seed_beam_used": self.seed_beam_used, "serial_ms": list(self.serial_ms)}
+                "seed_beam_used": self.seed_beam_used, "serial_ms": list(self.serial_ms),
+                "level_groups": list(self.level_groups), "hist_groups": self.hist_groups,
+                "hist_items": self.hist_items, "hist_fallbacks": self.hist_fallbacks, "hist_off": self.hist_off}
 
 
 class TuneEntry(C.Structure):
@@ -268,7 +273,8 @@ class Workspace:
 def localize(bmap: Map, scan, rmin, rmax, score_threshold: int, *, batch_size: int = 10000,
              translation_only: bool = False, profile: int = 0, workspace: Workspace | None = None,
              stream=None, prior=None, seed_beam: int = 0, persistent: bool = False,
-             score_items: int = 0, graph: bool = False) -> dict:
+             score_items: int = 0, graph: bool = False, hist_min_level: int = 0,
+             strategy: str = "best_first") -> dict:
     """Global localization of one scan (Alg. 2 on the GPU).  Returns the result
     fields as a dict (found, score, leaf, pose, node counters, timings).
     prior: optional 1088 logits of the proposal network."""
@@ -282,6 +288,8 @@ def localize(bmap: Map, scan, rmin, rmax, score_threshold: int, *, batch_size: i
     opt.persistent = int(persistent)
     opt.score_items = int(score_items)
     opt.graph = int(graph)
+    opt.hist_min_level = int(hist_min_level)
+    opt.strategy = STRATEGIES[strategy]
     pr = None
     if prior is not None:
         pr = np.ascontiguousarray(prior, dtype=np.float32).reshape(1088)
@@ -392,6 +400,7 @@ def serve(bmap: Map, scans, ranges, thresholds, arrivals, *, workers: int = 4, b
                            t_end.ctypes.data))
     del keep
     return [res[i].as_dict() for i in range(n)], t_start[:n], t_end[:n]
+
 
 def bandwidth_probe(kind: str, table_bytes: int, loads: int = 1 << 26) -> dict:
     """Achievable memory rate of the GPU: kind "stream" (coalesced read of the

@@ -148,6 +148,11 @@ struct SearchConst {
     float inv_r;
     int32_t r_pow2;                // r is a power of two: p / r == p * (1 / r) exactly
     int32_t score_items;           // scoring work items to aim for (groups x point splits)
+    int32_t dedup_levels;          // bit l: runs of level-l groups are scored through the scan's
+                                   // histogram of level-l voxels (packed keys fit, counts fit 16 bits)
+    int32_t depth_first;           // queue order: 0 score desc then level asc (Alg. 2); 1 level asc
+                                   // then score desc (the depth-first order of Alg. 1)
+    int32_t n_scores;              // K - threshold + 1: scores a queued node can have
 };
 
 // Error reporting (thread-local message).

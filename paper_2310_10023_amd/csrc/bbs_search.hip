@@ -68,6 +68,19 @@ struct State {
     int32_t seeded, seed_score;
     int64_t t_push, t_gather; // device real-time ticks (100 MHz) spent in the serial push and gather
     int64_t t_push_prefix, t_push_alloc;   // of t_push: bucket prefix over tiles, chunk allocation
+    // the pending batch as scoring items (written by the gather): runs of
+    // groups that share a level and rotation (`rgroups`), cut into n_items
+    // item descriptors (`items`): histogram items, pairs of groups, or point
+    // slices (n_slices per group) of groups scored point by point
+    int32_t runs;             // 1: the fields below describe the batch; 0: groups in index order, all direct
+    int32_t n_items;
+    int32_t n_slices;
+    int32_t pad2;
+    int64_t dedup_groups;     // groups scored through a histogram, since the start
+    int64_t dedup_items;      // histogram items, since the start
+    int32_t hist_off;         // bit l: a level-l scan histogram overflowed; later level-l runs go point by point
+    int32_t hist_fallbacks;   // histogram items that overflowed and were scored point by point
+    int64_t level_groups[kMaxLevels];   // groups scored per level (children batches, since the start)
 };
 
 // ---- learned prior: seed beam (not in the paper)
@@ -405,9 +418,23 @@ __device__ inline uint32_t mad24(uint32_t a, uint32_t b, uint32_t c)
     return d;
 }
 
+// Queue bucket of a (score, level): buckets are popped in index order, so
+// the best-first order (Alg. 2; ties: lower level first) is score-major and
+// the depth-first order (Alg. 1: deeper level first, then higher score) is
+// level-major.  Scores below the threshold are never queued.
 __device__ inline int bucket_of(int score, int level, const SearchConst &C)
 {
-    return (C.K - score) * (C.levels + 1) + level;
+    return C.depth_first ? level * C.n_scores + (C.K - score) : (C.K - score) * (C.levels + 1) + level;
+}
+
+__device__ inline int bucket_score(int q, const SearchConst &C)
+{
+    return C.depth_first ? C.K - q % C.n_scores : C.K - q / (C.levels + 1);
+}
+
+__device__ inline int bucket_level(int q, const SearchConst &C)
+{
+    return C.depth_first ? q / C.n_scores : q % (C.levels + 1);
 }
 
 // One tile of 32 groups (256 node slots) of a scored batch: the queue bucket
@@ -477,6 +504,33 @@ __device__ void tile_pass(int t, const uint4 *groups, int32_t *scores, State *st
     }
 }
 
+// Histogram of the scan's level-l voxels under one rotation (LDS open
+// addressing on the packed voxel, linear probing), then the same table
+// compacted in place to its D distinct voxels with their point counts.
+constexpr int kHistSlots = 2048;
+constexpr int kHistMax = 1536;                   // distinct voxels beyond this: the item scores point by point
+constexpr uint32_t kHistEmpty = 0xFFFFFFFFu;
+constexpr int kHistBias = 512;                   // packed voxel: 10 bits per axis, v + 512
+constexpr int kItemGroups = 64;                  // groups of one run per histogram item
+
+// Item descriptor (int4): x = first entry of rgroups, y = groups, z = kind,
+// w = point slice (kind 2).
+constexpr int kItemHist = 0;                     // one run's groups through the scan histogram
+constexpr int kItemPair = 1;                     // one or two groups, point by point
+constexpr int kItemSlice = 2;                    // a point slice of one group
+
+struct HistSmem {
+    uint32_t key[kHistSlots];
+    uint32_t cnt[kHistSlots / 2];                // two 16-bit counts per word (slot s: half s & 1)
+    uint32_t ckey[kHistMax];                     // the distinct voxels, compacted
+    uint16_t ccnt[kHistMax];                     // and their point counts
+    int n_distinct;
+    int full;                                    // more than kHistMax distinct voxels (or a long probe)
+    int n_compact;
+    int n_tiles;
+    int tiles[kItemGroups];                      // tiles this item completed
+};
+
 template <int NT>
 struct ScoreSmem {
     int red[NT / 64][16];
@@ -484,6 +538,12 @@ struct ScoreSmem {
     int sm[NT / 64];
     int s_last;
     int s_next;
+};
+
+// The same, with the histogram of the scoring through runs.
+template <int NT>
+struct ScoreSmemRuns : ScoreSmem<NT> {
+    HistSmem h;
 };
 
 struct ScoreArgs {
@@ -499,6 +559,9 @@ struct ScoreArgs {
     uint32_t *qmask;           // bit q: some tile of the batch holds a child of bucket q
     int32_t *ticket;           // NULL: items round-robin; else [0] next item ticket, [1] workgroups
                                // done (both 0 between launches)
+    const int32_t *rgroups;    // the batch's groups by run (with st->runs)
+    const int4 *items;         // item descriptors (with st->runs)
+    int32_t *gslices;          // per group: point slices done (0 between launches)
 };
 
 // A rotated coordinate in level-0 cells, as p / r: RM 0 divides (correctly
@@ -714,6 +777,441 @@ __device__ inline void hash_loop(const float *__restrict__ X, const float *__res
     }
 }
 
+// The eight member counts of a looked-up window, each weighted by c (the
+// points of one histogram voxel): member j = 4 jx + 2 jy + jz sits at window
+// bit 25 jz + 5 jy + jx.
+__device__ inline void add_window(uint32_t win, uint32_t c, uint32_t (&acc)[8])
+{
+    acc[0] = mad24(__builtin_amdgcn_ubfe(win, 0u, 1u), c, acc[0]);
+    acc[1] = mad24(__builtin_amdgcn_ubfe(win, 25u, 1u), c, acc[1]);
+    acc[2] = mad24(__builtin_amdgcn_ubfe(win, 5u, 1u), c, acc[2]);
+    acc[3] = mad24(__builtin_amdgcn_ubfe(win, 30u, 1u), c, acc[3]);
+    acc[4] = mad24(__builtin_amdgcn_ubfe(win, 1u, 1u), c, acc[4]);
+    acc[5] = mad24(__builtin_amdgcn_ubfe(win, 26u, 1u), c, acc[5]);
+    acc[6] = mad24(__builtin_amdgcn_ubfe(win, 6u, 1u), c, acc[6]);
+    acc[7] = mad24(__builtin_amdgcn_ubfe(win, 31u, 1u), c, acc[7]);
+}
+
+// 32-bit window of the eight siblings of voxel (x, y, z) (level-l voxel
+// coordinates of the group base plus the point's voxel) in a level held only
+// as a hash table: 0 when the brick is absent.
+__device__ inline uint32_t hash_window(const LevelView &lv, int32_t wx, int32_t wy, int32_t wz)
+{
+    const int32_t Bx = wx >> 2, By = wy >> 2, Bz = wz >> 2;
+    if ((uint32_t)(Bx - lv.bmin[0]) > (uint32_t)(lv.bmax[0] - lv.bmin[0]) ||
+        (uint32_t)(By - lv.bmin[1]) > (uint32_t)(lv.bmax[1] - lv.bmin[1]) ||
+        (uint32_t)(Bz - lv.bmin[2]) > (uint32_t)(lv.bmax[2] - lv.bmin[2]))
+        return 0u;
+    const uint32_t klo = brick_key_lo(Bx, By, Bz), khi = brick_key_hi(Bx, By, Bz);
+    uint32_t h = brick_hash(Bx, By, Bz) & lv.cap_mask;
+    for (;;) {
+        const uint2 kk = lv.keys[h];
+        if (kk.x == klo && kk.y == khi) break;
+        if (kk.x == kEmptyLo && kk.y == kEmptyHi) return 0u;
+        h = (h + 1) & lv.cap_mask;
+    }
+    const uint4 bits = lv.bits[h];
+    const int i0 = ((wz & 3) * 5 + (wy & 3)) * 5 + (wx & 3);
+    const int word = i0 >> 5;
+    const uint32_t lo = word == 0 ? bits.x : (word == 1 ? bits.y : bits.z);
+    const uint32_t hi = word == 0 ? bits.y : (word == 1 ? bits.z : bits.w);
+    return __builtin_amdgcn_alignbit(hi, lo, (uint32_t)(i0 & 31));
+}
+
+// A histogram item: up to kItemGroups groups of one run (one level l, one
+// rotation R).  Every scan point's level-l voxel v = floor(floor(R s / r) /
+// 2^l) goes into an LDS histogram; a group with base b then scores, for each
+// member j, the sum over distinct voxels v of count(v) [v + b + j in D_l]
+// (Eq. (12) with the points of one voxel taken together: the voxel of a
+// point, and hence every lookup, depends on the point only through v).
+// Returns false, having scored nothing, if the scan has more than kHistMax
+// distinct voxels at this level and rotation.
+template <int RM, int NT>
+__device__ bool hist_item(State *st, const int4 desc, const ScoreArgs &A, const MapView &map, const SearchConst &C,
+                          ScoreSmemRuns<NT> &sh, int32_t *__restrict__ scores)
+{
+    HistSmem &H = sh.h;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int first = desc.x, m = desc.y;
+    const uint4 Gv = A.groups[A.rgroups[first]];
+    const uint32_t gy = __builtin_amdgcn_readfirstlane(Gv.y), gz = __builtin_amdgcn_readfirstlane(Gv.z);
+    const int level = (int)(__builtin_amdgcn_readfirstlane(Gv.w) & 0xFF);
+    float R[9];
+    rotation(A.trig, C, level, hi16u(gy), lo16u(gz), hi16u(gz), R);
+    for (int i = tid; i < kHistSlots; i += NT) H.key[i] = kHistEmpty;
+    for (int i = tid; i < kHistSlots / 2; i += NT) H.cnt[i] = 0u;
+    if (tid == 0) {
+        H.n_distinct = 0;
+        H.full = 0;
+        H.n_compact = 0;
+    }
+    __syncthreads();
+    // 1. histogram of the points' level-l voxels
+    const float *__restrict__ X = A.X;
+    const float *__restrict__ Y = A.Y;
+    const float *__restrict__ Z = A.Z;
+    const int K = C.K;
+    volatile int *full = &H.full;
+    // wave-uniform trip count (the lane shuffle and ballot below need every
+    // lane); points past K get the empty key
+    for (int kb = tid; __builtin_amdgcn_readfirstlane(kb) < K && !__builtin_amdgcn_readfirstlane(*full);
+         kb += NT * 4) {
+        uint32_t key[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int k = kb + u * NT;
+            key[u] = kHistEmpty;
+            if (k < K) {
+                const float sx = X[k], sy = Y[k], sz = Z[k];
+                uint32_t packed = 0;
+#pragma unroll
+                for (int row = 0; row < 3; ++row) {
+                    float t0 = R[3 * row + 0] * sx;
+                    float t1 = R[3 * row + 1] * sy;
+                    float t2 = R[3 * row + 2] * sz;
+                    float p = (t0 + t1) + t2;
+                    float q = scale_to_cells<RM>(p, C);
+                    int32_t fl;
+                    asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(fl) : "v"(q));
+                    packed |= (uint32_t)((fl >> level) + kHistBias) << (10 * row);
+                }
+                key[u] = packed;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            // the lanes of a wave hold consecutive scan points, which the
+            // spatial sort keeps close together: a run of lanes with the same
+            // voxel is inserted once, by its first lane, with the run's length
+            const uint32_t prev = __shfl_up(key[u], 1);
+            const bool head = lane == 0 || key[u] != prev;
+            const uint64_t heads = __ballot(head);
+            const uint64_t after = lane == 63 ? 0ull : heads >> (lane + 1);
+            const uint32_t run = after ? (uint32_t)__ffsll((long long)after) : (uint32_t)(64 - lane);
+            if (!head || key[u] == kHistEmpty) continue;
+            uint32_t h = (key[u] * 0x9E3779B1u) >> 21;
+            bool placed = false;
+            for (int probe = 0; probe < 32; ++probe) {
+                const uint32_t old = atomicCAS(&H.key[h], kHistEmpty, key[u]);
+                if (old == kHistEmpty) {
+                    if (atomicAdd(&H.n_distinct, 1) >= kHistMax) *full = 1;
+                    placed = true;
+                    break;
+                }
+                if (old == key[u]) {
+                    placed = true;
+                    break;
+                }
+                h = (h + 1) & (kHistSlots - 1);
+            }
+            if (!placed) *full = 1;
+            else atomicAdd(&H.cnt[h >> 1], run << ((h & 1) << 4));
+        }
+    }
+    __syncthreads();
+    if (H.full) {
+        // too many distinct voxels at this level: later runs of the level go point by point
+        if (tid == 0) {
+            atomicOr(&st->hist_off, 1 << level);
+            atomicAdd(&st->hist_fallbacks, 1);
+        }
+        return false;
+    }
+    // 2. compact: each wave appends its non-empty slots (order is free: the
+    // scores are sums over the voxels)
+    for (int sl = tid; sl < kHistSlots; sl += NT) {
+        const uint32_t k = H.key[sl];
+        const bool live = k != kHistEmpty;
+        const uint64_t bal = __ballot(live);
+        int base = 0;
+        if (lane == 0 && bal) base = atomicAdd(&H.n_compact, (int)__popcll(bal));
+        base = __builtin_amdgcn_readfirstlane(base);
+        if (live) {
+            const int p = base + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+            H.ckey[p] = k;
+            H.ccnt[p] = (uint16_t)((H.cnt[sl >> 1] >> ((sl & 1) << 4)) & 0xFFFFu);
+        }
+    }
+    __syncthreads();
+    const int D = H.n_compact;
+    // 3. every group of the item against the D voxels, one group per wave at a time
+    const LevelView &lv = map.lv[level];
+    const bool dense = lv.dense != nullptr;
+    const uint32_t nx = (uint32_t)lv.nx, ny = (uint32_t)lv.ny;
+    const uint32_t lim0 = (uint32_t)(lv.bmax[0] - lv.bmin[0]) + 1u, lim1 = (uint32_t)(lv.bmax[1] - lv.bmin[1]) + 1u;
+    const uint32_t lim2 = 4u * ((uint32_t)(lv.bmax[2] - lv.bmin[2]) + 1u);
+    for (int gi = wave; gi < m; gi += NT / 64) {
+        const int g = __builtin_amdgcn_readfirstlane(A.rgroups[first + gi]);
+        const uint4 G = A.groups[g];
+        const int32_t bx = lo16s(__builtin_amdgcn_readfirstlane(G.x)), by = hi16s(__builtin_amdgcn_readfirstlane(G.x));
+        const int32_t bz = lo16s(__builtin_amdgcn_readfirstlane(G.y));
+        uint32_t acc[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
+        if (dense) {
+            // level-l voxel relative to 4 x the box minimum, with the key's bias taken off
+            const int32_t ox = bx - 4 * lv.bmin[0] - kHistBias, oy = by - 4 * lv.bmin[1] - kHistBias;
+            const int32_t oz = bz - 4 * lv.bmin[2] - kHistBias;
+            for (int d = lane; d < D; d += 64) {
+                const uint32_t key = H.ckey[d];
+                const uint32_t c = H.ccnt[d];
+                const int32_t ux = (int32_t)(key & 1023u) + ox;
+                const int32_t uy = (int32_t)((key >> 10) & 1023u) + oy;
+                const int32_t uz = (int32_t)(key >> 20) + oz;
+                const uint32_t rx = min((uint32_t)(ux >> 2), lim0), ry = min((uint32_t)(uy >> 2), lim1);
+                const uint32_t rz = min((uint32_t)uz, lim2);
+                const uint2 col = lv.dense[mad24(mad24(rz, ny, ry), nx, rx)];
+                const uint32_t i0 = ((uint32_t)uy & 3u) * 5u + ((uint32_t)ux & 3u);
+                add_window(__builtin_amdgcn_alignbit(col.y, col.x, i0), c, acc);
+            }
+        } else {
+            for (int d = lane; d < D; d += 64) {
+                const uint32_t key = H.ckey[d];
+                const uint32_t c = H.ccnt[d];
+                const int32_t wx = (int32_t)(key & 1023u) - kHistBias + bx;
+                const int32_t wy = (int32_t)((key >> 10) & 1023u) - kHistBias + by;
+                const int32_t wz = (int32_t)(key >> 20) - kHistBias + bz;
+                add_window(hash_window(lv, wx, wy, wz), c, acc);
+            }
+        }
+        int sum[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) sum[j] = wave_sum((int)acc[j]);
+        // hand-off to the tile pass: returning atomics (see score_items)
+        if (lane < 8) {
+            int v = sum[0];
+#pragma unroll
+            for (int j = 1; j < 8; ++j) v = lane == j ? sum[j] : v;
+            const int old = __hip_atomic_exchange(&scores[8 * (int64_t)g + lane], v, __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
+            asm volatile("" ::"v"(old));
+        }
+    }
+    return true;
+}
+
+// Point-by-point scoring of the points [k_begin, k_end) of one or two groups
+// (dense grid or hash table per group); cnt receives their member counts.
+template <int RM, int NT>
+__device__ void direct_groups(const ScoreArgs &A, const MapView &map, const SearchConst &C, const int gs[2], int ng,
+                              int k_begin, int k_end, int (&cnt)[2][8])
+{
+    const float *__restrict__ X = A.X;
+    const float *__restrict__ Y = A.Y;
+    const float *__restrict__ Z = A.Z;
+    // the groups are the same for every lane of the item: scalar registers
+    DenseGroup dg[2];
+    int lvl[2], base[2][3];
+    bool dense[2];
+    float R[2][9];
+#pragma unroll
+    for (int gi = 0; gi < 2; ++gi) {
+        const uint4 Gv = A.groups[gs[gi]];
+        const uint4 G = make_uint4(__builtin_amdgcn_readfirstlane(Gv.x), __builtin_amdgcn_readfirstlane(Gv.y),
+                                   __builtin_amdgcn_readfirstlane(Gv.z), __builtin_amdgcn_readfirstlane(Gv.w));
+        const int level = (int)(G.w & 0xFF);
+        lvl[gi] = level;
+        base[gi][0] = lo16s(G.x);
+        base[gi][1] = hi16s(G.x);
+        base[gi][2] = lo16s(G.y);
+        rotation(A.trig, C, level, hi16u(G.y), lo16u(G.z), hi16u(G.z), R[gi]);
+        const LevelView &lv = map.lv[level];
+        dense[gi] = lv.dense != nullptr;
+#pragma unroll
+        for (int e = 0; e < 9; ++e) dg[gi].R[e] = R[gi][e];
+        dg[gi].dense = lv.dense;
+        dg[gi].nx = (uint32_t)lv.nx;
+        dg[gi].ny = (uint32_t)lv.ny;
+        dg[gi].lim[0] = (uint32_t)(lv.bmax[0] - lv.bmin[0]) + 1u;
+        dg[gi].lim[1] = (uint32_t)(lv.bmax[1] - lv.bmin[1]) + 1u;
+        dg[gi].lim[2] = 4u * ((uint32_t)(lv.bmax[2] - lv.bmin[2]) + 1u);
+        const int32_t scale = 1 << level;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) dg[gi].off[a] = (base[gi][a] - 4 * lv.bmin[a]) * scale;
+        dg[gi].level = (uint32_t)level;
+    }
+#pragma unroll
+    for (int gi = 0; gi < 2; ++gi)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) cnt[gi][j] = 0;
+    if (ng == 2 && dense[0] && dense[1]) {
+        dense_loop<RM, NT, 2, kUnroll / 2>(X, Y, Z, k_begin, k_end, C, dg, cnt);
+    } else {
+#pragma unroll
+        for (int gi = 0; gi < 2; ++gi) {
+            if (gi >= ng) break;
+            if (dense[gi]) {
+                const DenseGroup one[1] = {dg[gi]};
+                int c1[1][8] = {{0, 0, 0, 0, 0, 0, 0, 0}};
+                dense_loop<RM, NT, 1, kUnroll>(X, Y, Z, k_begin, k_end, C, one, c1);
+#pragma unroll
+                for (int j = 0; j < 8; ++j) cnt[gi][j] = c1[0][j];
+            } else {
+                hash_loop<RM, NT>(X, Y, Z, k_begin, k_end, C, map.lv[lvl[gi]], R[gi], base[gi][0], base[gi][1],
+                                  base[gi][2], lvl[gi], cnt[gi]);
+            }
+        }
+    }
+}
+
+// Scoring of a batch the gather cut into runs and item descriptors (with
+// the histogram option; see score_items for the point-by-point scheme).
+template <int RM, int NT>
+__device__ void score_items_runs(State *st, const ScoreArgs &A, const MapView &map, const SearchConst &C,
+                                 ScoreSmemRuns<NT> &sh)
+{
+    int32_t *__restrict__ scores = A.scores;
+    int32_t *tile_done = A.tile_done;
+    auto &red = sh.red;
+    const int n_groups = st ? (ld_agent(&st->batch) ? ld_agent(&st->n_groups) : 0) : A.n_groups_fixed;
+    if (n_groups <= 0) return;
+    // Work items.  A batch the gather wrote comes as item descriptors over
+    // its runs (groups sharing a level and rotation): histogram items, or
+    // groups scored point by point.  Point by point, groups are scored two to
+    // an item, so that a workgroup reads every scan point once for both and
+    // pays the per-item latency (groups, rotations, count reduction, atomics)
+    // once per pair; groups too few to fill the grid are split score_items /
+    // groups ways into point slices.  Items go round-robin over the
+    // workgroups (the grid is as large as the device holds at once), or, with
+    // a ticket counter, to whichever workgroup asks next.
+    const bool runs = st && ld_agent(&st->runs);
+    const int K = C.K;
+    constexpr int kStep = NT * kUnroll;                 // points of one round of the workgroup
+    const int max_s = (K + kStep - 1) / kStep;
+    const int P = (int)gridDim.x;
+    // without runs (initial set, seed beam, node lists): groups in index
+    // order, paired, or split into point slices when they are too few
+    const int s_min = min(max_s, max(1, (C.score_items + n_groups - 1) / n_groups));
+    const bool legacy_pairs = s_min == 1;
+    const int S = runs ? max(1, ld_agent(&st->n_slices)) : (legacy_pairs ? 1 : s_min);
+    const int64_t n_items = runs ? (int64_t)ld_agent(&st->n_items)
+                                 : (legacy_pairs ? (n_groups + 1) / 2 : (int64_t)n_groups * S);
+    int32_t *ticket = A.ticket;
+    int64_t item = blockIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    while (item < n_items) {
+        // the next item's ticket, drawn now so that its latency is hidden
+        // behind the item (one atomic counter for the whole grid: used by
+        // the persistent loop, whose grid is one workgroup per CU)
+        int nxt = 0;
+        if (ticket && threadIdx.x == 0) nxt = atomicAdd(&ticket[0], 1);
+        // the item: x = first entry, y = groups, z = kind, w = slice
+        int4 desc;
+        if (runs) {
+            const int4 dv = A.items[item];
+            desc = make_int4(__builtin_amdgcn_readfirstlane(dv.x), __builtin_amdgcn_readfirstlane(dv.y),
+                             __builtin_amdgcn_readfirstlane(dv.z), __builtin_amdgcn_readfirstlane(dv.w));
+        } else if (legacy_pairs) {
+            desc = make_int4(2 * (int)item, 2 * (int)item + 1 < n_groups ? 2 : 1, kItemPair, 0);
+        } else {
+            desc = make_int4((int)(item / S), 1, kItemSlice, (int)(item % S));
+        }
+        auto group_at = [&](int e) { return runs ? A.rgroups[e] : e; };
+        const bool sliced = desc.z == kItemSlice;
+        bool done = false;
+        if (desc.z == kItemHist) done = hist_item<RM, NT>(st, desc, A, map, C, sh, scores);
+        int gs[2] = {0, 0}, ng = 0;
+        if (!done) {
+            // point by point: a pair, a slice, or (rarely) a histogram item
+            // whose scan had too many distinct voxels, one group at a time
+            const int n_pass = desc.z == kItemHist ? desc.y : 1;
+            for (int pass = 0; pass < n_pass; ++pass) {
+                int k_begin = 0, k_end = K;
+                if (desc.z == kItemHist) {
+                    gs[0] = gs[1] = group_at(desc.x + pass);
+                    ng = 1;
+                } else if (desc.z == kItemPair) {
+                    ng = desc.y;
+                    gs[0] = group_at(desc.x);
+                    gs[1] = group_at(desc.x + ng - 1);
+                } else {
+                    gs[0] = gs[1] = group_at(desc.x);
+                    ng = 1;
+                    // slices are whole rounds, so only the last one is ragged; its tail
+                    // runs over the scan padding (points that fall outside every box)
+                    const int chunk = ((K + S - 1) / S + kStep - 1) / kStep * kStep;
+                    k_begin = min(K, desc.w * chunk);
+                    k_end = min(K, k_begin + chunk);
+                }
+                gs[0] = __builtin_amdgcn_readfirstlane(gs[0]);
+                gs[1] = __builtin_amdgcn_readfirstlane(gs[1]);
+                int cnt[2][8];
+                direct_groups<RM, NT>(A, map, C, gs, ng, k_begin, k_end, cnt);
+#pragma unroll
+                for (int gi = 0; gi < 2; ++gi) {
+                    if (gi < ng) {
+#pragma unroll
+                        for (int j = 0; j < 8; ++j) {
+                            const int v = wave_sum(cnt[gi][j]);
+                            if (lane == 0) red[wave][8 * gi + j] = v;
+                        }
+                    }
+                }
+                __syncthreads();
+                // Hand-off to the tile pass without a device-scope fence (which on this
+                // GPU writes back and invalidates the XCD's L2): the scores are written
+                // with returning atomics, which have been performed once the barrier's
+                // wait for outstanding memory operations is over; only then is the
+                // tile counter bumped, and the tile pass reads the scores with atomics
+                // too, at the same coherence point.  Whole groups store their counts;
+                // the slices of a group add theirs to scores zeroed by the batch's producer.
+                if (threadIdx.x < 8 * ng) {
+                    int sum = 0;
+                    for (int wv = 0; wv < NT / 64; ++wv) sum += red[wv][threadIdx.x];
+                    const int g = threadIdx.x >= 8 ? gs[1] : gs[0];
+                    int32_t *dst = &scores[8 * (int64_t)g + (threadIdx.x & 7)];
+                    const int old = !sliced ? __hip_atomic_exchange(dst, sum, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                            : __hip_atomic_fetch_add(dst, sum, __ATOMIC_RELAXED,
+                                                                     __HIP_MEMORY_SCOPE_AGENT);
+                    asm volatile("" ::"v"(old));          // keep the returning form of the atomic
+                }
+                __syncthreads();
+            }
+        }
+        __syncthreads();
+        if (tile_done) {
+            // every group this item completed counts towards its tile (32
+            // consecutive groups); the item that completes a tile sorts it into
+            // queue buckets
+            if (threadIdx.x == 0) sh.h.n_tiles = 0;
+            __syncthreads();
+            const int n_done = desc.y;
+            if ((int)threadIdx.x < n_done) {
+                int g = desc.z == kItemHist ? group_at(desc.x + (int)threadIdx.x) : (threadIdx.x == 0 ? gs[0] : gs[1]);
+                bool whole = true;
+                if (sliced) whole = atomicAdd(&A.gslices[g], 1) == S - 1;
+                if (whole) {
+                    if (sliced) __hip_atomic_store(&A.gslices[g], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    const int t = g / kTileGroups;
+                    const int in_tile = min(n_groups, (t + 1) * kTileGroups) - t * kTileGroups;
+                    if (atomicAdd(&tile_done[t], 1) == in_tile - 1) sh.h.tiles[atomicAdd(&sh.h.n_tiles, 1)] = t;
+                }
+            }
+            __syncthreads();
+            const int n_t = sh.h.n_tiles;
+            for (int i = 0; i < n_t; ++i) {
+                const int t = sh.h.tiles[i];
+                tile_pass<NT>(t, A.groups, scores, st, C, n_groups, A.kq, A.krank, A.knode, A.kcnt, A.hist, A.qmask,
+                              sh.sq, sh.sm);
+                if (threadIdx.x == 0) __hip_atomic_store(&tile_done[t], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __syncthreads();
+            }
+        }
+        if (ticket) {
+            if (threadIdx.x == 0) sh.s_next = nxt;
+            __syncthreads();
+            item = (int64_t)P + sh.s_next;
+        } else {
+            item += P;
+        }
+    }
+    // Every workgroup has drawn its last ticket: the last one to get here
+    // rewinds the counters for the next launch.
+    if (ticket && threadIdx.x == 0 && atomicAdd(&ticket[1], 1) == P - 1) {
+        __hip_atomic_store(&ticket[0], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&ticket[1], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
 template <int RM, int NT>
 __device__ void score_items(State *st, const ScoreArgs &A, const MapView &map, const SearchConst &C,
                             ScoreSmem<NT> &sh)
@@ -892,6 +1390,16 @@ __global__ __launch_bounds__(kScoreThreads) void k_score(State *st, ScoreArgs A,
     score_items<RM, kScoreThreads>(st, A, map, C, sh);
 }
 
+// The run-scheduled scoring, at most 96 vector registers a lane (five
+// resident workgroups per CU; the histogram path alone would take it to 116).
+template <int RM>
+__global__ __launch_bounds__(kScoreThreads) __attribute__((amdgpu_waves_per_eu(kScoreWgPerCu))) void k_score_runs(
+    State *st, ScoreArgs A, MapView map, SearchConst C)
+{
+    __shared__ ScoreSmemRuns<kScoreThreads> sh;
+    score_items_runs<RM, kScoreThreads>(st, A, map, C, sh);
+}
+
 // ------------------------------------------------------------------ initial set
 
 // Top-level cells as the valid children of virtual cells one level above:
@@ -927,6 +1435,7 @@ __global__ void k_enum_initial(uint4 *groups, int32_t *scores, int64_t g0, int32
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         st->n_groups = count;
+        st->runs = 0;
         st->batch = 1;
         st->q_min = INT_MAX;
         st->q_max = -1;
@@ -1209,7 +1718,28 @@ __device__ inline void child_counts(const Tab &C, const int32_t t[3], const int3
 // extends past a bucket only if that bucket ends in this chunk (otherwise its
 // next chunk comes first).  Writes the pending children as groups and zeroes
 // their score slots.
-template <int NT>
+// Runs of the pending batch: groups that share a level and rotation, found
+// with an LDS hash on (level, angle indices).  Each hash slot owns a region
+// of kRunCap entries of rgroups; slot kRunSlots is the overflow run (groups
+// of a full table or a full region, scored point by point), whose region
+// follows the others and holds a whole batch.
+constexpr int kRunSlots = 2048;
+constexpr int kRunCap = 256;
+constexpr unsigned long long kRunEmpty = ~0ull;
+
+// The run hash of the gather (only in the run-scheduled variant).
+template <bool RUNS>
+struct RunSmem {
+    unsigned long long rkey[kRunSlots];   // level | roll << 8 | pitch << 24 | yaw << 40
+    int rcnt[kRunSlots + 1];              // groups of the run
+    int roff[kRunSlots + 1];              // first entry of the run in rgroups
+    int lvl_groups[kMaxLevels];           // groups of the batch per level (runs of the hash table)
+};
+template <>
+struct RunSmem<false> {
+};
+
+template <int NT, bool RUNS>
 struct GatherSmem {
     int sm[NT / 64];
     int smatch[NT][6];
@@ -1220,16 +1750,35 @@ struct GatherSmem {
     int s_last[2];
     int s_end;
     int s_cut;
+    RunSmem<RUNS> run;
 };
+
+// Where the gather leaves the batch's runs for the scoring kernel.
+struct RunBufs {
+    int32_t *rgroups;         // group indices by run: kRunSlots x kRunCap, then the overflow run
+    int4 *items;              // item descriptors (first entry, groups, kind, slice)
+};
+
+// Slot of a run key in the LDS hash (kRunSlots when the table is full).
+__device__ inline int run_slot(unsigned long long *rkey, unsigned long long key)
+{
+    uint32_t h = (uint32_t)((key * 0x9E3779B97F4A7C15ull) >> 53);
+    for (int p = 0; p < kRunSlots; ++p) {
+        const unsigned long long old = atomicCAS(&rkey[h], kRunEmpty, key);
+        if (old == kRunEmpty || old == key) return (int)h;
+        h = (h + 1) & (kRunSlots - 1);
+    }
+    return kRunSlots;
+}
 
 __device__ inline int seg_len(const Bucket &b)
 {
     return (b.head_chunk == b.tail_chunk ? b.tail_fill : kChunk) - b.head_off;
 }
 
-template <int NT>
+template <int NT, bool RUNS>
 __device__ void gather(State *st, Bucket *bk, const int32_t *chunk_next, const uint4 *arena, const SearchConst &C,
-                       uint4 *groups, int32_t *scores, GatherSmem<NT> &sh)
+                       uint4 *groups, int32_t *scores, const RunBufs &RB, GatherSmem<NT, RUNS> &sh)
 {
     static_assert(NT >= kChunk, "a window must be able to hold a whole chunk segment");
     const int tid = threadIdx.x;
@@ -1250,9 +1799,20 @@ __device__ void gather(State *st, Bucket *bk, const int32_t *chunk_next, const u
         sh.lt.tlo[ax][l] = C.tlo[ax][l];
         sh.lt.thi[ax][l] = C.thi[ax][l];
     }
+    constexpr bool runs = RUNS;
+    int hist_levels = 0;
+    if constexpr (RUNS) {
+        hist_levels = C.dedup_levels & ~ld_agent(&st->hist_off);
+        for (int i = tid; i < kRunSlots; i += NT) sh.run.rkey[i] = kRunEmpty;
+        for (int i = tid; i <= kRunSlots; i += NT) sh.run.rcnt[i] = 0;
+        if (tid < kMaxLevels) sh.run.lvl_groups[tid] = 0;
+    }
     __syncthreads();
+    // buckets past qlim hold only scores below best (best-first); in the
+    // depth-first order those lie inside every level's range and are skipped
+    auto last_live = [&](int b) { return C.depth_first ? C.q_count - 1 : min((C.K - b) * Lp1 + C.levels, C.q_count - 1); };
     while (!cut && best <= C.K) {
-        int qlim = min((C.K - best) * Lp1 + C.levels, C.q_count - 1);
+        int qlim = last_live(best);
         if (q > qlim) break;
         // list the non-empty buckets among the next NT
         const int scan_end = min(q + NT - 1, qlim);
@@ -1272,9 +1832,13 @@ __device__ void gather(State *st, Bucket *bk, const int32_t *chunk_next, const u
             while (e < n_list && !cut) {
                 const int qe = sh.lq[e];
                 if (qe > qlim) break;
-                if (qe % Lp1 == 0) {
+                if (bucket_score(qe, C) < best) {   // depth-first only: below best, never popped
+                    ++e;
+                    continue;
+                }
+                if (bucket_level(qe, C) == 0) {
                     // a leaf bucket: accept all of it
-                    const int score = C.K - qe / Lp1;
+                    const int score = bucket_score(qe, C);
                     const Bucket lbk = sh.lb[e];
                     int c = lbk.head_chunk, off = lbk.head_off;
                     int32_t mine[6] = {INT_MAX, INT_MAX, INT_MAX, INT_MAX, INT_MAX, INT_MAX};
@@ -1304,7 +1868,7 @@ __device__ void gather(State *st, Bucket *bk, const int32_t *chunk_next, const u
                     __syncthreads();
                     have = 1;
                     best = score;
-                    qlim = min((C.K - best) * Lp1 + C.levels, C.q_count - 1);
+                    qlim = last_live(best);
                     if (tid == 0) bk[qe] = Bucket{-1, 0, -1, 0};
                     ++e;
                     continue;
@@ -1316,7 +1880,7 @@ __device__ void gather(State *st, Bucket *bk, const int32_t *chunk_next, const u
                     bool ok = false;
                     if (i < n_list) {
                         const int qi = sh.lq[i];
-                        ok = qi <= qlim && qi % Lp1 != 0;
+                        ok = qi <= qlim && bucket_level(qi, C) != 0 && bucket_score(qi, C) >= best;
                         seg = ok ? seg_len(sh.lb[i]) : 0;
                     }
                     int tot;
@@ -1349,7 +1913,7 @@ __device__ void gather(State *st, Bucket *bk, const int32_t *chunk_next, const u
                     const int j = lo;
                     const int base = j > 0 ? sh.pre[j - 1] : 0;
                     const Bucket bj = sh.lb[e + j];
-                    level = sh.lq[e + j] % Lp1;
+                    level = bucket_level(sh.lq[e + j], C);
                     node_unpack(arena[(int64_t)bj.head_chunk * kChunk + bj.head_off + (tid - base)], t3, ang, lv);
                     child_counts(sh.lt, t3, ang, level, rc, tmask, nn, ng);
                 }
@@ -1382,6 +1946,18 @@ __device__ void gather(State *st, Bucket *bk, const int32_t *chunk_next, const u
                                 const int ra = sh.lt.a[0][level] * ang[0] + ja;
                                 const int rb = sh.lt.a[1][level] * ang[1] + jb;
                                 const int rg = sh.lt.a[2][level] * ang[2] + jg;
+                                if constexpr (RUNS) {
+                                    const unsigned long long key =
+                                        (unsigned long long)(level - 1) | ((unsigned long long)ra << 8) |
+                                        ((unsigned long long)rb << 24) | ((unsigned long long)rg << 40);
+                                    int slot = run_slot(sh.run.rkey, key);
+                                    int rank = slot < kRunSlots ? atomicAdd(&sh.run.rcnt[slot], 1) : kRunCap;
+                                    if (rank >= kRunCap) {
+                                        slot = kRunSlots;
+                                        rank = atomicAdd(&sh.run.rcnt[kRunSlots], 1);
+                                    }
+                                    RB.rgroups[(int64_t)slot * kRunCap + rank] = gi;
+                                }
                                 groups[gi++] = make_uint4(pack16(2 * t3[0], 2 * t3[1]), pack16(2 * t3[2], ra),
                                                           pack16(rb, rg), (uint32_t)(level - 1) | (tmask << 8));
                             }
@@ -1433,11 +2009,84 @@ __device__ void gather(State *st, Bucket *bk, const int32_t *chunk_next, const u
         }
     }
     __syncthreads();
-    // a batch of at least score_items groups is scored in pairs, which store
-    // their counts; a smaller one in slices that add to zeroed scores
-    if (ngrp < C.score_items)
+    // The batch as scoring items.  Runs of a level whose scan histogram fits
+    // (C.dedup_levels, less the levels whose histogram overflowed) become
+    // histogram items of at most kItemGroups groups; the other groups are
+    // scored point by point, in pairs within a run, or, when fewer than
+    // score_items of them are pending, in point slices.
+    int n_items = 0, n_hist_items = 0, n_hist_groups = 0, n_slices = 1;
+    if constexpr (RUNS) {
+        constexpr int kPer = (kRunSlots + NT) / NT;    // slots per thread, the overflow slot included
+        int cnt_s[kPer];
+        bool hist_s[kPer];
+        int xcnt = 0, hcnt = 0, hitems = 0;
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) {
+            const int sl = tid * kPer + i;
+            int c = 0;
+            bool h = false;
+            if (sl < kRunSlots) {
+                c = min(sh.run.rcnt[sl], kRunCap);
+                if (c > 0) h = (hist_levels >> (int)(sh.run.rkey[sl] & 0xFF)) & 1;
+            } else if (sl == kRunSlots) {
+                c = sh.run.rcnt[sl];
+            }
+            cnt_s[i] = c;
+            hist_s[i] = h;
+            if (h) {
+                hcnt += c;
+                hitems += (c + kItemGroups - 1) / kItemGroups;
+            } else {
+                xcnt += c;
+            }
+            if (c > 0 && sl < kRunSlots) atomicAdd(&sh.run.lvl_groups[(int)(sh.run.rkey[sl] & 0xFF)], c);
+        }
+        int x_tot;
+        (void)block_scan_incl<NT>(xcnt, sh.sm, &x_tot);
+        const int max_s = (C.K + kScoreThreads * kUnroll - 1) / (kScoreThreads * kUnroll);
+        if (x_tot > 0 && x_tot < C.score_items) n_slices = max(1, min(max_s, (C.score_items + x_tot - 1) / x_tot));
+        // items of this thread's slots, then their offsets
+        int mine = hitems;
+#pragma unroll
+        for (int i = 0; i < kPer; ++i)
+            if (!hist_s[i]) mine += n_slices > 1 ? cnt_s[i] * n_slices : (cnt_s[i] + 1) / 2;
+        int i_tot, h_tot;
+        int at = block_scan_incl<NT>(mine, sh.sm, &i_tot) - mine;
+        (void)block_scan_incl<NT>(hcnt, sh.sm, &h_tot);
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) {
+            const int sl = tid * kPer + i;
+            const int c = cnt_s[i];
+            const int first = sl * kRunCap;
+            if (hist_s[i]) {
+                for (int q = 0; q < c; q += kItemGroups)
+                    RB.items[at++] = make_int4(first + q, min(kItemGroups, c - q), kItemHist, 0);
+            } else if (n_slices > 1) {
+                for (int q = 0; q < c; ++q)
+                    for (int j = 0; j < n_slices; ++j) RB.items[at++] = make_int4(first + q, 1, kItemSlice, j);
+            } else {
+                for (int q = 0; q < c; q += 2) RB.items[at++] = make_int4(first + q, min(2, c - q), kItemPair, 0);
+            }
+        }
+        n_items = i_tot;
+        n_hist_groups = h_tot;
+        int hi_tot;
+        (void)block_scan_incl<NT>(hitems, sh.sm, &hi_tot);
+        n_hist_items = hi_tot;
+    }
+    // sliced groups add their counts to zeroed scores (so does the legacy
+    // scheme when fewer than score_items groups are pending)
+    if (runs ? n_slices > 1 : ngrp < C.score_items)
         for (int i = tid; i < 8 * ngrp; i += NT) scores[i] = 0;
+    if constexpr (RUNS) {
+        if (tid < kMaxLevels) st->level_groups[tid] += sh.run.lvl_groups[tid];
+    }
     if (tid == 0) {
+        st->runs = runs ? 1 : 0;
+        st->n_items = n_items;
+        st->n_slices = n_slices;
+        st->dedup_items += n_hist_items;
+        st->dedup_groups += n_hist_groups;
         st->best = best;
         st->have_match = have;
         for (int i = 0; i < 6; ++i) st->match[i] = match[i];
@@ -1464,19 +2113,47 @@ __device__ void gather(State *st, Bucket *bk, const int32_t *chunk_next, const u
 // The serial part of an iteration, one workgroup: push the scored batch,
 // then (unless this is an initial-set chunk with more to come) gather the
 // next one.
-template <int NT>
-struct SerialSmem {
-    int sm[NT / 64];
-    GatherSmem<NT> g;
+// LDS copies of the push's per-bucket lists (occupied buckets, their totals,
+// tail chunk, fill and first new chunk), which only the serial workgroup
+// writes and reads: used when the queue has at most kPushLds buckets (and
+// the gather keeps no run hash), otherwise the global workspace arrays.
+constexpr int kPushLds = 4096;
+template <bool ON>
+struct PushSmem {
+    int qlist[kPushLds];
+    int totals[kPushLds];
+    int pT[kPushLds];
+    int pf[kPushLds];
+    int pc0[kPushLds];
+};
+template <>
+struct PushSmem<false> {
 };
 
-template <int NT>
+template <int NT, bool RUNS>
+struct SerialSmem {
+    int sm[NT / 64];
+    GatherSmem<NT, RUNS> g;
+    PushSmem<!RUNS> p;
+};
+
+template <int NT, bool RUNS>
 __device__ void serial_body(State *st, const SearchConst &C, Bucket *bk, uint4 *groups, int32_t *scores,
-                            const PushBufs &B, int do_gather, SerialSmem<NT> &sh)
+                            const PushBufs &B, const RunBufs &RB, int do_gather, SerialSmem<NT, RUNS> &sh)
 {
     if (ld_agent(&st->done)) return;
     const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
-    if (ld_agent(&st->batch)) push_finish<NT>(st, C, bk, groups, B, sh.sm, sh.g.pre);
+    PushBufs Bp = B;
+    if constexpr (!RUNS) {
+        if (C.q_count <= kPushLds) {
+            Bp.qlist = sh.p.qlist;
+            Bp.totals = sh.p.totals;
+            Bp.pT = sh.p.pT;
+            Bp.pf = sh.p.pf;
+            Bp.pc0 = sh.p.pc0;
+        }
+    }
+    if (ld_agent(&st->batch)) push_finish<NT>(st, C, bk, groups, Bp, sh.sm, sh.g.pre);
     __syncthreads();
     const uint64_t t1 = __builtin_amdgcn_s_memrealtime();
     if (threadIdx.x == 0) st->t_push += (int64_t)(t1 - t0);
@@ -1484,17 +2161,18 @@ __device__ void serial_body(State *st, const SearchConst &C, Bucket *bk, uint4 *
     if (threadIdx.x == 0) st->batch = 0;
     __syncthreads();
     if (do_gather) {
-        gather<NT>(st, bk, B.chunk_next, B.arena, C, groups, scores, sh.g);
+        gather<NT, RUNS>(st, bk, B.chunk_next, B.arena, C, groups, scores, RB, sh.g);
         __syncthreads();
         if (threadIdx.x == 0) st->t_gather += (int64_t)(__builtin_amdgcn_s_memrealtime() - t1);
     }
 }
 
+template <bool RUNS>
 __global__ __launch_bounds__(kSerialThreads) void k_serial(State *st, SearchConst C, Bucket *bk, uint4 *groups,
-                                                           int32_t *scores, PushBufs B, int do_gather)
+                                                           int32_t *scores, PushBufs B, RunBufs RB, int do_gather)
 {
-    __shared__ SerialSmem<kSerialThreads> sh;
-    serial_body<kSerialThreads>(st, C, bk, groups, scores, B, do_gather, sh);
+    __shared__ SerialSmem<kSerialThreads, RUNS> sh;
+    serial_body<kSerialThreads, RUNS>(st, C, bk, groups, scores, B, RB, do_gather, sh);
 }
 
 // ------------------------------------------------------------------ persistent search loop
@@ -1541,16 +2219,17 @@ __device__ bool grid_sync(unsigned *bar, int32_t *err, int *s_ok)
 template <int RM>
 __global__ __launch_bounds__(kPersistThreads) void k_persistent(State *st, ScoreArgs A, MapView map, SearchConst C,
                                                                 Bucket *bk, uint4 *groups, int32_t *scores,
-                                                                PushBufs B, unsigned *bar, int32_t max_iters)
+                                                                PushBufs B, RunBufs RB, unsigned *bar,
+                                                                int32_t max_iters)
 {
     __shared__ ScoreSmem<kPersistThreads> ssh;
-    __shared__ SerialSmem<kPersistThreads> sh;
+    __shared__ SerialSmem<kPersistThreads, false> sh;
     __shared__ int s_ok;
     for (int it = 0; it < max_iters; ++it) {
         if (ld_agent(&st->done)) break;
         score_items<RM, kPersistThreads>(st, A, map, C, ssh);
         if (!grid_sync(bar, &st->error, &s_ok)) break;
-        if (blockIdx.x == 0) serial_body<kPersistThreads>(st, C, bk, groups, scores, B, 1, sh);
+        if (blockIdx.x == 0) serial_body<kPersistThreads, false>(st, C, bk, groups, scores, B, RB, 1, sh);
         if (!grid_sync(bar, &st->error, &s_ok)) break;
     }
 }
@@ -1564,6 +2243,7 @@ __global__ void k_begin_batch(State *st, int32_t *scores, int32_t n_groups)
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < 8 * n_groups; i += gridDim.x * blockDim.x) scores[i] = 0;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         st->n_groups = n_groups;
+        st->runs = 0;
         st->batch = 1;
         st->q_min = INT_MAX;
         st->q_max = -1;
@@ -1763,6 +2443,12 @@ struct bbs_workspace {
     int64_t tile_done_n = 0;
     int32_t *ticket = nullptr;   // scoring item tickets (2 counters, zero between launches)
     int64_t ticket_n = 0;
+    int32_t *rgroups = nullptr;  // runs of the pending batch and their items (see RunBufs)
+    int64_t rgroups_n = 0;
+    int4 *items = nullptr;
+    int64_t items_n = 0;
+    int32_t *gslices = nullptr;  // point slices done per group (zero between launches)
+    int64_t gslices_n = 0;
     int32_t score_grid[3] = {0, 0, 0};   // resident k_score workgroups, per division mode
     float *scan = nullptr;
     int64_t scan_n = 0;
@@ -1859,7 +2545,7 @@ void free_ws(bbs_workspace *w)
                     w->pc0,     w->groups,     w->scores,  w->kq,       w->krank,   w->hbase, w->knode,
                     w->kcnt,    w->tile_done,  w->ticket,  w->scan,     w->scan_aos, w->scan_tmp, w->mkeys,
                     w->mhist,   w->trig,       w->state,   w->maxsq,    w->beam,    w->prior, w->dstate,
-                    w->bar,     w->qmask,      w->qlist};
+                    w->bar,     w->qmask,      w->qlist,   w->rgroups,  w->items,   w->gslices};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (w->host_state) (void)hipHostFree(w->host_state);
@@ -2016,6 +2702,7 @@ bbs_status setup_search(const bbs_map *m, bbs_workspace *ws, const float *scan, 
     C.threshold = T;
     C.q_count = (C.K - T + 1) * (C.levels + 1);
     if (C.q_count < 0) C.q_count = 0;
+    C.n_scores = std::max<int32_t>(C.K - T + 1, 1);
     C.batch = batch;
     C.r = g.r;
     S.pow2 = is_pow2_float(g.r);
@@ -2058,6 +2745,9 @@ ScoreArgs score_args(const Setup &S, bbs_workspace *ws, int32_t n_fixed, bool ti
     A.hist = ws->hist;
     A.qmask = ws->qmask;
     A.ticket = nullptr;
+    A.rgroups = ws->rgroups;
+    A.items = ws->items;
+    A.gslices = ws->gslices;
     return A;
 }
 
@@ -2066,9 +2756,15 @@ void launch_score(const Setup &S, const bbs_map *m, bbs_workspace *ws, State *st
 {
     const ScoreArgs A = score_args(S, ws, n_fixed, tile_pass);
     const MapView v = m->view();
-    if (S.rmode == 2) k_score<2><<<grid, kScoreThreads, 0, S.s>>>(st, A, v, S.C);
-    else if (S.rmode == 1) k_score<1><<<grid, kScoreThreads, 0, S.s>>>(st, A, v, S.C);
-    else k_score<0><<<grid, kScoreThreads, 0, S.s>>>(st, A, v, S.C);
+    if (S.C.dedup_levels) {
+        if (S.rmode == 2) k_score_runs<2><<<grid, kScoreThreads, 0, S.s>>>(st, A, v, S.C);
+        else if (S.rmode == 1) k_score_runs<1><<<grid, kScoreThreads, 0, S.s>>>(st, A, v, S.C);
+        else k_score_runs<0><<<grid, kScoreThreads, 0, S.s>>>(st, A, v, S.C);
+    } else {
+        if (S.rmode == 2) k_score<2><<<grid, kScoreThreads, 0, S.s>>>(st, A, v, S.C);
+        else if (S.rmode == 1) k_score<1><<<grid, kScoreThreads, 0, S.s>>>(st, A, v, S.C);
+        else k_score<0><<<grid, kScoreThreads, 0, S.s>>>(st, A, v, S.C);
+    }
 }
 
 int64_t max_children(const Grid &g)
@@ -2214,6 +2910,9 @@ bbs_status localize_impl(const bbs_map *map, bbs_workspace *ws, const float *sca
     if (o.score_items < 0 || o.score_items > (1 << 20))
         return fail(BBS_ERR_INVALID_ARG, "bbs_localize: score_items must be in [0, 2^20]");
     if (o.score_items > 0) S.C.score_items = o.score_items;
+    if (o.strategy != 0 && o.strategy != 1)
+        return fail(BBS_ERR_INVALID_ARG, "bbs_localize: strategy must be 0 (best first) or 1 (depth first)");
+    S.C.depth_first = o.strategy;
     const Grid &g = S.g;
     const SearchConst &C = S.C;
     const int L = g.levels;
@@ -2236,14 +2935,31 @@ bbs_status localize_impl(const bbs_map *map, bbs_workspace *ws, const float *sca
     S.C.max_children = (int32_t)std::min<int64_t>(mc, INT32_MAX);
     const int64_t cap_groups = std::max<int64_t>(o.batch_size + mc, 4096);
     const int64_t n_tiles = (cap_groups + kTileGroups - 1) / kTileGroups;
+    // levels whose runs are scored through the scan's voxel histogram: from
+    // hist_min_level up (off by default; -1: from level 0), where the packed
+    // voxel fits (|v| < 512), the 16-bit counts cannot overflow and the run
+    // ranks fit 20 bits
+    {
+        const int lo_l = o.hist_min_level > 0 ? o.hist_min_level : (o.hist_min_level < 0 ? 0 : 99);
+        S.C.dedup_levels = 0;
+        if (k <= 65535 && cap_groups < (1 << 20))
+            for (int l = lo_l; l <= L; ++l)
+                if ((g.dmax / (double)g.r + 2.0) / (double)(1 << l) < 500.0) S.C.dedup_levels |= 1 << l;
+    }
     const int64_t qn = std::max<int32_t>(C.q_count, 1);
     if (ensure(ws, ws->groups, ws->groups_n, cap_groups) || ensure(ws, ws->scores, ws->scores_n, 8 * cap_groups) ||
         ensure(ws, ws->kq, ws->kq_n, n_tiles * kTileSlots) || ensure(ws, ws->knode, ws->knode_n, n_tiles * kTileSlots) ||
         ensure(ws, ws->kcnt, ws->kcnt_n, n_tiles) || ensure(ws, ws->hbase, ws->hbase_n, n_tiles * qn) ||
         ensure(ws, ws->krank, ws->krank_n, n_tiles * kTileSlots) || ensure(ws, ws->totals, ws->totals_n, qn) ||
         ensure(ws, ws->pT, ws->pT_n, qn) || ensure(ws, ws->pf, ws->pf_n, qn) || ensure(ws, ws->pc0, ws->pc0_n, qn) ||
-        ensure(ws, ws->buckets, ws->buckets_n, qn) || ensure(ws, ws->state, ws->state_n, 1))
+        ensure(ws, ws->buckets, ws->buckets_n, qn) || ensure(ws, ws->state, ws->state_n, 1) ||
+        ensure(ws, ws->rgroups, ws->rgroups_n, (int64_t)kRunSlots * kRunCap + cap_groups) ||
+        ensure(ws, ws->items, ws->items_n, 2 * cap_groups + S.C.score_items + 4 * (kRunSlots + 1)))
         return ws_fail(ws);
+    if (!ws->gslices || ws->gslices_n < cap_groups) {
+        if (ensure(ws, ws->gslices, ws->gslices_n, cap_groups)) return ws_fail(ws);
+        ws->hist_dirty = true;
+    }
     if (!ws->tile_done || ws->tile_done_n < n_tiles) {
         if (ensure(ws, ws->tile_done, ws->tile_done_n, n_tiles)) return ws_fail(ws);
         ws->hist_dirty = true;
@@ -2280,6 +2996,7 @@ bbs_status localize_impl(const bbs_map *map, bbs_workspace *ws, const float *sca
         BBS_HIP(zero_async(ws->qmask, (size_t)ws->qmask_n * 4, s));
         BBS_HIP(zero_async(ws->hist, (size_t)ws->hist_n * 4, s));
         BBS_HIP(zero_async(ws->tile_done, (size_t)ws->tile_done_n * 4, s));
+        BBS_HIP(zero_async(ws->gslices, (size_t)ws->gslices_n * 4, s));
         BBS_HIP(zero_async(ws->ticket, 2 * sizeof(int32_t), s));
         ws->hist_dirty = false;
     }
@@ -2323,8 +3040,16 @@ bbs_status localize_impl(const bbs_map *map, bbs_workspace *ws, const float *sca
     B.hbase = ws->hbase;
     B.knode = ws->knode;
     B.kcnt = ws->kcnt;
+    RunBufs RB;
+    RB.rgroups = ws->rgroups;
+    RB.items = ws->items;
     auto serial = [&](int do_gather) {
-        k_serial<<<1, kSerialThreads, 0, s>>>(ws->state, C, ws->buckets, ws->groups, ws->scores, B, do_gather);
+        if (C.dedup_levels)
+            k_serial<true><<<1, kSerialThreads, 0, s>>>(ws->state, C, ws->buckets, ws->groups, ws->scores, B, RB,
+                                                         do_gather);
+        else
+            k_serial<false><<<1, kSerialThreads, 0, s>>>(ws->state, C, ws->buckets, ws->groups, ws->scores, B, RB,
+                                                          do_gather);
     };
     const double t_setup = ms_since(t_start);
 
@@ -2458,7 +3183,7 @@ bbs_status localize_impl(const bbs_map *map, bbs_workspace *ws, const float *sca
             int32_t *sp = ws->scores;
             unsigned *barp = ws->bar;
             int32_t max_it = 1 << 24;
-            void *args[] = {&stp, &A, &v, &Cv, &bkp, &gp, &sp, &B, &barp, &max_it};
+            void *args[] = {&stp, &A, &v, &Cv, &bkp, &gp, &sp, &B, &RB, &barp, &max_it};
             const int grid = cus * std::min(per_cu, 4);
             oe = hipLaunchCooperativeKernel(fn, dim3(grid), dim3(kPersistThreads), args, 0, s);
             if (oe == hipSuccess) persistent_used = true;
@@ -2599,6 +3324,11 @@ bbs_status localize_impl(const bbs_map *map, bbs_workspace *ws, const float *sca
     out->serial_ms[2] = (double)fs.t_push_prefix * 1e-5;
     out->serial_ms[3] = (double)fs.t_push_alloc * 1e-5;
     out->seed_score = fs.seeded ? fs.seed_score : 0;
+    for (int l = 0; l < kMaxLevels; ++l) out->level_groups[l] = fs.level_groups[l];
+    out->hist_groups = fs.dedup_groups;
+    out->hist_items = fs.dedup_items;
+    out->hist_fallbacks = fs.hist_fallbacks;
+    out->hist_off = fs.hist_off;
     out->flushes = fs.flushes;
     out->leaves_accepted = fs.leaves_accepted;
     out->initial_size = init_nodes;

@@ -5,11 +5,14 @@ instances (`tests/golden/schedule_hand.json`) whose node scores can be read
 off the voxel sets by eye, with every pop, flush, counter and the match
 traced by hand from the rules of Alg. 2 and the readings the oracle states
 (queue order score desc, level asc, first in first out; strict `<` prune;
-flush when more than b children are pending, and when the queue runs empty).
+flush when more than b children are pending, and when the queue runs empty),
+each also traced in the depth-first order of Alg. 1 (level asc, then score
+desc, then first in first out).
 
-The mutation tests show that these pins bind: each of five plausible slips in
+The mutation tests show that these pins bind: each of seven plausible slips in
 the schedule (level order reversed, last in first out, flush at >= b, no
-termination flush, prune at <=) is planted in a copy of the oracle's source,
+termination flush, prune at <=, and in the depth-first order levels reversed
+or the best-first order used instead) is planted in a copy of the oracle's source,
 compiled, and must fail the hand-traced pins (run in a subprocess that loads
 the broken copy); the unmodified copy must pass them.
 """
@@ -58,7 +61,8 @@ def test_hand_traced_voxel_sets_and_scores(inst):
 @pytest.mark.parametrize("inst", INSTANCES, ids=[i["name"] for i in INSTANCES])
 def test_hand_traced_schedule(inst):
     _, s = build_instance(inst)
-    r = s.localize(inst["threshold"], batch=inst["batch"], threads=1, trace_cap=64, events_cap=64)
+    r = s.localize(inst["threshold"], batch=inst["batch"], threads=1, trace_cap=64, events_cap=64,
+                   strategy=inst.get("strategy", "best_first"))
     assert r["events"] == inst["events"]
     want = inst["result"]
     got = {k: r[k] for k in want if k != "flush_sizes"}
@@ -74,6 +78,10 @@ MUTANTS = {
     "no_termination_flush": ("if (pending.n == 0) break;\n            flush = 1;",
                              "break;\n            flush = 1;"),
     "prune_at_equal": ("if (c.score < best) {", "if (c.score <= best) {"),
+    "depth_first_levels_reversed": ("if (order == ORC_DEPTH_FIRST && a->level != b->level) return a->level < b->level;",
+                                    "if (order == ORC_DEPTH_FIRST && a->level != b->level) return a->level > b->level;"),
+    "depth_first_as_best_first": ("if (order == ORC_DEPTH_FIRST && a->level != b->level)",
+                                  "if (order == 99 && a->level != b->level)"),
 }
 
 

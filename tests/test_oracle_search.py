@@ -64,6 +64,39 @@ def test_translation_only_bnb_equals_full_search(seed, frac):
             assert r["score"] == bf["score"] and r["leaf"] == bf["leaf"], b
 
 
+@pytest.mark.parametrize("seed", [0, 4])
+def test_depth_first_translation_only_equals_full_search(seed):
+    """The depth-first order of Alg. 1 (Table I, DFS) changes only the pop
+    order: with the exact bound of translation-only branching it returns the
+    full search's optimum too, at every batch size."""
+    s = tiny_case(seed, k=150, rp_deg=1.0, z_w=0.5)
+    T = int(0.6 * s.k)
+    bf = s.bruteforce(T, threads=8)
+    for b in (1, 64, 10000):
+        r = s.localize(T, batch=b, threads=8, strategy="depth_first")
+        assert r["found"] == bf["found"], b
+        if bf["found"]:
+            assert r["score"] == bf["score"] and r["leaf"] == bf["leaf"], b
+
+
+def test_depth_first_pops_levels_in_order():
+    """Between two flushes nothing is pushed, so the depth-first pops of one
+    batch come in (level ascending, score descending) order, and a leaf is
+    reached before any pending parent of a higher level is popped."""
+    s = tiny_case(1, k=200, translation_only=False, rp_deg=2.0)
+    r = s.localize(int(0.5 * s.k), batch=64, threads=8, events_cap=200000, strategy="depth_first")
+    assert r["events_total"] <= 200000
+    prev = None
+    for e in r["events"]:
+        if e[0] == "flush":
+            prev = None
+            continue
+        key = (e[1][0], -e[2])
+        if prev is not None:
+            assert key >= prev, (prev, key)
+        prev = key
+
+
 def test_translation_only_with_z_and_tilt_axes():
     s = tiny_case(5, k=120, rp_deg=2.0, z_w=0.5)
     T = int(0.6 * s.k)
