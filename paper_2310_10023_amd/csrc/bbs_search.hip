@@ -1505,9 +1505,11 @@ __device__ void push_finish(State *st, const SearchConst &C, Bucket *bk, const u
     // per-bucket prefix over tiles (tile-major histogram, in blocks of 16 tiles)
     const int n_blk = (n_tiles + 15) / 16;
     if (n_occ * n_blk <= NT) {
-        // one (bucket, block) pair per thread: every load in one round, block
-        // sums scanned per bucket in LDS, the counts rewritten from registers
-        const int pidx = tid, i = pidx / n_blk, j = pidx - i * n_blk;
+        // one (bucket, block) pair per thread, consecutive threads on
+        // consecutive occupied buckets of one block (neighbouring entries of a
+        // histogram row): every load in one round, block sums scanned per
+        // bucket in LDS, the counts rewritten from registers
+        const int pidx = tid, j = pidx / n_occ, i = pidx - j * n_occ;
         const bool act = pidx < n_occ * n_blk;
         const int q = act ? B.qlist[i] : 0;
         int v[16], sum = 0;
@@ -1522,8 +1524,8 @@ __device__ void push_finish(State *st, const SearchConst &C, Bucket *bk, const u
         if (tid < n_occ) {
             int acc = 0;
             for (int jj = 0; jj < n_blk; ++jj) {
-                const int x = blk[tid * n_blk + jj];
-                blk[tid * n_blk + jj] = acc;
+                const int x = blk[jj * n_occ + tid];
+                blk[jj * n_occ + tid] = acc;
                 acc += x;
             }
             B.totals[tid] = acc;
