@@ -305,6 +305,14 @@ bbs_status bbs_net_forward(bbs_net *net, const uint8_t *images, int32_t images_o
 bbs_status bbs_net_train_step(bbs_net *net, const uint8_t *images, int32_t images_on_device, const int32_t *yaw,
                               const int32_t *xy, int32_t batch, float lr, float weight_decay, float *loss_out,
                               float *grads_out);
+/* The prior of one scan for bbs_localize's opt->prior: the scan's bird's-eye
+ * polar image (as bbs_bev_image computes it, d_max included) and the forward
+ * pass, on the device, with only the 1088 logits copied to the host array.
+ * The scan may be host or device memory; a host scan is staged in a device
+ * buffer the network keeps (grown when a larger scan comes).  Runs on the
+ * network's own stream and returns when the logits are in place. */
+bbs_status bbs_net_prior(bbs_net *net, const float *scan_xyz, int64_t k, int32_t scan_on_device, float *logits);
+
 /* Bird's-eye polar image of a scan into a host [64, 64] uint8 array: range
  * bin floor(64 |(x, y)| / d_max) clamped to 63, azimuth bin
  * floor(64 atan2(y, x) / 2 pi) mod 64, min(255, count) per cell. */

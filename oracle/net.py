@@ -187,3 +187,27 @@ def bev_image(scan: np.ndarray, dmax: float) -> np.ndarray:
     img = np.zeros((BINS, BINS), np.int64)
     np.add.at(img, (rb, ab), 1)
     return np.minimum(img, 255).astype(np.uint8)
+
+
+def adamw_step(params: dict, moments: dict, grads: dict, step: int, lr: float, weight_decay: float,
+               b1: float = 0.9, b2: float = 0.999, eps: float = 1e-8):
+    """One step of Adam with decoupled weight decay (Loshchilov and Hutter,
+    "Decoupled Weight Decay Regularization"), in float64: first and second
+    moment averages with bias correction by 1 - beta^step, and weight decay
+    lr * wd * p applied to the weights (not the biases) apart from the
+    gradient step.  moments maps each name to an (m, v) pair, updated; the
+    new parameters are returned."""
+    out = {}
+    c1, c2 = 1.0 - b1 ** step, 1.0 - b2 ** step
+    for name in PARAM_NAMES:
+        g = np.asarray(grads[name], np.float64)
+        m, v = moments.get(name, (np.zeros_like(g), np.zeros_like(g)))
+        m = b1 * m + (1.0 - b1) * g
+        v = b2 * v + (1.0 - b2) * g * g
+        moments[name] = (m, v)
+        p = np.asarray(params[name], np.float64)
+        if name.endswith("w"):
+            p = p - lr * weight_decay * p
+        out[name] = p - lr * (m / c1) / (np.sqrt(v / c2) + eps)
+    return out
+

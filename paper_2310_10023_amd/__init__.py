@@ -25,7 +25,7 @@ EXPORTED_SYMBOLS = (
     "bbs_default_options", "bbs_abi_version", "bbs_last_error", "bbs_build_map", "bbs_free_map", "bbs_map_info",
     "bbs_map_layout", "bbs_map_dump_level", "bbs_map_contains", "bbs_workspace_create", "bbs_workspace_free", "bbs_localize", "bbs_localize_noalloc",
     "bbs_score_nodes", "bbs_serve", "bbs_net_param_count", "bbs_net_create", "bbs_net_free", "bbs_net_set_params",
-    "bbs_net_get_params", "bbs_net_forward", "bbs_net_train_step", "bbs_bev_image", "bbs_autotune",
+    "bbs_net_get_params", "bbs_net_forward", "bbs_net_prior", "bbs_net_train_step", "bbs_bev_image", "bbs_autotune",
     "bbs_bandwidth_probe",
 )
 
@@ -101,6 +101,13 @@ def lib():
     if _lib is None:
         if not os.path.exists(_LIB_PATH):
             raise LibraryMissing(f"libbbs is not built ({_LIB_PATH}); run python -m paper_2310_10023_amd.build")
+        # torch ships its own HIP runtime under the same soname; loading torch
+        # first makes libbbs bind to that one, so the process holds a single
+        # HIP runtime (a second one, loaded first, leaves torch without devices)
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(_LIB_PATH)
         P, I32, I64, F = C.c_void_p, C.c_int32, C.c_int64, C.c_float
         L.bbs_default_options.argtypes = [C.POINTER(Options)]

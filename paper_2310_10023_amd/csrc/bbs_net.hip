@@ -16,6 +16,7 @@
 // Parameter order (flat, row-major): c1w [16,3,3,1] c1b, c2w [32,3,3,16] c2b,
 // c3w [64,3,3,32] c3b, c4w [64,3,3,64] c4b, f1w [256,1024] f1b,
 // f2w [1088,256] f2b.  Activations are [B, H, W, C].
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -305,6 +306,51 @@ __global__ void k_bev_pack(const int32_t *cnt, uint8_t *img)
     if (i < kBins * kBins) img[i] = (uint8_t)min(cnt[i], 255);
 }
 
+// The largest squared range of the scan in double ((x*x + y*y) + z*z), as
+// the bits of a non-negative double, by atomic maximum; a non-finite
+// coordinate gives +inf.
+__global__ void k_bev_maxsq(const float *xyz, int64_t k, unsigned long long *max_sq)
+{
+    __shared__ double sm[256];
+    double m = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < k; i += (int64_t)gridDim.x * blockDim.x) {
+        const double x = xyz[3 * i], y = xyz[3 * i + 1], z = xyz[3 * i + 2];
+        double d = x * x + y * y + z * z;
+        if (!(d <= 1.0e300)) d = INFINITY;
+        m = fmax(m, d);
+    }
+    sm[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicMax(max_sq, (unsigned long long)__double_as_longlong(sm[0]));
+}
+
+// The BEV counts with d_max read from the device (float of the double square
+// root, as the host path computes it); an empty or non-finite scan leaves
+// the counts at zero and sets *bad.
+__global__ void k_bev_count_dev(const float *xyz, int64_t k, const unsigned long long *max_sq, int32_t *cnt,
+                                int32_t *bad)
+{
+    const double mx = __longlong_as_double((long long)*max_sq);
+    const float dmax = (float)sqrt(mx);
+    if (!(dmax > 0.0f) || !isfinite(dmax)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) *bad = 1;
+        return;
+    }
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < k; i += (int64_t)gridDim.x * blockDim.x) {
+        const float x = xyz[3 * i], y = xyz[3 * i + 1];
+        const float rho = sqrtf(x * x + y * y);
+        int rb = (int)(kBins * rho / dmax);
+        rb = min(max(rb, 0), kBins - 1);
+        int ab = (int)floorf(kBins * atan2f(y, x) / 6.283185307179586f);
+        ab = ((ab % kBins) + kBins) % kBins;
+        atomicAdd(&cnt[rb * kBins + ab], 1);
+    }
+}
+
 struct Shapes {
     int64_t off[12], size[12], total;
     Shapes()
@@ -346,6 +392,13 @@ struct bbs_net {
     uint16_t *dlog = nullptr, *dh1 = nullptr, *dh0 = nullptr, *da[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     float *loss = nullptr;
     int64_t step = 0;
+    // on-device prior of one scan (bbs_net_prior): scan staging (grows),
+    // squared range, BEV counts, failure flag
+    float *scan = nullptr;
+    int64_t scan_cap = 0;
+    unsigned long long *maxsq = nullptr;
+    int32_t *bev_cnt = nullptr;
+    int32_t *bev_bad = nullptr;
     std::vector<void *> owned;
 };
 
@@ -439,7 +492,8 @@ extern "C" bbs_status bbs_net_create(int32_t max_batch, bbs_net **out)
                net_alloc(n, (void **)&n->table, 256 * 2) || net_alloc(n, (void **)&n->x0, B * 64 * 64 * 2) ||
                net_alloc(n, (void **)&n->h1, B * kF1 * 2) || net_alloc(n, (void **)&n->logits, B * kOut * 4) ||
                net_alloc(n, (void **)&n->dlog, B * kOut * 2) || net_alloc(n, (void **)&n->dh1, B * kF1 * 2) ||
-               net_alloc(n, (void **)&n->loss, 64);
+               net_alloc(n, (void **)&n->loss, 64) || net_alloc(n, (void **)&n->maxsq, 64) ||
+               net_alloc(n, (void **)&n->bev_cnt, kBins * kBins * 4) || net_alloc(n, (void **)&n->bev_bad, 64);
     for (int i = 1; i <= 4 && !bad; ++i) {
         const int64_t e = B * act_hw(i) * act_hw(i) * kCh[i];
         bad = net_alloc(n, (void **)&n->a[i], e * 2) || net_alloc(n, (void **)&n->da[i], std::max<int64_t>(e, B * 4096) * 2);
@@ -514,6 +568,50 @@ extern "C" bbs_status bbs_net_forward(bbs_net *n, const uint8_t *images, int32_t
     BBS_HIP(hipGetLastError());
     BBS_HIP(hipMemcpyAsync(logits, n->logits, (size_t)batch * kOut * 4, hipMemcpyDeviceToHost, s));
     BBS_HIP(hipStreamSynchronize(s));
+    return BBS_OK;
+}
+
+// The prior of one scan: its BEV image and the forward pass, on the device
+// (d_max included), with only the 1088 logits copied back.
+extern "C" bbs_status bbs_net_prior(bbs_net *n, const float *scan_xyz, int64_t k, int32_t scan_on_device,
+                                    float *logits)
+{
+    if (!n || !scan_xyz || !logits || k < 1) return fail(BBS_ERR_INVALID_ARG, "bbs_net_prior: bad arguments");
+    hipStream_t s = n->own;
+    const float *dev = scan_xyz;
+    if (!scan_on_device) {
+        if (n->scan_cap < k) {
+            void *q = nullptr;
+            if (alloc_dev(&q, (size_t)k * 12)) return BBS_ERR_OOM;
+            if (n->scan) {
+                n->owned.erase(std::find(n->owned.begin(), n->owned.end(), (void *)n->scan));
+                (void)hipFree(n->scan);
+            }
+            n->owned.push_back(q);
+            n->scan = static_cast<float *>(q);
+            n->scan_cap = k;
+        }
+        BBS_HIP(hipMemcpyAsync(n->scan, scan_xyz, (size_t)k * 12, hipMemcpyHostToDevice, s));
+        dev = n->scan;
+    }
+    BBS_HIP(hipMemsetAsync(n->maxsq, 0, 8, s));
+    BBS_HIP(hipMemsetAsync(n->bev_cnt, 0, kBins * kBins * 4, s));
+    BBS_HIP(hipMemsetAsync(n->bev_bad, 0, 4, s));
+    const int grid = (int)std::min<int64_t>((k + 255) / 256, 1024);
+    k_bev_maxsq<<<grid, 256, 0, s>>>(dev, k, n->maxsq);
+    k_bev_count_dev<<<grid, 256, 0, s>>>(dev, k, n->maxsq, n->bev_cnt, n->bev_bad);
+    uint8_t *img = reinterpret_cast<uint8_t *>(n->da[1]);   // as load_images stages host images
+    k_bev_pack<<<kBins * kBins / 256, 256, 0, s>>>(n->bev_cnt, img);
+    BBS_HIP(hipGetLastError());
+    bbs_status st = load_images(n, img, 1, 1, s);
+    if (st) return st;
+    forward(n, 1, s);
+    BBS_HIP(hipGetLastError());
+    int32_t bad = 0;
+    BBS_HIP(hipMemcpyAsync(logits, n->logits, kOut * 4, hipMemcpyDeviceToHost, s));
+    BBS_HIP(hipMemcpyAsync(&bad, n->bev_bad, 4, hipMemcpyDeviceToHost, s));
+    BBS_HIP(hipStreamSynchronize(s));
+    if (bad) return fail(BBS_ERR_INVALID_ARG, "bbs_net_prior: scan range must be finite and > 0");
     return BBS_OK;
 }
 

@@ -36,6 +36,8 @@ def _bind():
     L.bbs_net_train_step.restype = C.c_int
     L.bbs_bev_image.argtypes = [P, I64, I32, P]
     L.bbs_bev_image.restype = C.c_int
+    L.bbs_net_prior.argtypes = [P, P, I64, I32, P]
+    L.bbs_net_prior.restype = C.c_int
     L._net_bound = True
     return L
 
@@ -88,6 +90,15 @@ class Net:
         img = np.ascontiguousarray(images, np.uint8).reshape(-1, 64, 64)
         out = np.zeros((len(img), N_OUT), np.float32)
         _check(_bind().bbs_net_forward(self._h, img.ctypes.data, 0, len(img), out.ctypes.data))
+        return out
+
+    def prior(self, scan) -> np.ndarray:
+        """The 1088 logits of one scan (host array or device tensor): BEV image
+        and forward pass on the device, no host copy of the scan."""
+        ptr, k, dev, keep = _points(scan, "scan")
+        out = np.zeros(N_OUT, np.float32)
+        _check(_bind().bbs_net_prior(self._h, ptr, k, dev, out.ctypes.data))
+        del keep
         return out
 
     def train_step(self, images, yaw, xy, lr: float, weight_decay: float = 0.0, want_grads: bool = False):

@@ -87,6 +87,23 @@ def test_forward_and_gradients_match_oracle():
         assert err < 0.03, name
 
 
+def test_prior_equals_bev_image_then_forward():
+    """bbs_net_prior (BEV image and forward on the device, d_max included)
+    gives the logits of bbs_bev_image followed by bbs_net_forward, for host and
+    device scans."""
+    import torch
+    from paper_2310_10023_amd import proposal
+    say("prior")
+    flat = flatten(onet.init_params(5)).astype(np.float32)
+    net = proposal.Net(max_batch=2, params=flat)
+    scene = synth.city_scene(1000, half=120.0)
+    for seed in range(2):
+        sc = synth.scan_scene(scene, seed, 8000, z=1.8, rp_deg=3.0, n_beams=32, n_az=512, voxel=0.5)
+        want = net.forward(proposal.bev_image(sc.points)[None])[0]
+        np.testing.assert_array_equal(net.prior(sc.points), want)
+        np.testing.assert_array_equal(net.prior(torch.from_numpy(sc.points).cuda()), want)
+
+
 def test_training_overfits_a_batch():
     from paper_2310_10023_amd import proposal
     say("overfit")
@@ -104,3 +121,35 @@ def test_training_overfits_a_batch():
     z = gnet.forward(imgs)
     acc = np.mean(np.argmax(z[:, :64], axis=1) == yaw)
     assert acc > 0.9
+
+
+def test_adamw_step_matches_oracle():
+    """One optimiser step on the device against the oracle's AdamW applied to
+    the device's own gradients at the same parameters (so only the optimiser
+    is compared): moments, bias correction and decoupled weight decay."""
+    from paper_2310_10023_amd import proposal
+    say("adamw")
+    rng = np.random.default_rng(3)
+    flat = flatten(onet.init_params(11)).astype(np.float32)
+    imgs = random_images(rng, 4)
+    yaw = rng.integers(0, 64, size=4)
+    xy = rng.integers(0, 1024, size=4)
+    gnet = proposal.Net(max_batch=8, params=flat)
+    _, grads = gnet.train_step(imgs, yaw, xy, lr=-1.0, want_grads=True)
+    lr, wd = 1e-3, 0.05
+    for step in (1, 2):
+        before = gnet.get_params().astype(np.float64) if step > 1 else flat.astype(np.float64)
+        if step == 1:
+            gnet.set_params(flat)                      # fresh optimiser state
+            moments = {}
+        _, g = gnet.train_step(imgs, yaw, xy, lr=-1.0, want_grads=True)
+        gnet.train_step(imgs, yaw, xy, lr=lr, weight_decay=wd)
+        got = gnet.get_params().astype(np.float64)
+        want = flatten(onet.adamw_step(unflatten(before), moments, unflatten(g.astype(np.float64)), step, lr, wd))
+        # float32 arithmetic against float64, and gradients that may differ in
+        # the last bits between the two passes (atomic summation order): an
+        # update is about lr in size, so compare to a fraction of it
+        err = np.abs(got - want)
+        bad = err > 1e-6 * np.maximum(1.0, np.abs(want)) + 0.02 * lr
+        assert bad.mean() < 1e-3, (step, int(bad.sum()), float(err.max()))
+

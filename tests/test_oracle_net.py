@@ -104,3 +104,28 @@ def test_input_table():
     t = net.input_table()
     assert t[0] == 0.0 and t[1] == 0.125 and t[3] == 0.25 and t[255] == 1.0
     assert np.all(np.diff(t) >= 0)
+
+
+def test_adamw_first_steps_closed_form():
+    """Pins of the oracle's AdamW: on the first step the bias-corrected moments
+    are g and g^2, so each parameter moves by lr g / (|g| + eps) after the
+    decoupled decay p (1 - lr wd) (weights only); a constant gradient keeps
+    that size on the second step."""
+    rng = np.random.default_rng(0)
+    shapes = net.param_shapes()
+    p0 = {n: rng.normal(size=shapes[n]) for n in net.PARAM_NAMES}
+    g = {n: rng.normal(size=shapes[n]) for n in net.PARAM_NAMES}
+    lr, wd, eps = 1e-2, 0.1, 1e-8
+    mom = {}
+    p1 = net.adamw_step(p0, mom, g, 1, lr, wd, eps=eps)
+    for n in net.PARAM_NAMES:
+        decay = (1 - lr * wd) if n.endswith("w") else 1.0
+        np.testing.assert_allclose(p1[n], p0[n] * decay - lr * g[n] / (np.abs(g[n]) + eps), rtol=1e-12, atol=1e-15)
+        m, v = mom[n]
+        np.testing.assert_allclose(m, 0.1 * g[n], rtol=1e-12)
+        np.testing.assert_allclose(v, 0.001 * g[n] ** 2, rtol=1e-12)
+    p2 = net.adamw_step(p1, mom, g, 2, lr, wd, eps=eps)
+    for n in net.PARAM_NAMES:
+        decay = (1 - lr * wd) if n.endswith("w") else 1.0
+        np.testing.assert_allclose(p2[n], p1[n] * decay - lr * g[n] / (np.abs(g[n]) + eps), rtol=1e-9, atol=1e-12)
+
