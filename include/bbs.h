@@ -356,6 +356,55 @@ bbs_status bbs_autotune(const bbs_map *map, const bbs_query *queries, int64_t n,
  */
 bbs_status bbs_bandwidth_probe(int32_t kind, int64_t table_bytes, int64_t loads, double *gbs, double *ms);
 
+/*
+ * Scan preprocessing, the step before the search: alignment with the measured
+ * gravity direction (Sec. III-A assumes the scan roughly aligned with gravity;
+ * Sec. IV-B aligns each scan with the IMU's average acceleration), then the
+ * voxel-grid filter that brings scans to about 1,000 points (Sec. IV).
+ *   gravity        accelerometer reading in the scan frame (points up when the
+ *                  sensor rests); all zero: no alignment.  The scan is rotated
+ *                  by the smallest rotation taking g / |g| to +z (yaw is left
+ *                  free): with a = g / |g| and k = 1 / (1 + a_z),
+ *                  R = [[1 - k a_x a_x, -k a_x a_y, -a_x], [-k a_x a_y,
+ *                  1 - k a_y a_y, -a_y], [a_x, a_y, a_z]] formed in double and
+ *                  rounded to float (diag(1, -1, -1) when 1 + a_z < 1e-9);
+ *                  each coordinate is (R_i0 x + R_i1 y) + R_i2 z in float32
+ *   leaf           voxel edge in m, 0 (no filter) or at least 2^-10.  A point's
+ *                  voxel is floor(float32(p / leaf)) per axis; each occupied
+ *                  voxel becomes the mean of its points, summed exactly as
+ *                  integers in units of 2^-24 m (so independent of order) and
+ *                  rounded once to float; voxels come out in the order of their
+ *                  first point.  Coordinates must be finite and below 1024 m.
+ *   target_points  > 0: the leaf is chosen instead, by 24 bisection steps in
+ *                  float on [2^-10, max(2 * extent, 1)] m (extent: the largest
+ *                  per-axis max - min after alignment): a voxel count above the
+ *                  target moves the lower end up, otherwise the upper end
+ *                  down; the final upper end is the leaf
+ */
+typedef struct bbs_preprocess_options {
+    float gravity[3];
+    float leaf;
+    int64_t target_points;
+} bbs_preprocess_options;
+
+/*
+ * Align and filter one scan (see bbs_preprocess_options).
+ *   xyz, n         n x 3 float32 points (x, y, z), n < 2^31; host memory if
+ *                  on_device is 0, device memory otherwise
+ *   out_xyz        out_cap x 3 float32 points on the same side as xyz
+ *                  (caller-allocated; out_cap = n always suffices)
+ *   out_n          receives the number of output points; when it exceeds
+ *                  out_cap the call writes no points and returns
+ *                  BBS_ERR_INVALID_ARG with *out_n set
+ *   leaf_used      NULL or receives the leaf of the filter (0: none)
+ *   stream         hipStream_t or NULL; the call returns after the stream has
+ *                  finished its work
+ * Allocates its device scratch (about 40 bytes per point) for the duration of
+ * the call.
+ */
+bbs_status bbs_preprocess_scan(const float *xyz, int64_t n, int32_t on_device, const bbs_preprocess_options *opt,
+                               float *out_xyz, int64_t out_cap, int64_t *out_n, float *leaf_used, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -15,7 +15,7 @@ import os
 import numpy as np
 
 __all__ = ["LibraryMissing", "BbsError", "Map", "Workspace", "localize", "localize_noalloc", "score_nodes", "serve", "lib",
-           "library_path", "EXPORTED_SYMBOLS"]
+           "library_path", "preprocess_scan", "EXPORTED_SYMBOLS"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "_lib", "libbbs.so")
@@ -26,7 +26,7 @@ EXPORTED_SYMBOLS = (
     "bbs_map_layout", "bbs_map_dump_level", "bbs_map_contains", "bbs_workspace_create", "bbs_workspace_free", "bbs_localize", "bbs_localize_noalloc",
     "bbs_score_nodes", "bbs_serve", "bbs_net_param_count", "bbs_net_create", "bbs_net_free", "bbs_net_set_params",
     "bbs_net_get_params", "bbs_net_forward", "bbs_net_prior", "bbs_net_train_step", "bbs_bev_image", "bbs_autotune",
-    "bbs_bandwidth_probe",
+    "bbs_bandwidth_probe", "bbs_preprocess_scan",
 )
 
 STRATEGIES = {"best_first": 0, "depth_first": 1}
@@ -81,6 +81,10 @@ class Result(C.Structure):
 
 class TuneEntry(C.Structure):
     _fields_ = [("batch_size", C.c_int32), ("score_items", C.c_int32), ("ms", C.c_double)]
+
+
+class PreprocessOptions(C.Structure):
+    _fields_ = [("gravity", C.c_float * 3), ("leaf", C.c_float), ("target_points", C.c_int64)]
 
 
 class Query(C.Structure):
@@ -142,6 +146,9 @@ def lib():
         L.bbs_autotune.restype = C.c_int
         L.bbs_bandwidth_probe.argtypes = [I32, I64, I64, C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.bbs_bandwidth_probe.restype = C.c_int
+        L.bbs_preprocess_scan.argtypes = [P, I64, I32, C.POINTER(PreprocessOptions), P, I64, C.POINTER(I64),
+                                          C.POINTER(F), P]
+        L.bbs_preprocess_scan.restype = C.c_int
         _lib = L
     return _lib
 
@@ -418,3 +425,28 @@ def bandwidth_probe(kind: str, table_bytes: int, loads: int = 1 << 26) -> dict:
     _check(lib().bbs_bandwidth_probe(k, int(table_bytes), int(loads), C.byref(gbs), C.byref(ms)))
     return {"kind": kind, "gbs": gbs.value, "ms": ms.value, "table_bytes": int(table_bytes),
             "loads": int(loads) if k == 1 else None}
+
+
+def preprocess_scan(points, gravity=None, leaf: float = 0.0, target_points: int = 0, stream=None):
+    """Gravity alignment and voxel-grid filter of one scan (bbs_preprocess_scan).
+    `points`: an (n, 3) float32 numpy array or device tensor; the result is
+    of the same kind.  Returns (points, leaf used or 0.0)."""
+    ptr, n, dev, keep = _points(points, "points")
+    opt = PreprocessOptions()
+    if gravity is not None:
+        for i, v in enumerate(np.asarray(gravity, np.float32).reshape(3)):
+            opt.gravity[i] = float(v)
+    opt.leaf = float(leaf)
+    opt.target_points = int(target_points)
+    out_n, used = C.c_int64(), C.c_float()
+    if dev:
+        import torch
+        out = torch.empty((max(n, 1), 3), dtype=torch.float32, device=keep.device)
+        optr = out.data_ptr()
+    else:
+        out = np.empty((max(n, 1), 3), np.float32)
+        optr = out.ctypes.data
+    _check(lib().bbs_preprocess_scan(ptr, n, dev, C.byref(opt), optr, n, C.byref(out_n), C.byref(used),
+                                      C.c_void_p(_stream(stream))))
+    del keep
+    return out[:out_n.value], float(used.value)
