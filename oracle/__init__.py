@@ -52,7 +52,8 @@ class Grid(C.Structure):
                 ("dmax", C.c_double), ("delta", C.c_double * MAX_LEVELS),
                 ("n", (C.c_int32 * MAX_LEVELS) * 3), ("dprime", (C.c_double * MAX_LEVELS) * 3),
                 ("a", (C.c_int32 * MAX_LEVELS) * 3), ("wmin", C.c_double * 3), ("wmax", C.c_double * 3),
-                ("lo", C.c_int32 * 3), ("hi", C.c_int32 * 3), ("tmin", C.c_double * 3), ("tmax", C.c_double * 3)]
+                ("lo", C.c_int32 * 3), ("hi", C.c_int32 * 3), ("tmin", C.c_double * 3), ("tmax", C.c_double * 3),
+                ("rot_exact", C.c_int32), ("pad", C.c_int32)]
 
 
 class Result(C.Structure):
@@ -86,6 +87,11 @@ def lib():
         P, I32, I64, F = C.c_void_p, C.c_int32, C.c_int64, C.c_float
         L.orc_build_map.argtypes = [P, I64, F, I32, I32, C.POINTER(P)]
         L.orc_build_map.restype = C.c_int
+        L.orc_build_map_margins.argtypes = [P, I64, F, I32, I32, P, C.POINTER(P)]
+        L.orc_build_map_margins.restype = C.c_int
+        L.orc_map_contains_rot.argtypes = [P, I32, I32, I32, I32]
+        L.orc_map_contains_rot.restype = I32
+        L.orc_rotation_margins.argtypes = [C.POINTER(Grid), P]
         L.orc_free_map.argtypes = [P]
         L.orc_map_level_size.argtypes = [P, I32]
         L.orc_map_level_size.restype = I64
@@ -133,15 +139,23 @@ class OracleError(RuntimeError):
 class Map:
     """The dilated multi-resolution voxel sets D_0 .. D_levels (Sec. III-C)."""
 
-    def __init__(self, points, r: float, levels: int, dilate_leaf: bool = True):
+    def __init__(self, points, r: float, levels: int, dilate_leaf: bool = True, margins=None):
+        """margins: None, or levels + 1 ints ([0] unused); M_l > 0 also builds
+        D_l grown by the box [-M_l, M_l]^3, the table of the exact rotational
+        bound at level l."""
         pts = _f32(points).reshape(-1, 3)
         h = C.c_void_p()
-        rc = lib().orc_build_map(pts.ctypes.data, len(pts), float(r), int(levels), int(dilate_leaf), C.byref(h))
+        mg = None if margins is None else _i32(margins).reshape(-1)
+        if mg is not None and len(mg) != int(levels) + 1:
+            raise ValueError("margins needs levels + 1 entries")
+        rc = lib().orc_build_map_margins(pts.ctypes.data, len(pts), float(r), int(levels), int(dilate_leaf),
+                                         None if mg is None else mg.ctypes.data, C.byref(h))
         if rc != 0:
             raise OracleError(f"orc_build_map failed ({rc})")
         self._h = h
         self.r = float(np.float32(r))
         self.levels = int(levels)
+        self.margins = [0] * (int(levels) + 1) if mg is None else [int(v) for v in mg]
 
     def __del__(self):
         if getattr(self, "_h", None) and _lib is not None:
@@ -164,12 +178,22 @@ class Map:
     def contains(self, l: int, x: int, y: int, z: int) -> bool:
         return bool(lib().orc_map_contains(self._h, l, int(x), int(y), int(z)))
 
+    def contains_grown(self, l: int, x: int, y: int, z: int) -> bool:
+        """Membership in the grown table of level l >= 1 (rot_margin > 0)."""
+        v = lib().orc_map_contains_rot(self._h, l, int(x), int(y), int(z))
+        if v < 0:
+            raise OracleError("no grown table at this level")
+        return bool(v)
+
 
 class Search:
     """A scan plus its search ranges: the angular/translational grid and the
     oracle's score, branching and search."""
 
-    def __init__(self, omap: Map, scan, rmin, rmax, translation_only: bool = False):
+    def __init__(self, omap: Map, scan, rmin, rmax, translation_only: bool = False, rot_exact: bool = False):
+        """rot_exact: inner nodes are scored against the map's grown tables
+        (the exact rotational bound); the map's rot_margin must be at least
+        margin_needed()."""
         self.map = omap
         self.scan = _f32(scan).reshape(-1, 3)
         self.rmin = _f32(rmin)
@@ -179,6 +203,16 @@ class Search:
                              omap.r, omap.levels, int(translation_only), C.byref(self.grid))
         if rc != 0:
             raise OracleError(f"orc_setup failed ({rc})")
+        self.grid.rot_exact = int(bool(rot_exact))
+        if rot_exact and any(e > m for e, m in zip(self.margins_needed(), omap.margins)):
+            raise OracleError(f"the map's rotation margins {omap.margins} are below the {self.margins_needed()} "
+                              f"this search needs")
+
+    def margins_needed(self) -> list:
+        """Per-level box margins e_l of the exact rotational bound ([0] = 0)."""
+        out = np.zeros(MAX_LEVELS, dtype=np.int32)
+        lib().orc_rotation_margins(C.byref(self.grid), out.ctypes.data)
+        return [int(v) for v in out[: self.map.levels + 1]]
 
     # grid accessors
     @property

@@ -78,12 +78,18 @@ typedef struct {
     int32_t dilate_leaf;               /* 1: level 0 is dilated like every other level */
     int64_t n_keys[ORC_MAX_LEVELS];
     int64_t *keys[ORC_MAX_LEVELS];     /* sorted set D_l of packed voxel keys */
+    int32_t margin[ORC_MAX_LEVELS];    /* M_l > 0: keys_rot[l] exists (l >= 1) */
+    int64_t n_rot[ORC_MAX_LEVELS];
+    int64_t *keys_rot[ORC_MAX_LEVELS]; /* D_l grown by the box [-M_l, M_l]^3 (exact rotational bound) */
 } orc_map;
 
 void orc_free_map(orc_map *m)
 {
     if (!m) return;
-    for (int l = 0; l < ORC_MAX_LEVELS; ++l) free(m->keys[l]);
+    for (int l = 0; l < ORC_MAX_LEVELS; ++l) {
+        free(m->keys[l]);
+        free(m->keys_rot[l]);
+    }
     free(m);
 }
 
@@ -97,17 +103,32 @@ void orc_free_map(orc_map *m)
  * j in {0,1}^3 (V_add, Sec. III-C), at every level (level 0 too unless
  * dilate_leaf is 0).
  */
-int orc_build_map(const float *xyz, int64_t n, float r, int32_t levels, int32_t dilate_leaf,
-                  orc_map **out)
+/*
+ * With margins (NULL, or levels + 1 entries of which [0] is unused), every
+ * level l >= 1 with M_l = margins[l] > 0 also gets D_l grown by the box
+ * [-M_l, M_l]^3, i.e. every occupied voxel contributes v - j for j in
+ * [-M_l, 1 + M_l]^3.  These are the tables of the exact rotational bound (see
+ * orc_rotation_margins).
+ */
+int orc_build_map_margins(const float *xyz, int64_t n, float r, int32_t levels, int32_t dilate_leaf,
+                          const int32_t *margins, orc_map **out)
 {
     *out = NULL;
     if (!xyz || n < 1 || !(r > 0.0f) || !isfinite(r) || levels < 0 || levels >= ORC_MAX_LEVELS)
         return ORC_ERR_ARG;
+    int32_t rot_margin = 0;    /* the largest margin, for the scratch size */
+    if (margins)
+        for (int l = 1; l <= levels; ++l) {
+            if (margins[l] < 0 || margins[l] > 8) return ORC_ERR_ARG;
+            if (margins[l] > rot_margin) rot_margin = margins[l];
+        }
     orc_map *m = (orc_map *)calloc(1, sizeof(orc_map));
     if (!m) return ORC_ERR_OOM;
     m->r = r;
     m->levels = levels;
     m->dilate_leaf = dilate_leaf;
+    if (margins)
+        for (int l = 1; l <= levels; ++l) m->margin[l] = margins[l];
     /* occupied level-0 voxels, as a set: duplicates change no D_l */
     int64_t *occ = (int64_t *)malloc((size_t)n * sizeof(int64_t));
     if (!occ) { orc_free_map(m); return ORC_ERR_OOM; }
@@ -126,7 +147,9 @@ int orc_build_map(const float *xyz, int64_t n, float r, int32_t levels, int32_t 
         occ[i] = pack_key(v[0], v[1], v[2]);
     }
     int64_t n_occ = sort_unique(occ, n);
-    int64_t *buf = (int64_t *)malloc((size_t)n_occ * 8 * sizeof(int64_t));
+    const int64_t span = 2 + 2 * (int64_t)rot_margin;     /* offsets per axis of the grown tables */
+    const int64_t per = span * span * span > 8 ? span * span * span : 8;
+    int64_t *buf = (int64_t *)malloc((size_t)n_occ * per * sizeof(int64_t));
     if (!buf) { free(occ); orc_free_map(m); return ORC_ERR_OOM; }
     for (int l = 0; l <= levels; ++l) {
         int dilate = (l > 0) || dilate_leaf;
@@ -146,11 +169,34 @@ int orc_build_map(const float *xyz, int64_t n, float r, int32_t levels, int32_t 
         if (!m->keys[l]) { free(occ); free(buf); orc_free_map(m); return ORC_ERR_OOM; }
         memcpy(m->keys[l], buf, (size_t)cnt * sizeof(int64_t));
         m->n_keys[l] = cnt;
+        if (l > 0 && m->margin[l] > 0) {
+            const int32_t M = m->margin[l];
+            cnt = 0;
+            for (int64_t i = 0; i < n_occ; ++i) {
+                int32_t vx = floor_div_pow2((int32_t)((occ[i] >> 42) & 0x1FFFFF) - ORC_KEY_BIAS, l);
+                int32_t vy = floor_div_pow2((int32_t)((occ[i] >> 21) & 0x1FFFFF) - ORC_KEY_BIAS, l);
+                int32_t vz = floor_div_pow2((int32_t)(occ[i] & 0x1FFFFF) - ORC_KEY_BIAS, l);
+                for (int jx = -M; jx <= 1 + M; ++jx)
+                    for (int jy = -M; jy <= 1 + M; ++jy)
+                        for (int jz = -M; jz <= 1 + M; ++jz)
+                            buf[cnt++] = pack_key(vx - jx, vy - jy, vz - jz);
+            }
+            cnt = sort_unique(buf, cnt);
+            m->keys_rot[l] = (int64_t *)malloc((size_t)(cnt ? cnt : 1) * sizeof(int64_t));
+            if (!m->keys_rot[l]) { free(occ); free(buf); orc_free_map(m); return ORC_ERR_OOM; }
+            memcpy(m->keys_rot[l], buf, (size_t)cnt * sizeof(int64_t));
+            m->n_rot[l] = cnt;
+        }
     }
     free(occ);
     free(buf);
     *out = m;
     return ORC_OK;
+}
+
+int orc_build_map(const float *xyz, int64_t n, float r, int32_t levels, int32_t dilate_leaf, orc_map **out)
+{
+    return orc_build_map_margins(xyz, n, r, levels, dilate_leaf, NULL, out);
 }
 
 int64_t orc_map_level_size(const orc_map *m, int32_t l)
@@ -173,19 +219,30 @@ int64_t orc_map_level_keys(const orc_map *m, int32_t l, int32_t *out_xyz, int64_
     return m->n_keys[l];
 }
 
-/* H^l(v): binary occupancy of voxel v in the dilated level-l map (Sec. III-C). */
-int32_t orc_map_contains(const orc_map *m, int32_t l, int32_t x, int32_t y, int32_t z)
+static int32_t set_contains(const int64_t *k, int64_t n, int32_t x, int32_t y, int32_t z)
 {
     if (!key_in_range(x, y, z)) return 0;
     int64_t key = pack_key(x, y, z);
-    const int64_t *k = m->keys[l];
-    int64_t lo = 0, hi = m->n_keys[l];
+    int64_t lo = 0, hi = n;
     while (lo < hi) {
         int64_t mid = lo + (hi - lo) / 2;
         if (k[mid] < key) lo = mid + 1;
         else hi = mid;
     }
-    return lo < m->n_keys[l] && k[lo] == key;
+    return lo < n && k[lo] == key;
+}
+
+/* H^l(v): binary occupancy of voxel v in the dilated level-l map (Sec. III-C). */
+int32_t orc_map_contains(const orc_map *m, int32_t l, int32_t x, int32_t y, int32_t z)
+{
+    return set_contains(m->keys[l], m->n_keys[l], x, y, z);
+}
+
+/* The same in the grown table of the exact rotational bound (l >= 1). */
+int32_t orc_map_contains_rot(const orc_map *m, int32_t l, int32_t x, int32_t y, int32_t z)
+{
+    if (l < 1 || !m->keys_rot[l]) return -1;
+    return set_contains(m->keys_rot[l], m->n_rot[l], x, y, z);
 }
 
 /* ------------------------------------------------------------------ search grid */
@@ -202,6 +259,8 @@ typedef struct {
     double wmin[3], wmax[3];               /* angular ranges */
     int32_t lo[3], hi[3];                  /* leaf translation index range per axis */
     double tmin[3], tmax[3];               /* translation ranges [m] */
+    int32_t rot_exact;                     /* 1: inner nodes are scored against the grown tables */
+    int32_t pad;
 } orc_grid;
 
 /*
@@ -286,6 +345,62 @@ static double cell_angle(const orc_grid *g, int ax, int32_t c, int l)
 }
 
 /*
+ * Exact rotational bound (not in the paper, which notes that its bound is not
+ * strictly exact under rotation, Sec. III-D).  A level-l node is scored at the
+ * centre rotation of its angular cell; a leaf below it has a rotation whose
+ * angles differ from that centre by at most dev_ax per axis (the largest
+ * distance between the node's cell centre and the centres of the leaf cells
+ * [c P, (c + 1) P - 1], P the product of the divisions a of levels 1..l).
+ * Since Rz Ry Rx changes by at most the sum of the three angle changes in
+ * operator norm, a scan point moves by at most disp = d_max (dev_roll +
+ * dev_pitch + dev_yaw), i.e. its level-0 voxel by at most
+ * D = ceil((disp + slack) / r) per axis (slack = 1e-5 d_max + 1e-6 m covers
+ * the float transform) and its level-l voxel by at most e_l = ceil(D / 2^l).
+ * The node scored with the leaf's own rotation lands in D_l whenever the leaf
+ * hits (the nesting of the translation-only case), so scoring the node against
+ * D_l grown by [-e_l, e_l]^3 bounds every leaf below it.  Writes e_l to
+ * out[l] for l = 1..levels (out[0] = 0; all 0 in translation-only mode, where
+ * every node carries a leaf rotation).
+ */
+void orc_rotation_margins(const orc_grid *g, int32_t *out)
+{
+    for (int l = 0; l <= g->levels; ++l) out[l] = 0;
+    if (g->translation_only) return;
+    for (int l = 1; l <= g->levels; ++l) {
+        double theta = 0.0;
+        for (int ax = 0; ax < 3; ++ax) {
+            int64_t P = 1;
+            for (int j = 1; j <= l; ++j) P *= g->a[ax][j];
+            double dev = 0.0;
+            for (int32_t c = 0; c < g->n[ax][l]; ++c) {
+                int64_t i0 = (int64_t)c * P, i1 = (int64_t)(c + 1) * P - 1;
+                if (i0 > g->n[ax][0] - 1) break;
+                if (i1 > g->n[ax][0] - 1) i1 = g->n[ax][0] - 1;
+                double centre = cell_angle(g, ax, c, l);
+                double d0 = fabs(cell_angle(g, ax, (int32_t)i0, 0) - centre);
+                double d1 = fabs(cell_angle(g, ax, (int32_t)i1, 0) - centre);
+                if (d0 > dev) dev = d0;
+                if (d1 > dev) dev = d1;
+            }
+            theta += dev;
+        }
+        double disp = g->dmax * theta;
+        double D = ceil((disp + 1e-5 * g->dmax + 1e-6) / (double)g->r);
+        out[l] = (int32_t)ceil(D / ldexp(1.0, l));
+    }
+}
+
+/* 1 when the map's grown tables cover every level's margin. */
+static int margins_cover(const orc_map *m, const orc_grid *g)
+{
+    int32_t need[ORC_MAX_LEVELS];
+    orc_rotation_margins(g, need);
+    for (int l = 1; l <= g->levels; ++l)
+        if (need[l] > 0 && (m->margin[l] < need[l] || !m->keys_rot[l])) return 0;
+    return 1;
+}
+
+/*
  * Rotation of the pose's Euler angles (roll alpha, pitch beta, yaw gamma),
  * Sec. III-A.  Reading: R = Rz(gamma) Ry(beta) Rx(alpha), entries formed in
  * double with the products evaluated left to right, then rounded to float.
@@ -342,6 +457,7 @@ int32_t orc_score(const orc_map *m, const float *scan, int64_t k, const orc_grid
     orc_rotation(g, level, ia, ib, ig, R);
     const float r = g->r;
     int32_t count = 0;
+    const int grown = g->rot_exact && !g->translation_only && level > 0 && m->keys_rot[level];
     for (int64_t i = 0; i < k; ++i) {
         float sx = scan[3 * i], sy = scan[3 * i + 1], sz = scan[3 * i + 2];
         int32_t key[3];
@@ -356,7 +472,8 @@ int32_t orc_score(const orc_map *m, const float *scan, int64_t k, const orc_grid
         int32_t vx = floor_div_pow2(key[0], level) + x;
         int32_t vy = floor_div_pow2(key[1], level) + y;
         int32_t vz = floor_div_pow2(key[2], level) + z;
-        count += orc_map_contains(m, level, vx, vy, vz);
+        if (grown) count += set_contains(m->keys_rot[level], m->n_rot[level], vx, vy, vz);
+        else count += orc_map_contains(m, level, vx, vy, vz);
     }
     return count;
 }
@@ -748,6 +865,7 @@ int orc_localize(const orc_map *m, const float *scan, int64_t k, const orc_grid 
     memset(res, 0, sizeof(*res));
     if (!m || !scan || k < 1 || batch < 1 || g->levels != m->levels) return ORC_ERR_ARG;
     if (order != ORC_BEST_FIRST && order != ORC_DEPTH_FIRST) return ORC_ERR_ARG;
+    if (g->rot_exact && !margins_cover(m, g)) return ORC_ERR_ARG;
     const int L = g->levels;
     node_vec heap = {0}, pending = {0};
     int64_t seq = 0;
