@@ -89,7 +89,14 @@ typedef struct {
                                  ascending); 1 depth first (the order of Alg. 1, Table I
                                  "DFS": level ascending, then score descending); first in
                                  first out among equal keys, same batching and pruning */
-    int32_t reserved2;
+    int32_t rot_exact;        /* 1: exact rotational bound (not in the paper, whose bound is not
+                                 strictly exact under rotation, Sec. III-D): nodes of level
+                                 l >= 1 are scored against D_l grown by the box margin e_l of
+                                 bbs_rotation_margins, so every node bounds every leaf below
+                                 it and the result is the full search's optimum (largest
+                                 score, lexicographically smallest leaf), whatever the order.
+                                 The map must hold grown tables with margins >= e_l
+                                 (bbs_build_map_margins), else INVALID_ARG */
 } bbs_options;
 
 typedef struct {
@@ -154,6 +161,32 @@ const char *bbs_last_error(void);
  */
 bbs_status bbs_build_map(const float *xyz, int64_t n, int32_t xyz_on_device, float min_res, int32_t levels,
                          int32_t dilate_leaf, void *stream, bbs_map **out);
+
+/*
+ * bbs_build_map, plus the grown tables of the exact rotational bound (option
+ * rot_exact): for every level l >= 1 with margins[l] = M > 0, the set D_l
+ * grown by the box [-M, M]^3 (every occupied voxel v marks v - j for j in
+ * [-M, 1 + M]^3), in the same layout.
+ *   margins         NULL (no grown tables) or levels + 1 entries in [0, 8];
+ *                   margins[0] is ignored (leaves are scored exactly)
+ */
+bbs_status bbs_build_map_margins(const float *xyz, int64_t n, int32_t xyz_on_device, float min_res,
+                                 int32_t levels, int32_t dilate_leaf, const int32_t *margins, void *stream,
+                                 bbs_map **out);
+
+/*
+ * The box margins e_l that the exact rotational bound needs (option
+ * rot_exact) for scans of largest range d_max searched over `range` on a map
+ * of min_res and levels.  A level-l node is scored at the centre rotation of
+ * its angular cell; the leaves below it lie within dev_ax of that centre on
+ * each axis, so a scan point moves by at most d_max (dev_roll + dev_pitch +
+ * dev_yaw), i.e. by D = ceil((that + 1e-5 d_max + 1e-6) / min_res) level-0
+ * cells, and e_l = ceil(D / 2^l).  margins: levels + 1 outputs, [0] = 0.
+ * A scan of smaller range may need other margins (the angular grid changes
+ * with d_max); bbs_localize checks the scan's own.
+ */
+bbs_status bbs_rotation_margins(float min_res, int32_t levels, double d_max, const bbs_search_range *range,
+                                int32_t *margins);
 
 /* Release a map (NULL is ignored). */
 void bbs_free_map(bbs_map *map);
@@ -241,9 +274,11 @@ bbs_status bbs_localize_noalloc(const bbs_map *map, const float *scan_xyz, int64
  * The angular grid is the one bbs_localize derives from scan and range.
  * Nodes outside the search set are scored all the same (their cell angles
  * are extrapolated from the grid).
+ *   mode            bit 0: translation-only grid (as option translation_only);
+ *                   bit 1: exact rotational bound (as option rot_exact)
  */
 bbs_status bbs_score_nodes(const bbs_map *map, const float *scan_xyz, int64_t k, const bbs_search_range *range,
-                           int32_t translation_only, const int32_t *nodes, int64_t n, int32_t *scores);
+                           int32_t mode, const int32_t *nodes, int64_t n, int32_t *scores);
 
 /* One query of a stream. */
 typedef struct {

@@ -15,7 +15,7 @@ import os
 import numpy as np
 
 __all__ = ["LibraryMissing", "BbsError", "Map", "Workspace", "localize", "localize_noalloc", "score_nodes", "serve", "lib",
-           "library_path", "preprocess_scan", "EXPORTED_SYMBOLS"]
+           "library_path", "preprocess_scan", "rotation_margins", "EXPORTED_SYMBOLS"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "_lib", "libbbs.so")
@@ -26,7 +26,7 @@ EXPORTED_SYMBOLS = (
     "bbs_map_layout", "bbs_map_dump_level", "bbs_map_contains", "bbs_workspace_create", "bbs_workspace_free", "bbs_localize", "bbs_localize_noalloc",
     "bbs_score_nodes", "bbs_serve", "bbs_net_param_count", "bbs_net_create", "bbs_net_free", "bbs_net_set_params",
     "bbs_net_get_params", "bbs_net_forward", "bbs_net_prior", "bbs_net_train_step", "bbs_bev_image", "bbs_autotune",
-    "bbs_bandwidth_probe", "bbs_preprocess_scan",
+    "bbs_bandwidth_probe", "bbs_preprocess_scan", "bbs_build_map_margins", "bbs_rotation_margins",
 )
 
 STRATEGIES = {"best_first": 0, "depth_first": 1}
@@ -51,7 +51,7 @@ class Options(C.Structure):
     _fields_ = [("batch_size", C.c_int32), ("translation_only", C.c_int32), ("profile", C.c_int32),
                 ("seed_beam", C.c_int32), ("stream", C.c_void_p), ("prior", C.c_void_p),
                 ("persistent", C.c_int32), ("score_items", C.c_int32), ("graph", C.c_int32),
-                ("hist_min_level", C.c_int32), ("strategy", C.c_int32), ("reserved2", C.c_int32)]
+                ("hist_min_level", C.c_int32), ("strategy", C.c_int32), ("rot_exact", C.c_int32)]
 
 
 class Result(C.Structure):
@@ -119,6 +119,10 @@ def lib():
         L.bbs_last_error.restype = C.c_char_p
         L.bbs_build_map.argtypes = [P, I64, I32, F, I32, I32, P, C.POINTER(P)]
         L.bbs_build_map.restype = C.c_int
+        L.bbs_build_map_margins.argtypes = [P, I64, I32, F, I32, I32, P, P, C.POINTER(P)]
+        L.bbs_build_map_margins.restype = C.c_int
+        L.bbs_rotation_margins.argtypes = [F, I32, C.c_double, C.POINTER(SearchRange), P]
+        L.bbs_rotation_margins.restype = C.c_int
         L.bbs_free_map.argtypes = [P]
         L.bbs_map_info.argtypes = [P, C.POINTER(I32), C.POINTER(F), P, P, P]
         L.bbs_map_info.restype = C.c_int
@@ -200,12 +204,19 @@ def _range(rmin, rmax):
 class Map:
     """Sparse multi-resolution voxel map (Sec. III-C) resident on the GPU."""
 
-    def __init__(self, points, min_res: float, levels: int, dilate_leaf: bool = True, stream=None):
+    def __init__(self, points, min_res: float, levels: int, dilate_leaf: bool = True, stream=None, margins=None):
+        """margins: None, or levels + 1 box margins of the grown tables that the
+        exact rotational bound (localize(rot_exact=True)) reads; see
+        rotation_margins()."""
         ptr, n, dev, keep = _points(points, "points")
         h = C.c_void_p()
-        _check(lib().bbs_build_map(ptr, n, dev, float(min_res), int(levels), int(dilate_leaf), _stream(stream),
-                                   C.byref(h)))
+        mg = None if margins is None else np.ascontiguousarray(margins, dtype=np.int32).reshape(-1)
+        if mg is not None and len(mg) != int(levels) + 1:
+            raise ValueError("margins needs levels + 1 entries")
+        _check(lib().bbs_build_map_margins(ptr, n, dev, float(min_res), int(levels), int(dilate_leaf),
+                                           None if mg is None else mg.ctypes.data, _stream(stream), C.byref(h)))
         del keep
+        self.margins = [0] * (int(levels) + 1) if mg is None else [int(v) for v in mg]
         self._h = h
         self.min_res = float(np.float32(min_res))
         self.levels = int(levels)
@@ -288,7 +299,7 @@ def localize(bmap: Map, scan, rmin, rmax, score_threshold: int, *, batch_size: i
              translation_only: bool = False, profile: int = 0, workspace: Workspace | None = None,
              stream=None, prior=None, seed_beam: int = 0, persistent: bool = False,
              score_items: int = 0, graph: bool = False, hist_min_level: int = 0,
-             strategy: str = "best_first") -> dict:
+             strategy: str = "best_first", rot_exact: bool = False) -> dict:
     """Global localization of one scan (Alg. 2 on the GPU).  Returns the result
     fields as a dict (found, score, leaf, pose, node counters, timings).
     prior: optional 1088 logits of the proposal network."""
@@ -304,6 +315,7 @@ def localize(bmap: Map, scan, rmin, rmax, score_threshold: int, *, batch_size: i
     opt.graph = int(graph)
     opt.hist_min_level = int(hist_min_level)
     opt.strategy = STRATEGIES[strategy]
+    opt.rot_exact = int(rot_exact)
     pr = None
     if prior is not None:
         pr = np.ascontiguousarray(prior, dtype=np.float32).reshape(1088)
@@ -344,14 +356,16 @@ def localize_noalloc(bmap: Map, scan, rmin, rmax, score_threshold: int, *, batch
     return res.as_dict()
 
 
-def score_nodes(bmap: Map, scan, rmin, rmax, nodes, translation_only: bool = False) -> np.ndarray:
+def score_nodes(bmap: Map, scan, rmin, rmax, nodes, translation_only: bool = False,
+                rot_exact: bool = False) -> np.ndarray:
     """Scores of arbitrary nodes (rows level, x, y, z, i_roll, i_pitch, i_yaw)
     computed by the device scoring kernel."""
     s = np.ascontiguousarray(scan, dtype=np.float32).reshape(-1, 3)
     nd = np.ascontiguousarray(nodes, dtype=np.int32).reshape(-1, 7)
     out = np.zeros(len(nd), np.int32)
     rng = _range(rmin, rmax)
-    _check(lib().bbs_score_nodes(bmap.handle, s.ctypes.data, len(s), C.byref(rng), int(translation_only),
+    _check(lib().bbs_score_nodes(bmap.handle, s.ctypes.data, len(s), C.byref(rng),
+                                 int(bool(translation_only)) | (2 if rot_exact else 0),
                                  nd.ctypes.data, len(nd), out.ctypes.data))
     return out
 
@@ -450,3 +464,12 @@ def preprocess_scan(points, gravity=None, leaf: float = 0.0, target_points: int 
                                       C.c_void_p(_stream(stream))))
     del keep
     return out[:out_n.value], float(used.value)
+
+
+def rotation_margins(min_res: float, levels: int, d_max: float, rmin, rmax) -> list:
+    """Box margins e_l ([0] = 0) that the exact rotational bound needs for
+    scans of largest range d_max over the search range (bbs_rotation_margins)."""
+    out = np.zeros(int(levels) + 1, np.int32)
+    rng = _range(rmin, rmax)
+    _check(lib().bbs_rotation_margins(float(min_res), int(levels), float(d_max), C.byref(rng), out.ctypes.data))
+    return [int(v) for v in out]

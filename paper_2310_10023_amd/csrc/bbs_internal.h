@@ -185,5 +185,10 @@ struct bbs_map {
     int64_t voxels[bbs::kMaxLevels];
     int32_t bmin[bbs::kMaxLevels][3];
     int32_t bmax[bbs::kMaxLevels][3];
+    // exact rotational bound: level l >= 1 grown by the box margin margin[l]
+    // (0: no grown table), held in the same layout by `grown` (levels >= 1)
+    int32_t margin[bbs::kMaxLevels];
+    bbs_map *grown;
     bbs::MapView view() const;
+    bbs::MapView view_exact() const;
 };

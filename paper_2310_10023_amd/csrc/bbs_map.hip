@@ -27,6 +27,7 @@ constexpr int64_t kDenseRatio = 4;              // dense grid only if its bricks
 constexpr int64_t kDenseMax = (int64_t)1 << 28; // and at most 2^28 entries (2 GiB, byte offsets < 2^31)
 constexpr int64_t kDenseAxis = 4096;            // and at most 4096 bricks along x and y
 constexpr int64_t kDenseZY = (int64_t)1 << 24;  // and z voxels x y bricks <= 2^24 (24-bit index products)
+constexpr int32_t kMaxMargin = 8;               // box margin of a grown level table
 
 inline int grid_for(int64_t n, int threads = kThreads, int cap = 8192)
 {
@@ -146,20 +147,20 @@ __device__ inline uint32_t find_or_insert(Slot *table, uint32_t cap_mask, int32_
 }
 
 // OR every voxel of D_level into each brick that covers it.  `occ` holds the
-// distinct occupied voxels of the level (Occ_level); each marks itself and,
-// with dilation, its neighbours v - j, j in {0,1}^3.  A voxel v lies in brick
-// floor(v / 4) and, on each axis where v is a multiple of 4, also in the brick
-// below (as its fifth layer).
-__global__ void k_insert_bricks(const unsigned long long *occ, int64_t n_occ, int dilate, Slot *table,
+// distinct occupied voxels of the level (Occ_level); each marks v - j for
+// every j in [jlo, jhi]^3: j in {0} undilated, {0,1}^3 with the dilation of
+// Sec. III-C, [-M, 1 + M]^3 for the table grown by the box margin M.  A voxel
+// v lies in brick floor(v / 4) and, on each axis where v is a multiple of 4,
+// also in the brick below (as its fifth layer).
+__global__ void k_insert_bricks(const unsigned long long *occ, int64_t n_occ, int jlo, int jhi, Slot *table,
                                 uint32_t cap_mask, unsigned long long *n_bricks, int *err)
 {
-    const int jmax = dilate ? 1 : 0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_occ; i += (int64_t)gridDim.x * blockDim.x) {
         int32_t w[3];
         unpack_voxel(occ[i], w[0], w[1], w[2]);
-        for (int jx = 0; jx <= jmax; ++jx)
-            for (int jy = 0; jy <= jmax; ++jy)
-                for (int jz = 0; jz <= jmax; ++jz) {
+        for (int jx = jlo; jx <= jhi; ++jx)
+            for (int jy = jlo; jy <= jhi; ++jy)
+                for (int jz = jlo; jz <= jhi; ++jz) {
                     int32_t v[3] = {w[0] - jx, w[1] - jy, w[2] - jz};
                     int32_t b0[3];
                     int nb[3];
@@ -446,6 +447,18 @@ bbs::MapView bbs_map::view() const
     return v;
 }
 
+// The levels of the exact rotational bound: level 0 as built, every level
+// l >= 1 with a margin from the grown tables.
+bbs::MapView bbs_map::view_exact() const
+{
+    MapView v = view();
+    if (!grown) return v;
+    const MapView gv = grown->view();
+    for (int l = 1; l <= levels; ++l)
+        if (margin[l] > 0) v.lv[l] = gv.lv[l];
+    return v;
+}
+
 extern "C" void bbs_free_map(bbs_map *map)
 {
     if (!map) return;
@@ -454,11 +467,110 @@ extern "C" void bbs_free_map(bbs_map *map)
         if (map->bits[l]) (void)hipFree(map->bits[l]);
         if (map->dense[l]) (void)hipFree(map->dense[l]);
     }
+    bbs_free_map(map->grown);
     delete map;
 }
 
-extern "C" bbs_status bbs_build_map(const float *xyz, int64_t n, int32_t xyz_on_device, float min_res, int32_t levels,
-                                    int32_t dilate_leaf, void *stream, bbs_map **out)
+namespace bbs {
+namespace {
+
+// Scratch of one map build (device counters and the level's bounding box).
+struct BuildScratch {
+    DevBuf dcount, derr, dbbox, dvox;
+};
+
+// The brick table (and, where it pays, the dense column grid) of level l of
+// m from the level's occupied voxels occ, each marking v - j for j in
+// [jlo, jhi]^3.
+bbs_status build_level(bbs_map *m, int l, const unsigned long long *occ, int64_t n_occ, int jlo, int jhi,
+                       hipStream_t s, BuildScratch &B)
+{
+    const uint4 home = home_mask();
+    int err = 0;
+    const int span = jhi - jlo + 1;
+    uint64_t tmp_cap = next_pow2(std::max<uint64_t>(1024, 4 * (uint64_t)n_occ * std::max(1, span * span * span / 8)));
+    for (;;) {
+        DevBuf tmp;
+        if (alloc_dev(&tmp.p, tmp_cap * sizeof(Slot))) return BBS_ERR_OOM;
+        BBS_HIP(hipMemsetAsync(B.dcount.p, 0, 64, s));
+        BBS_HIP(hipMemsetAsync(B.derr.p, 0, 64, s));
+        k_fill_slots<<<grid_for((int64_t)tmp_cap), kThreads, 0, s>>>(tmp.as<Slot>(), tmp_cap);
+        k_insert_bricks<<<grid_for(n_occ), kThreads, 0, s>>>(occ, n_occ, jlo, jhi, tmp.as<Slot>(),
+                                                              (uint32_t)(tmp_cap - 1),
+                                                              B.dcount.as<unsigned long long>(), B.derr.as<int>());
+        BBS_HIP(hipGetLastError());
+        unsigned long long nb = 0;
+        BBS_HIP(hipMemcpyAsync(&nb, B.dcount.p, 8, hipMemcpyDeviceToHost, s));
+        BBS_HIP(hipMemcpyAsync(&err, B.derr.p, 4, hipMemcpyDeviceToHost, s));
+        BBS_HIP(hipStreamSynchronize(s));
+        if (err || nb * 2 > tmp_cap) {   // too full: grow and rebuild this level
+            if (tmp_cap >= ((uint64_t)1 << 31))
+                return fail(BBS_ERR_OOM, "bbs_build_map: brick table would exceed 2^31 slots");
+            tmp_cap *= 4;
+            continue;
+        }
+        uint64_t cap = next_pow2(std::max<uint64_t>(16, 2 * nb));
+        void *dk = nullptr, *db = nullptr;
+        if (alloc_dev(&dk, cap * sizeof(uint2)) || alloc_dev(&db, cap * sizeof(uint4))) {
+            if (dk) (void)hipFree(dk);
+            return BBS_ERR_OOM;
+        }
+        m->keys[l] = static_cast<uint2 *>(dk);
+        m->bits[l] = static_cast<uint4 *>(db);
+        m->cap[l] = cap;
+        m->bricks[l] = (int64_t)nb;
+        int bbox_init[6] = {INT_MAX, INT_MAX, INT_MAX, INT_MIN, INT_MIN, INT_MIN};
+        BBS_HIP(hipMemcpyAsync(B.dbbox.p, bbox_init, sizeof(bbox_init), hipMemcpyHostToDevice, s));
+        BBS_HIP(hipMemsetAsync(B.dvox.p, 0, 8, s));
+        k_fill_level<<<grid_for((int64_t)cap), kThreads, 0, s>>>(m->keys[l], m->bits[l], cap);
+        k_compact<<<grid_for((int64_t)tmp_cap, kThreads, 2048), kThreads, 0, s>>>(
+            tmp.as<Slot>(), tmp_cap, m->keys[l], m->bits[l], (uint32_t)(cap - 1), home, B.dbbox.as<int>(),
+            B.dvox.as<unsigned long long>(), B.derr.as<int>());
+        BBS_HIP(hipGetLastError());
+        int bbox[6];
+        unsigned long long nv = 0;
+        BBS_HIP(hipMemcpyAsync(bbox, B.dbbox.p, sizeof(bbox), hipMemcpyDeviceToHost, s));
+        BBS_HIP(hipMemcpyAsync(&nv, B.dvox.p, 8, hipMemcpyDeviceToHost, s));
+        BBS_HIP(hipMemcpyAsync(&err, B.derr.p, 4, hipMemcpyDeviceToHost, s));
+        BBS_HIP(hipStreamSynchronize(s));
+        if (err) return fail(BBS_ERR_INTERNAL, "bbs_build_map: brick compaction failed");
+        for (int a = 0; a < 3; ++a) {
+            m->bmin[l][a] = bbox[a];
+            m->bmax[l][a] = bbox[3 + a];
+        }
+        m->voxels[l] = (int64_t)nv;
+        // dense column grid when the bounding box holds at most kDenseRatio x
+        // the hash capacity in bricks and the index products stay within 24
+        // bits; one extra layer of empty entries past the box maximum on
+        // every axis is where the scoring clamps points outside the box
+        const int64_t n3[3] = {(int64_t)bbox[3] - bbox[0] + 2, (int64_t)bbox[4] - bbox[1] + 2,
+                               4 * ((int64_t)bbox[5] - bbox[2] + 1) + 1};
+        const int64_t dn = n3[0] * n3[1] * n3[2];
+        const int64_t box_bricks = n3[0] * n3[1] * ((int64_t)bbox[5] - bbox[2] + 2);
+        const bool axes_ok = n3[0] <= kDenseAxis && n3[1] <= kDenseAxis && n3[2] * n3[1] <= kDenseZY;
+        if (axes_ok && box_bricks <= kDenseRatio * (int64_t)cap && dn <= kDenseMax) {
+            void *dd = nullptr;
+            if (alloc_dev(&dd, (size_t)dn * sizeof(uint2))) return BBS_ERR_OOM;
+            m->dense[l] = static_cast<uint2 *>(dd);
+            m->dense_n[l] = dn;
+            m->nx[l] = (int32_t)n3[0];
+            m->ny[l] = (int32_t)n3[1];
+            BBS_HIP(hipMemsetAsync(dd, 0, (size_t)dn * sizeof(uint2), s));
+            k_fill_dense<<<grid_for((int64_t)cap), kThreads, 0, s>>>(m->keys[l], m->bits[l], cap, m->dense[l],
+                                                                     bbox[0], bbox[1], bbox[2], m->nx[l], m->ny[l]);
+            BBS_HIP(hipGetLastError());
+            BBS_HIP(hipStreamSynchronize(s));
+        }
+        return BBS_OK;
+    }
+}
+
+}  // namespace
+}  // namespace bbs
+
+extern "C" bbs_status bbs_build_map_margins(const float *xyz, int64_t n, int32_t xyz_on_device, float min_res,
+                                            int32_t levels, int32_t dilate_leaf, const int32_t *margins, void *stream,
+                                            bbs_map **out)
 {
     if (!out) return fail(BBS_ERR_INVALID_ARG, "bbs_build_map: out is NULL");
     *out = nullptr;
@@ -468,6 +580,13 @@ extern "C" bbs_status bbs_build_map(const float *xyz, int64_t n, int32_t xyz_on_
     if (!(min_res > 0.0f) || !std::isfinite(min_res))
         return fail(BBS_ERR_INVALID_ARG, "bbs_build_map: min_res must be finite and > 0");
     if (levels < 0 || levels >= kMaxLevels) return fail(BBS_ERR_INVALID_ARG, "bbs_build_map: levels must be in [0, 15]");
+    bool any_margin = false;
+    if (margins)
+        for (int l = 1; l <= levels; ++l) {
+            if (margins[l] < 0 || margins[l] > kMaxMargin)
+                return fail(BBS_ERR_INVALID_ARG, "bbs_build_map_margins: margins must be in [0, 8]");
+            any_margin = any_margin || margins[l] > 0;
+        }
 
     StreamGuard sg;
     sg.s = static_cast<hipStream_t>(stream);
@@ -477,7 +596,9 @@ extern "C" bbs_status bbs_build_map(const float *xyz, int64_t n, int32_t xyz_on_
     }
     hipStream_t s = sg.s;
 
-    DevBuf dxyz, dkeys, dset, duniq, dcount, derr, dbbox, dvox;
+    DevBuf dxyz, dkeys, dset, duniq;
+    BuildScratch B;
+    DevBuf &dcount = B.dcount, &derr = B.derr, &dbbox = B.dbbox, &dvox = B.dvox;
     const float *pts = xyz;
     if (!xyz_on_device) {
         if (alloc_dev(&dxyz.p, (size_t)n * 3 * sizeof(float))) return BBS_ERR_OOM;
@@ -515,7 +636,14 @@ extern "C" bbs_status bbs_build_map(const float *xyz, int64_t n, int32_t xyz_on_
     m->r = min_res;
     m->dilate_leaf = dilate_leaf ? 1 : 0;
     (void)hipGetDevice(&m->device);
-    const uint4 home = home_mask();
+    if (any_margin) {
+        m->grown = new bbs_map();
+        m->grown->levels = levels;
+        m->grown->r = min_res;
+        m->grown->dilate_leaf = m->dilate_leaf;
+        m->grown->device = m->device;
+        for (int l = 1; l <= levels; ++l) m->margin[l] = margins[l];
+    }
 
     // Occ_0 is in duniq; Occ_{l+1} = distinct parents of Occ_l (floor division
     // nests), so every level inserts only its own distinct voxels
@@ -548,97 +676,23 @@ extern "C" bbs_status bbs_build_map(const float *xyz, int64_t n, int32_t xyz_on_
             std::swap(occ, occ_next);
             n_occ = (int64_t)n_next;
         }
-        int dilate = (l > 0 || dilate_leaf) ? 1 : 0;
-        uint64_t tmp_cap = next_pow2(std::max<uint64_t>(1024, 4 * (uint64_t)n_occ));
-        for (;;) {
-            DevBuf tmp;
-            if (alloc_dev(&tmp.p, tmp_cap * sizeof(Slot))) {
-                bbs_free_map(m);
-                return BBS_ERR_OOM;
-            }
-            BBS_HIP(hipMemsetAsync(dcount.p, 0, 64, s));
-            BBS_HIP(hipMemsetAsync(derr.p, 0, 64, s));
-            k_fill_slots<<<grid_for((int64_t)tmp_cap), kThreads, 0, s>>>(tmp.as<Slot>(), tmp_cap);
-            k_insert_bricks<<<grid_for(n_occ), kThreads, 0, s>>>(occ, n_occ, dilate, tmp.as<Slot>(),
-                                                                  (uint32_t)(tmp_cap - 1),
-                                                                  dcount.as<unsigned long long>(), derr.as<int>());
-            BBS_HIP(hipGetLastError());
-            unsigned long long nb = 0;
-            BBS_HIP(hipMemcpyAsync(&nb, dcount.p, 8, hipMemcpyDeviceToHost, s));
-            BBS_HIP(hipMemcpyAsync(&err, derr.p, 4, hipMemcpyDeviceToHost, s));
-            BBS_HIP(hipStreamSynchronize(s));
-            if (err || nb * 2 > tmp_cap) {   // too full: grow and rebuild this level
-                if (tmp_cap >= ((uint64_t)1 << 31)) {
-                    bbs_free_map(m);
-                    return fail(BBS_ERR_OOM, "bbs_build_map: brick table would exceed 2^31 slots");
-                }
-                tmp_cap *= 4;
-                continue;
-            }
-            uint64_t cap = next_pow2(std::max<uint64_t>(16, 2 * nb));
-            void *dk = nullptr, *db = nullptr;
-            if (alloc_dev(&dk, cap * sizeof(uint2)) || alloc_dev(&db, cap * sizeof(uint4))) {
-                if (dk) (void)hipFree(dk);
-                bbs_free_map(m);
-                return BBS_ERR_OOM;
-            }
-            m->keys[l] = static_cast<uint2 *>(dk);
-            m->bits[l] = static_cast<uint4 *>(db);
-            m->cap[l] = cap;
-            m->bricks[l] = (int64_t)nb;
-            int bbox_init[6] = {INT_MAX, INT_MAX, INT_MAX, INT_MIN, INT_MIN, INT_MIN};
-            BBS_HIP(hipMemcpyAsync(dbbox.p, bbox_init, sizeof(bbox_init), hipMemcpyHostToDevice, s));
-            BBS_HIP(hipMemsetAsync(dvox.p, 0, 8, s));
-            k_fill_level<<<grid_for((int64_t)cap), kThreads, 0, s>>>(m->keys[l], m->bits[l], cap);
-            k_compact<<<grid_for((int64_t)tmp_cap, kThreads, 2048), kThreads, 0, s>>>(
-                tmp.as<Slot>(), tmp_cap, m->keys[l], m->bits[l], (uint32_t)(cap - 1), home, dbbox.as<int>(),
-                dvox.as<unsigned long long>(), derr.as<int>());
-            BBS_HIP(hipGetLastError());
-            int bbox[6];
-            unsigned long long nv = 0;
-            BBS_HIP(hipMemcpyAsync(bbox, dbbox.p, sizeof(bbox), hipMemcpyDeviceToHost, s));
-            BBS_HIP(hipMemcpyAsync(&nv, dvox.p, 8, hipMemcpyDeviceToHost, s));
-            BBS_HIP(hipMemcpyAsync(&err, derr.p, 4, hipMemcpyDeviceToHost, s));
-            BBS_HIP(hipStreamSynchronize(s));
-            if (err) {
-                bbs_free_map(m);
-                return fail(BBS_ERR_INTERNAL, "bbs_build_map: brick compaction failed");
-            }
-            for (int a = 0; a < 3; ++a) {
-                m->bmin[l][a] = bbox[a];
-                m->bmax[l][a] = bbox[3 + a];
-            }
-            m->voxels[l] = (int64_t)nv;
-            // dense column grid when the bounding box holds at most kDenseRatio x
-            // the hash capacity in bricks and the index products stay within 24
-            // bits; one extra layer of empty entries past the box maximum on
-            // every axis is where the scoring clamps points outside the box
-            const int64_t n3[3] = {(int64_t)bbox[3] - bbox[0] + 2, (int64_t)bbox[4] - bbox[1] + 2,
-                                   4 * ((int64_t)bbox[5] - bbox[2] + 1) + 1};
-            const int64_t dn = n3[0] * n3[1] * n3[2];
-            const int64_t box_bricks = n3[0] * n3[1] * ((int64_t)bbox[5] - bbox[2] + 2);
-            const bool axes_ok = n3[0] <= kDenseAxis && n3[1] <= kDenseAxis && n3[2] * n3[1] <= kDenseZY;
-            if (axes_ok && box_bricks <= kDenseRatio * (int64_t)cap && dn <= kDenseMax) {
-                void *dd = nullptr;
-                if (alloc_dev(&dd, (size_t)dn * sizeof(uint2))) {
-                    bbs_free_map(m);
-                    return BBS_ERR_OOM;
-                }
-                m->dense[l] = static_cast<uint2 *>(dd);
-                m->dense_n[l] = dn;
-                m->nx[l] = (int32_t)n3[0];
-                m->ny[l] = (int32_t)n3[1];
-                BBS_HIP(hipMemsetAsync(dd, 0, (size_t)dn * sizeof(uint2), s));
-                k_fill_dense<<<grid_for((int64_t)cap), kThreads, 0, s>>>(m->keys[l], m->bits[l], cap, m->dense[l],
-                                                                         bbox[0], bbox[1], bbox[2], m->nx[l], m->ny[l]);
-                BBS_HIP(hipGetLastError());
-                BBS_HIP(hipStreamSynchronize(s));
-            }
-            break;
+        const int jhi = (l > 0 || dilate_leaf) ? 1 : 0;
+        bbs_status st = build_level(m, l, occ, n_occ, 0, jhi, s, B);
+        if (st == BBS_OK && l > 0 && m->margin[l] > 0)
+            st = build_level(m->grown, l, occ, n_occ, -m->margin[l], 1 + m->margin[l], s, B);
+        if (st) {
+            bbs_free_map(m);
+            return st;
         }
     }
     *out = m;
     return BBS_OK;
+}
+
+extern "C" bbs_status bbs_build_map(const float *xyz, int64_t n, int32_t xyz_on_device, float min_res, int32_t levels,
+                                    int32_t dilate_leaf, void *stream, bbs_map **out)
+{
+    return bbs_build_map_margins(xyz, n, xyz_on_device, min_res, levels, dilate_leaf, nullptr, stream, out);
 }
 
 extern "C" bbs_status bbs_map_layout(const bbs_map *map, int32_t level, int32_t *dense, int64_t *dense_entries)

@@ -2613,11 +2613,61 @@ double cell_angle(const Grid &g, int ax, int c, int l)
     return g.wmin[ax] + g.dprime[ax][l] * ((double)c + 0.5);
 }
 
+// Box margins of the exact rotational bound (not in the paper, whose bound is
+// not strictly exact under rotation, Sec. III-D).  A level-l node is scored at
+// the centre rotation of its cell; the leaves below it lie within dev_ax of
+// that centre per axis (their cells are [c P, (c + 1) P - 1], P the product of
+// the divisions of levels 1..l), so a scan point moves by at most d_max times
+// the sum of the three deviations (Rz Ry Rx changes by at most the sum of its
+// angle changes in operator norm), i.e. its level-0 voxel by at most
+// D = ceil((move + 1e-5 d_max + 1e-6) / r) cells (the slack covers the float
+// transform) and its level-l voxel by at most e_l = ceil(D / 2^l).  Scoring
+// level l against D_l grown by [-e_l, e_l]^3 then bounds every leaf below
+// the node.  e_0 = 0, and every e_l = 0 on a translation-only grid.
+void rotation_margins(const Grid &g, int32_t e[kMaxLevels])
+{
+    for (int l = 0; l < kMaxLevels; ++l) e[l] = 0;
+    if (g.translation_only) return;
+    for (int l = 1; l <= g.levels; ++l) {
+        double sum_dev = 0.0;
+        for (int ax = 0; ax < 3; ++ax) {
+            int64_t P = 1;
+            for (int j = 1; j <= l; ++j) P *= g.a[ax][j];
+            const int64_t last = g.n[ax][0] - 1;
+            double dev = 0.0;
+            for (int c = 0; c < g.n[ax][l] && (int64_t)c * P <= last; ++c) {
+                const int64_t i0 = (int64_t)c * P, i1 = std::min<int64_t>((int64_t)(c + 1) * P - 1, last);
+                const double mid = cell_angle(g, ax, c, l);
+                dev = std::max(dev, std::fabs(cell_angle(g, ax, (int)i0, 0) - mid));
+                dev = std::max(dev, std::fabs(cell_angle(g, ax, (int)i1, 0) - mid));
+            }
+            sum_dev += dev;
+        }
+        const double cells = std::ceil((g.dmax * sum_dev + 1e-5 * g.dmax + 1e-6) / (double)g.r);
+        e[l] = (int32_t)std::ceil(cells / std::ldexp(1.0, l));
+    }
+}
+
+// The map's grown tables cover every level's margin of this grid.
+bbs_status check_margins(const bbs_map *m, const Grid &g, const char *who)
+{
+    int32_t e[kMaxLevels];
+    rotation_margins(g, e);
+    for (int l = 1; l <= g.levels; ++l)
+        if (e[l] > 0 && (!m->grown || m->margin[l] < e[l]))
+            return fail(BBS_ERR_INVALID_ARG, std::string(who) + ": the exact rotational bound needs a margin of " +
+                                                 std::to_string(e[l]) + " at level " + std::to_string(l) +
+                                                 " and the map has " + std::to_string(m->margin[l]) +
+                                                 " (see bbs_rotation_margins / bbs_build_map_margins)");
+    return BBS_OK;
+}
+
 struct Setup {
     Grid g;
     SearchConst C;
     hipStream_t s;
     bool pow2;
+    bool exact = false;       // exact rotational bound: levels >= 1 scored against the grown tables
     int rmode;                // scoring's division by r: 0 divide, 1 multiply by 1 / r, 2 r = 1
     int64_t kpad;             // scan arrays' stride: K rounded up to whole scoring rounds
     int32_t score_grid;       // k_score workgroups: as many as the device holds at once
@@ -2757,7 +2807,7 @@ void launch_score(const Setup &S, const bbs_map *m, bbs_workspace *ws, State *st
                   bool tile_pass)
 {
     const ScoreArgs A = score_args(S, ws, n_fixed, tile_pass);
-    const MapView v = m->view();
+    const MapView v = S.exact ? m->view_exact() : m->view();
     if (S.C.dedup_levels) {
         if (S.rmode == 2) k_score_runs<2><<<grid, kScoreThreads, 0, S.s>>>(st, A, v, S.C);
         else if (S.rmode == 1) k_score_runs<1><<<grid, kScoreThreads, 0, S.s>>>(st, A, v, S.C);
@@ -2915,6 +2965,11 @@ bbs_status localize_impl(const bbs_map *map, bbs_workspace *ws, const float *sca
     if (o.strategy != 0 && o.strategy != 1)
         return fail(BBS_ERR_INVALID_ARG, "bbs_localize: strategy must be 0 (best first) or 1 (depth first)");
     S.C.depth_first = o.strategy;
+    if (o.rot_exact != 0 && o.rot_exact != 1) return fail(BBS_ERR_INVALID_ARG, "bbs_localize: rot_exact must be 0 or 1");
+    if (o.rot_exact) {
+        if ((st = check_margins(map, S.g, "bbs_localize"))) return st;
+        S.exact = true;
+    }
     const Grid &g = S.g;
     const SearchConst &C = S.C;
     const int L = g.levels;
@@ -3177,7 +3232,7 @@ bbs_status localize_impl(const bbs_map *map, bbs_workspace *ws, const float *sca
         if (oe == hipSuccess && per_cu > 0) {
             ScoreArgs A = score_args(S, ws, 0, true);
             A.ticket = ws->ticket;            // items to whichever workgroup asks next
-            MapView v = map->view();
+            MapView v = S.exact ? map->view_exact() : map->view();
             SearchConst Cv = C;
             State *stp = ws->state;
             Bucket *bkp = ws->buckets;
@@ -3438,8 +3493,30 @@ extern "C" bbs_status bbs_localize_noalloc(const bbs_map *map, const float *scan
     return localize_impl(map, &w, scan_xyz, k, scan_on_device, range, score_threshold, o, out);
 }
 
+extern "C" bbs_status bbs_rotation_margins(float min_res, int32_t levels, double d_max, const bbs_search_range *range,
+                                           int32_t *margins)
+{
+    if (!range || !margins) return fail(BBS_ERR_INVALID_ARG, "bbs_rotation_margins: NULL argument");
+    if (!(min_res > 0.0f) || !std::isfinite(min_res) || levels < 0 || levels >= kMaxLevels)
+        return fail(BBS_ERR_INVALID_ARG, "bbs_rotation_margins: min_res must be > 0 and levels in [0, 15]");
+    if (!(d_max > 0.0) || !std::isfinite(d_max)) return fail(BBS_ERR_INVALID_ARG, "bbs_rotation_margins: d_max must be > 0");
+    for (int i = 0; i < 6; ++i)
+        if (!std::isfinite(range->min[i]) || !std::isfinite(range->max[i]) || range->min[i] > range->max[i])
+            return fail(BBS_ERR_INVALID_ARG, "bbs_rotation_margins: bad search range");
+    bbs_map shape{};              // the grid needs only the level count and r
+    shape.levels = levels;
+    shape.r = min_res;
+    Grid g;
+    bbs_status st = make_grid(&shape, d_max, range, 0, g);
+    if (st) return st;
+    int32_t e[kMaxLevels];
+    rotation_margins(g, e);
+    for (int l = 0; l <= levels; ++l) margins[l] = e[l];
+    return BBS_OK;
+}
+
 extern "C" bbs_status bbs_score_nodes(const bbs_map *map, const float *scan_xyz, int64_t k,
-                                      const bbs_search_range *range, int32_t translation_only, const int32_t *nodes,
+                                      const bbs_search_range *range, int32_t mode, const int32_t *nodes,
                                       int64_t n, int32_t *scores)
 {
     if (!map) return fail(BBS_ERR_INVALID_ARG, "bbs_score_nodes: map is NULL");
@@ -3451,8 +3528,13 @@ extern "C" bbs_status bbs_score_nodes(const bbs_map *map, const float *scan_xyz,
     bbs_workspace *ws = tmp.w;
     hipStream_t s = ws->own_stream;
     Setup S;
-    st = setup_search(map, ws, scan_xyz, k, 0, range, translation_only, 0, 1, s, S);
+    if (mode & ~3) return fail(BBS_ERR_INVALID_ARG, "bbs_score_nodes: mode must be in [0, 3]");
+    st = setup_search(map, ws, scan_xyz, k, 0, range, mode & 1, 0, 1, s, S);
     if (st) return st;
+    if (mode & 2) {
+        if ((st = check_margins(map, S.g, "bbs_score_nodes"))) return st;
+        S.exact = true;
+    }
     if (n == 0) return BBS_OK;
     std::vector<uint4> groups((size_t)n);
     for (int64_t i = 0; i < n; ++i) {
