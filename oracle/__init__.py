@@ -92,6 +92,8 @@ def lib():
         L.orc_map_contains_rot.argtypes = [P, I32, I32, I32, I32]
         L.orc_map_contains_rot.restype = I32
         L.orc_rotation_margins.argtypes = [C.POINTER(Grid), P]
+        L.orc_grid_nest.argtypes = [C.POINTER(Grid)]
+        L.orc_grid_nest.restype = C.c_int
         L.orc_free_map.argtypes = [P]
         L.orc_map_level_size.argtypes = [P, I32]
         L.orc_map_level_size.restype = I64
@@ -190,10 +192,12 @@ class Search:
     """A scan plus its search ranges: the angular/translational grid and the
     oracle's score, branching and search."""
 
-    def __init__(self, omap: Map, scan, rmin, rmax, translation_only: bool = False, rot_exact: bool = False):
+    def __init__(self, omap: Map, scan, rmin, rmax, translation_only: bool = False, rot_exact: bool = False,
+                 nested: bool = False):
         """rot_exact: inner nodes are scored against the map's grown tables
-        (the exact rotational bound); the map's rot_margin must be at least
-        margin_needed()."""
+        (the exact rotational bound); the map's margins must cover
+        margins_needed().  nested: the angular grid is built top down so that
+        every cell splits into equal children (orc_grid_nest)."""
         self.map = omap
         self.scan = _f32(scan).reshape(-1, 3)
         self.rmin = _f32(rmin)
@@ -203,6 +207,8 @@ class Search:
                              omap.r, omap.levels, int(translation_only), C.byref(self.grid))
         if rc != 0:
             raise OracleError(f"orc_setup failed ({rc})")
+        if nested and lib().orc_grid_nest(C.byref(self.grid)) != 0:
+            raise OracleError("orc_grid_nest failed")
         self.grid.rot_exact = int(bool(rot_exact))
         if rot_exact and any(e > m for e, m in zip(self.margins_needed(), omap.margins)):
             raise OracleError(f"the map's rotation margins {omap.margins} are below the {self.margins_needed()} "

@@ -337,6 +337,37 @@ int orc_setup(const float *scan, int64_t k, const float rmin[6], const float rma
     return ORC_OK;
 }
 
+/*
+ * Nested angular cells (an alternative reading, not the default).  With
+ * delta'_l = W / n_l per level (Eq. (13)) and the children a c + j of
+ * Eq. (14), a = ceil(n_{l-1} / n_l) (Eq. (15)), a child cell lies inside its
+ * parent only when n_{l-1} = a n_l; otherwise children drift away from their
+ * parent's angle (with a = 3 where n_{l-1} is just above 2 n_l, level-l cell
+ * c has children at about 1.5 times its angle).  This builds the grid top
+ * down instead: n_lmax as in Eq. (13), then a_l = ceil((W / n_l) /
+ * delta(r_{l-1})) and n_{l-1} = a_l n_l, so every cell splits into a_l equal
+ * children, each at most delta(r_{l-1}) wide.  Translation-only grids and
+ * axes with W = 0 are unchanged.
+ */
+int orc_grid_nest(orc_grid *g)
+{
+    if (g->translation_only) return ORC_OK;
+    for (int ax = 0; ax < 3; ++ax) {
+        double W = g->wmax[ax] - g->wmin[ax];
+        if (W == 0.0) continue;
+        for (int l = g->levels; l >= 1; --l) {
+            double a = ceil((W / g->n[ax][l]) / g->delta[l - 1]);
+            if (!(a >= 1.0)) a = 1.0;
+            if (a * g->n[ax][l] > 1.0e8) return ORC_ERR_ARG;
+            g->n[ax][l - 1] = (int32_t)(a * g->n[ax][l]);
+        }
+        for (int l = 0; l <= g->levels; ++l) g->dprime[ax][l] = W / g->n[ax][l];
+        g->a[ax][0] = 1;
+        for (int l = 1; l <= g->levels; ++l) g->a[ax][l] = g->n[ax][l - 1] / g->n[ax][l];
+    }
+    return ORC_OK;
+}
+
 /* Angle of cell c of axis ax at level l.  Reading: cells are anchored at their
  * centres, W_min + delta'_l (c + 1/2). */
 static double cell_angle(const orc_grid *g, int ax, int32_t c, int l)
