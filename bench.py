@@ -258,6 +258,7 @@ def main():
     ap.add_argument("--table1-queries", type=int, default=10)
     ap.add_argument("--rot-exact", action="store_true",
                     help="the city queries with the exact rotational bound against plain (grown map tables)")
+    ap.add_argument("--nested", action="store_true", help="with --rot-exact: on the nested angular grid")
     ap.add_argument("--table1-cpu-seconds", type=float, default=20.0,
                     help="CPU seconds each CPU configuration of Table I may spend (it runs as many queries as fit)")
     args = ap.parse_args()
@@ -391,13 +392,21 @@ def main():
     if not args.no_extra:
         same = lambda rr: sum(a["found"] == b["found"] and a["leaf"] == b["leaf"] and a["score"] == b["score"] and
                               a["nodes_expanded"] == b["nodes_expanded"] for a, b in zip(rr, results))
-        for mode, kw in (("persistent", {"persistent": True}), ("graph", {"graph": True})):
+        for mode, kw in (("persistent", {"persistent": True}), ("graph", {"graph": True}),
+                         ("nested_angles", {"nested_angles": True})):
             bbs.localize(gmap, dev[warm_seeds[0] if warm_seeds else 0], lo, hi, T, batch_size=args.batch,
                          workspace=ws, **kw)
             rr, dt = timed_leg(gmap, dev, seeds, lo, hi, T, args.batch, ws, **kw)
             line["config"][mode] = {"ms_per_localization_mean": dt / len(seeds) * 1e3,
                                     "nodes_per_s": sum(r["nodes_scored"] for r in rr) / dt,
                                     "same_result_as_plain": f"{same(rr)}/{len(seeds)}"}
+            if mode == "nested_angles":
+                # another angular grid (a reading option): its own results, not the plain ones
+                line["config"][mode].update({
+                    "reading": "angular cells nested top down (option nested_angles), not the default grid",
+                    "nodes_scored_total": sum(r["nodes_scored"] for r in rr),
+                    "found": f"{sum(r['found'] for r in rr)}/{len(seeds)}",
+                    "success_2m_0p05rad": f"{sum(success(r, scans[s].pose) for s, r in zip(seeds, rr))}/{len(seeds)}"})
             print(f"[bench] {mode}: {line['config'][mode]}", file=sys.stderr, flush=True)
         # achievable memory rates: a streaming read of 1 GiB (HBM) and random
         # 8-byte gathers into a table of the size of the map's level grids
@@ -476,7 +485,9 @@ def learned_order(gmap, dev, seeds, plain, lo, hi, T, args):
 def rot_exact_bench(args):
     """The exact rotational bound on the city workload: the map is built with
     the grown tables that the queries' margins need (largest over the
-    queries), then every query is localized plain and with rot_exact.  One
+    queries whose margins are all at most 8; a query whose angular grid makes
+    child cells drift far from their parent's angle needs more and is
+    skipped), then those queries are localized plain and with rot_exact.  One
     JSON line: ms per localization and nodes scored of both, and how many
     results agree."""
     import numpy as np
@@ -489,9 +500,12 @@ def rot_exact_bench(args):
     T = synth.threshold_95(args.k)
     seeds = list(range(args.steps))
     scans = {s: synth.city_query(city, s, args.k, voxel=0.5) for s in seeds}
-    ranges = [float(np.sqrt((v.points.astype(np.float64) ** 2).sum(1)).max()) for v in scans.values()]
-    dmax = max(ranges)
-    need = [max(col) for col in zip(*(bbs.rotation_margins(1.0, 6, d, lo, hi) for d in ranges))]
+    ranges = {s: float(np.sqrt((v.points.astype(np.float64) ** 2).sum(1)).max()) for s, v in scans.items()}
+    margins = {s: bbs.rotation_margins(1.0, 6, d, lo, hi, nested_angles=args.nested) for s, d in ranges.items()}
+    all_seeds = seeds
+    seeds = [s for s in seeds if max(margins[s]) <= 8]
+    dmax = max(ranges[s] for s in seeds)
+    need = [max(col) for col in zip(*(margins[s] for s in seeds))]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     gmap = bbs.Map(torch.from_numpy(city.points).cuda(), 1.0, 6, margins=need)
@@ -501,7 +515,8 @@ def rot_exact_bench(args):
     ws = bbs.Workspace()
     out = {}
     for mode in ("plain", "rot_exact"):
-        kw = {"rot_exact": mode == "rot_exact", "batch_size": args.batch, "workspace": ws}
+        kw = {"rot_exact": mode == "rot_exact", "batch_size": args.batch, "workspace": ws,
+              "nested_angles": args.nested}
         bbs.localize(gmap, dev[seeds[0]], lo, hi, T, **kw)
         res, ms = [], []
         for s in seeds:
@@ -527,8 +542,11 @@ def rot_exact_bench(args):
         "steps": len(seeds), "warmup": 1, "ms_per_step": out["rot_exact"]["ms_mean"], "higher_is_better": False,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic (seeded procedural city and ray-cast scans)",
-        "config": {"workload": f"city seed 1000, {args.k}-pt scans (query seeds 0..{len(seeds) - 1}), b={args.batch}",
+        "config": {"workload": f"city seed 1000, {args.k}-pt scans (query seeds {seeds}), b={args.batch}"
+                               + (", nested angular grid" if args.nested else ""),
                    "margins": need, "d_max_largest": dmax, "map_build_ms_with_grown_tables": build_ms,
+                   "queries_within_margin_8": f"{len(seeds)}/{len(all_seeds)}",
+                   "margins_of_skipped": {str(s): margins[s] for s in all_seeds if s not in seeds},
                    "plain": out["plain"], "rot_exact": out["rot_exact"],
                    "same_result": f"{same}/{len(seeds)}", "higher_score_with_exact_bound": higher},
     }

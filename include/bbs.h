@@ -97,6 +97,16 @@ typedef struct {
                                  score, lexicographically smallest leaf), whatever the order.
                                  The map must hold grown tables with margins >= e_l
                                  (bbs_build_map_margins), else INVALID_ARG */
+    int32_t nested_angles;    /* 1: nested angular cells (not the default reading): Eq. (13) sets
+                                 each level's cells on its own, and the children a c + j of
+                                 Eq. (14) (a of Eq. (15)) lie inside their parent only when
+                                 n_{l-1} = a n_l; otherwise they drift from the parent's angle.
+                                 With 1 the grid is built top down: n_lmax as in Eq. (13),
+                                 then a_l = ceil((W / n_l) / delta(r_{l-1})) and n_{l-1} =
+                                 a_l n_l, so each cell splits into a_l equal children at most
+                                 delta(r_{l-1}) wide (a finer leaf grid where the ratios were
+                                 not integers).  0 (default): Eq. (13) on every level */
+    int32_t reserved3;
 } bbs_options;
 
 typedef struct {
@@ -181,12 +191,74 @@ bbs_status bbs_build_map_margins(const float *xyz, int64_t n, int32_t xyz_on_dev
  * its angular cell; the leaves below it lie within dev_ax of that centre on
  * each axis, so a scan point moves by at most d_max (dev_roll + dev_pitch +
  * dev_yaw), i.e. by D = ceil((that + 1e-5 d_max + 1e-6) / min_res) level-0
- * cells, and e_l = ceil(D / 2^l).  margins: levels + 1 outputs, [0] = 0.
+ * cells, and e_l = ceil(D / 2^l).  nested_angles as the option of that name.
+ * margins: levels + 1 outputs, [0] = 0.
  * A scan of smaller range may need other margins (the angular grid changes
  * with d_max); bbs_localize checks the scan's own.
  */
 bbs_status bbs_rotation_margins(float min_res, int32_t levels, double d_max, const bbs_search_range *range,
-                                int32_t *margins);
+                                int32_t nested_angles, int32_t *margins);
+
+/*
+ * Pose refinement after the search.  The paper takes a BBS pose as good when
+ * local registration with GICP can finish from it (Sec. IV, the success
+ * criterion; Sec. IV-B aligns the ground truth with GICP) and gives no GICP
+ * arithmetic.  Readings: generalized ICP (Segal et al.) with voxel statistics
+ * as its distributions.
+ *   - Distributions: points grouped by voxel floor(p / voxel) (double); a
+ *     voxel of at least min_points points has mean S1 / n and covariance
+ *     S2 / n - mu mu^T, regularized plane to plane: eigenvectors U of
+ *     ascending eigenvalues, C = U diag(1e-3, 1, 1) U^T.
+ *   - The scan's own voxels (same edge, the call's min_points) give each scan
+ *     point its covariance C_i; points of smaller scan voxels take no part.
+ *   - Pairing: q_i = R p_i + t goes with the nearest target mean among the 27
+ *     voxels around floor(q_i / voxel) (lexicographic offsets, the first of
+ *     equal distances) if it is closer than one edge.
+ *   - Cost: sum of r_i^T Omega_i r_i, r_i = mu - q_i, Omega_i = (C + R C_i
+ *     R^T)^-1.  Gauss-Newton on q' = Exp(w) q + tau: J_i = [ [q_i]_x , -I ],
+ *     (w, tau) = -(sum J^T Omega J)^-1 sum J^T Omega r, then R <- Exp(w) R,
+ *     t <- Exp(w) t + tau; stop after max_iterations steps or once |w| <
+ *     eps_rot and |tau| < eps_trans (that step applied).
+ */
+typedef struct bbs_gicp_target bbs_gicp_target;
+
+/* The target's voxel distributions (device; the points may be freed after
+ * the call).  n in [1, 2^30), voxel > 0, min_points >= 4; INVALID_ARG for
+ * non-finite points or voxel indices beyond +-2^20. */
+bbs_status bbs_gicp_target_create(const float *xyz, int64_t n, int32_t on_device, double voxel, int32_t min_points,
+                                  void *stream, bbs_gicp_target **out);
+void bbs_gicp_target_free(bbs_gicp_target *target);
+
+typedef struct {
+    int32_t max_iterations;   /* Gauss-Newton steps, [0, 1000] (default 20) */
+    int32_t min_points;       /* points of a scan voxel that gives a covariance, >= 4 (default 5) */
+    double eps_rot;           /* convergence: rotation step below this (rad, default 1e-6) */
+    double eps_trans;         /* and translation step below this (m, default 1e-5) */
+} bbs_gicp_options;
+
+typedef struct {
+    double R[9];              /* refined rotation, row major */
+    double t[3];              /* refined translation (m) */
+    double cost;              /* cost at the refined pose */
+    int64_t pairs;            /* paired scan points at the refined pose */
+    int32_t iterations;       /* steps taken */
+    int32_t converged;        /* 1: the last step was below both eps */
+} bbs_gicp_result;
+
+void bbs_gicp_default_options(bbs_gicp_options *opt);
+
+/* Refine (R0, t0) (sensor to map; R0 row major).  The scan (k x 3 float32,
+ * host or device) is prepared on the device per call; the call returns when
+ * done.  Allocates its scratch for the duration of the call. */
+bbs_status bbs_gicp_refine(const bbs_gicp_target *target, const float *scan, int64_t k, int32_t on_device,
+                           const double R0[9], const double t0[3], const bbs_gicp_options *opt, void *stream,
+                           bbs_gicp_result *out);
+
+/* One linearization at (R, t): H (6 x 6 row major), g, cost and the number of
+ * paired points, in the order (w, tau) of the step. */
+bbs_status bbs_gicp_linearize(const bbs_gicp_target *target, const float *scan, int64_t k, int32_t on_device,
+                              const double R[9], const double t[3], int32_t min_points, void *stream, double H[36],
+                              double g[6], double *cost, int64_t *pairs);
 
 /* Release a map (NULL is ignored). */
 void bbs_free_map(bbs_map *map);
@@ -275,7 +347,8 @@ bbs_status bbs_localize_noalloc(const bbs_map *map, const float *scan_xyz, int64
  * Nodes outside the search set are scored all the same (their cell angles
  * are extrapolated from the grid).
  *   mode            bit 0: translation-only grid (as option translation_only);
- *                   bit 1: exact rotational bound (as option rot_exact)
+ *                   bit 1: exact rotational bound (as option rot_exact);
+ *                   bit 2: nested angular cells (as option nested_angles)
  */
 bbs_status bbs_score_nodes(const bbs_map *map, const float *scan_xyz, int64_t k, const bbs_search_range *range,
                            int32_t mode, const int32_t *nodes, int64_t n, int32_t *scores);

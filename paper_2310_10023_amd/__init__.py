@@ -27,6 +27,8 @@ EXPORTED_SYMBOLS = (
     "bbs_score_nodes", "bbs_serve", "bbs_net_param_count", "bbs_net_create", "bbs_net_free", "bbs_net_set_params",
     "bbs_net_get_params", "bbs_net_forward", "bbs_net_prior", "bbs_net_train_step", "bbs_bev_image", "bbs_autotune",
     "bbs_bandwidth_probe", "bbs_preprocess_scan", "bbs_build_map_margins", "bbs_rotation_margins",
+    "bbs_gicp_target_create", "bbs_gicp_target_free", "bbs_gicp_default_options", "bbs_gicp_refine",
+    "bbs_gicp_linearize",
 )
 
 STRATEGIES = {"best_first": 0, "depth_first": 1}
@@ -51,7 +53,8 @@ class Options(C.Structure):
     _fields_ = [("batch_size", C.c_int32), ("translation_only", C.c_int32), ("profile", C.c_int32),
                 ("seed_beam", C.c_int32), ("stream", C.c_void_p), ("prior", C.c_void_p),
                 ("persistent", C.c_int32), ("score_items", C.c_int32), ("graph", C.c_int32),
-                ("hist_min_level", C.c_int32), ("strategy", C.c_int32), ("rot_exact", C.c_int32)]
+                ("hist_min_level", C.c_int32), ("strategy", C.c_int32), ("rot_exact", C.c_int32),
+                ("nested_angles", C.c_int32), ("reserved3", C.c_int32)]
 
 
 class Result(C.Structure):
@@ -81,6 +84,16 @@ class Result(C.Structure):
 
 class TuneEntry(C.Structure):
     _fields_ = [("batch_size", C.c_int32), ("score_items", C.c_int32), ("ms", C.c_double)]
+
+
+class GicpOptions(C.Structure):
+    _fields_ = [("max_iterations", C.c_int32), ("min_points", C.c_int32), ("eps_rot", C.c_double),
+                ("eps_trans", C.c_double)]
+
+
+class GicpResult(C.Structure):
+    _fields_ = [("R", C.c_double * 9), ("t", C.c_double * 3), ("cost", C.c_double), ("pairs", C.c_int64),
+                ("iterations", C.c_int32), ("converged", C.c_int32)]
 
 
 class PreprocessOptions(C.Structure):
@@ -121,8 +134,17 @@ def lib():
         L.bbs_build_map.restype = C.c_int
         L.bbs_build_map_margins.argtypes = [P, I64, I32, F, I32, I32, P, P, C.POINTER(P)]
         L.bbs_build_map_margins.restype = C.c_int
-        L.bbs_rotation_margins.argtypes = [F, I32, C.c_double, C.POINTER(SearchRange), P]
+        L.bbs_rotation_margins.argtypes = [F, I32, C.c_double, C.POINTER(SearchRange), I32, P]
         L.bbs_rotation_margins.restype = C.c_int
+        D = C.c_double
+        L.bbs_gicp_target_create.argtypes = [P, I64, I32, D, I32, P, C.POINTER(P)]
+        L.bbs_gicp_target_create.restype = C.c_int
+        L.bbs_gicp_target_free.argtypes = [P]
+        L.bbs_gicp_default_options.argtypes = [C.POINTER(GicpOptions)]
+        L.bbs_gicp_refine.argtypes = [P, P, I64, I32, P, P, C.POINTER(GicpOptions), P, C.POINTER(GicpResult)]
+        L.bbs_gicp_refine.restype = C.c_int
+        L.bbs_gicp_linearize.argtypes = [P, P, I64, I32, P, P, I32, P, P, P, C.POINTER(D), C.POINTER(I64)]
+        L.bbs_gicp_linearize.restype = C.c_int
         L.bbs_free_map.argtypes = [P]
         L.bbs_map_info.argtypes = [P, C.POINTER(I32), C.POINTER(F), P, P, P]
         L.bbs_map_info.restype = C.c_int
@@ -299,7 +321,7 @@ def localize(bmap: Map, scan, rmin, rmax, score_threshold: int, *, batch_size: i
              translation_only: bool = False, profile: int = 0, workspace: Workspace | None = None,
              stream=None, prior=None, seed_beam: int = 0, persistent: bool = False,
              score_items: int = 0, graph: bool = False, hist_min_level: int = 0,
-             strategy: str = "best_first", rot_exact: bool = False) -> dict:
+             strategy: str = "best_first", rot_exact: bool = False, nested_angles: bool = False) -> dict:
     """Global localization of one scan (Alg. 2 on the GPU).  Returns the result
     fields as a dict (found, score, leaf, pose, node counters, timings).
     prior: optional 1088 logits of the proposal network."""
@@ -316,6 +338,7 @@ def localize(bmap: Map, scan, rmin, rmax, score_threshold: int, *, batch_size: i
     opt.hist_min_level = int(hist_min_level)
     opt.strategy = STRATEGIES[strategy]
     opt.rot_exact = int(rot_exact)
+    opt.nested_angles = int(nested_angles)
     pr = None
     if prior is not None:
         pr = np.ascontiguousarray(prior, dtype=np.float32).reshape(1088)
@@ -357,7 +380,7 @@ def localize_noalloc(bmap: Map, scan, rmin, rmax, score_threshold: int, *, batch
 
 
 def score_nodes(bmap: Map, scan, rmin, rmax, nodes, translation_only: bool = False,
-                rot_exact: bool = False) -> np.ndarray:
+                rot_exact: bool = False, nested_angles: bool = False) -> np.ndarray:
     """Scores of arbitrary nodes (rows level, x, y, z, i_roll, i_pitch, i_yaw)
     computed by the device scoring kernel."""
     s = np.ascontiguousarray(scan, dtype=np.float32).reshape(-1, 3)
@@ -365,7 +388,7 @@ def score_nodes(bmap: Map, scan, rmin, rmax, nodes, translation_only: bool = Fal
     out = np.zeros(len(nd), np.int32)
     rng = _range(rmin, rmax)
     _check(lib().bbs_score_nodes(bmap.handle, s.ctypes.data, len(s), C.byref(rng),
-                                 int(bool(translation_only)) | (2 if rot_exact else 0),
+                                 int(bool(translation_only)) | (2 if rot_exact else 0) | (4 if nested_angles else 0),
                                  nd.ctypes.data, len(nd), out.ctypes.data))
     return out
 
@@ -466,10 +489,67 @@ def preprocess_scan(points, gravity=None, leaf: float = 0.0, target_points: int 
     return out[:out_n.value], float(used.value)
 
 
-def rotation_margins(min_res: float, levels: int, d_max: float, rmin, rmax) -> list:
+def rotation_margins(min_res: float, levels: int, d_max: float, rmin, rmax, nested_angles: bool = False) -> list:
     """Box margins e_l ([0] = 0) that the exact rotational bound needs for
     scans of largest range d_max over the search range (bbs_rotation_margins)."""
     out = np.zeros(int(levels) + 1, np.int32)
     rng = _range(rmin, rmax)
-    _check(lib().bbs_rotation_margins(float(min_res), int(levels), float(d_max), C.byref(rng), out.ctypes.data))
+    _check(lib().bbs_rotation_margins(float(min_res), int(levels), float(d_max), C.byref(rng), int(nested_angles),
+                                      out.ctypes.data))
     return [int(v) for v in out]
+
+
+class GicpTarget:
+    """The voxel distributions of a map for pose refinement (bbs_gicp_target_create)."""
+
+    def __init__(self, points, voxel: float = 1.0, min_points: int = 5, stream=None):
+        ptr, n, dev, keep = _points(points, "points")
+        h = C.c_void_p()
+        _check(lib().bbs_gicp_target_create(ptr, n, dev, float(voxel), int(min_points), _stream(stream),
+                                            C.byref(h)))
+        del keep
+        self._h = h
+        self.voxel = float(voxel)
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().bbs_gicp_target_free(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def refine(self, scan, R0, t0, max_iterations: int = 20, min_points: int = 5, eps_rot: float = 1e-6,
+               eps_trans: float = 1e-5, stream=None):
+        """GICP from (R0, t0): returns (R 3x3, t 3, info dict)."""
+        ptr, k, dev, keep = _points(scan, "scan")
+        opt = GicpOptions()
+        lib().bbs_gicp_default_options(C.byref(opt))
+        opt.max_iterations, opt.min_points = int(max_iterations), int(min_points)
+        opt.eps_rot, opt.eps_trans = float(eps_rot), float(eps_trans)
+        R = np.ascontiguousarray(R0, np.float64).reshape(9)
+        t = np.ascontiguousarray(t0, np.float64).reshape(3)
+        res = GicpResult()
+        _check(lib().bbs_gicp_refine(self._h, ptr, k, dev, R.ctypes.data, t.ctypes.data, C.byref(opt),
+                                     _stream(stream), C.byref(res)))
+        del keep
+        return (np.array(res.R).reshape(3, 3), np.array(res.t),
+                {"cost": res.cost, "pairs": res.pairs, "iterations": res.iterations,
+                 "converged": bool(res.converged)})
+
+    def linearize(self, scan, R, t, min_points: int = 5, stream=None):
+        """(H 6x6, g 6, cost, pairs) of one Gauss-Newton step at (R, t)."""
+        ptr, k, dev, keep = _points(scan, "scan")
+        Rr = np.ascontiguousarray(R, np.float64).reshape(9)
+        tt = np.ascontiguousarray(t, np.float64).reshape(3)
+        H = np.zeros(36)
+        g = np.zeros(6)
+        cost, pairs = C.c_double(), C.c_int64()
+        _check(lib().bbs_gicp_linearize(self._h, ptr, k, dev, Rr.ctypes.data, tt.ctypes.data, int(min_points),
+                                        _stream(stream), H.ctypes.data, g.ctypes.data, C.byref(cost),
+                                        C.byref(pairs)))
+        del keep
+        return H.reshape(6, 6), g, cost.value, pairs.value

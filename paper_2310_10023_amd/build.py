@@ -13,7 +13,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIBDIR, "libbbs.so")
-SOURCES = ["bbs_api.cpp", "bbs_serve.cpp", "bbs_map.hip", "bbs_search.hip", "bbs_net.hip", "bbs_probe.hip", "bbs_prep.hip"]
+SOURCES = ["bbs_api.cpp", "bbs_serve.cpp", "bbs_map.hip", "bbs_search.hip", "bbs_net.hip", "bbs_probe.hip", "bbs_prep.hip", "bbs_gicp.hip"]
 ARCH = os.environ.get("BBS_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

@@ -2608,6 +2608,35 @@ bbs_status make_grid(const bbs_map *m, double dmax, const bbs_search_range *rang
     return BBS_OK;
 }
 
+// Nested angular cells (option nested_angles; not the default reading).
+// Eq. (13) sets each level's cells independently and Eq. (14) takes the
+// children a c + j with a = ceil(n_{l-1} / n_l) (Eq. (15)); a child cell lies
+// inside its parent only when n_{l-1} = a n_l, and otherwise children drift
+// from their parent's angle (a = 3 where n_{l-1} is just above 2 n_l puts
+// the children of cell c at about 1.5 times its angle).  Here the grid is
+// built top down: n_lmax as in Eq. (13), then a_l = ceil((W / n_l) /
+// delta(r_{l-1})) and n_{l-1} = a_l n_l, so every cell splits into a_l equal
+// children, each at most delta(r_{l-1}) wide.  Translation-only grids and
+// axes with W = 0 are unchanged.
+bbs_status nest_grid(Grid &g)
+{
+    if (g.translation_only) return BBS_OK;
+    for (int ax = 0; ax < 3; ++ax) {
+        const double W = g.wmax[ax] - g.wmin[ax];
+        if (W == 0.0) continue;
+        for (int l = g.levels; l >= 1; --l) {
+            const double a = std::max(1.0, std::ceil((W / g.n[ax][l]) / g.delta[l - 1]));
+            if (a * g.n[ax][l] > 65535.0)
+                return fail(BBS_ERR_INVALID_ARG, "bbs_localize: nested angular grid with more than 65535 cells");
+            g.n[ax][l - 1] = (int32_t)(a * g.n[ax][l]);
+        }
+        for (int l = 0; l <= g.levels; ++l) g.dprime[ax][l] = W / g.n[ax][l];
+        g.a[ax][0] = 1;
+        for (int l = 1; l <= g.levels; ++l) g.a[ax][l] = g.n[ax][l - 1] / g.n[ax][l];
+    }
+    return BBS_OK;
+}
+
 double cell_angle(const Grid &g, int ax, int c, int l)
 {
     return g.wmin[ax] + g.dprime[ax][l] * ((double)c + 0.5);
@@ -2677,7 +2706,7 @@ struct Setup {
 // Upload the scan, derive d_max, the grid and the cos/sin tables.
 bbs_status setup_search(const bbs_map *m, bbs_workspace *ws, const float *scan, int64_t k, int on_device,
                         const bbs_search_range *range, int translation_only, int32_t threshold, int64_t batch,
-                        hipStream_t s, Setup &S)
+                        hipStream_t s, Setup &S, bool nested = false)
 {
     if (k < 1 || k > (1 << 24)) return fail(BBS_ERR_INVALID_ARG, "bbs_localize: k must be in [1, 2^24]");
     if (!scan) return fail(BBS_ERR_INVALID_ARG, "bbs_localize: scan is NULL");
@@ -2716,6 +2745,7 @@ bbs_status setup_search(const bbs_map *m, bbs_workspace *ws, const float *scan, 
     double dmax = std::sqrt(maxsq);
     bbs_status st = make_grid(m, dmax, range, translation_only, S.g);
     if (st) return st;
+    if (nested && (st = nest_grid(S.g))) return st;
     {
         const float lo = -(float)dmax - 1.0f;
         const float inv_cell = (float)(1 << kMortonBits) / (2.0f * ((float)dmax + 1.0f));
@@ -2956,8 +2986,10 @@ bbs_status localize_impl(const bbs_map *map, bbs_workspace *ws, const float *sca
     const auto t_start = std::chrono::steady_clock::now();
     hipStream_t s = o.stream ? static_cast<hipStream_t>(o.stream) : ws->own_stream;
     Setup S;
+    if (o.nested_angles != 0 && o.nested_angles != 1)
+        return fail(BBS_ERR_INVALID_ARG, "bbs_localize: nested_angles must be 0 or 1");
     bbs_status st = setup_search(map, ws, scan_xyz, k, scan_on_device, range, o.translation_only, score_threshold,
-                                 o.batch_size, s, S);
+                                 o.batch_size, s, S, o.nested_angles != 0);
     if (st) return st;
     if (o.score_items < 0 || o.score_items > (1 << 20))
         return fail(BBS_ERR_INVALID_ARG, "bbs_localize: score_items must be in [0, 2^20]");
@@ -3494,7 +3526,7 @@ extern "C" bbs_status bbs_localize_noalloc(const bbs_map *map, const float *scan
 }
 
 extern "C" bbs_status bbs_rotation_margins(float min_res, int32_t levels, double d_max, const bbs_search_range *range,
-                                           int32_t *margins)
+                                           int32_t nested_angles, int32_t *margins)
 {
     if (!range || !margins) return fail(BBS_ERR_INVALID_ARG, "bbs_rotation_margins: NULL argument");
     if (!(min_res > 0.0f) || !std::isfinite(min_res) || levels < 0 || levels >= kMaxLevels)
@@ -3509,6 +3541,7 @@ extern "C" bbs_status bbs_rotation_margins(float min_res, int32_t levels, double
     Grid g;
     bbs_status st = make_grid(&shape, d_max, range, 0, g);
     if (st) return st;
+    if (nested_angles && (st = nest_grid(g))) return st;
     int32_t e[kMaxLevels];
     rotation_margins(g, e);
     for (int l = 0; l <= levels; ++l) margins[l] = e[l];
@@ -3528,8 +3561,8 @@ extern "C" bbs_status bbs_score_nodes(const bbs_map *map, const float *scan_xyz,
     bbs_workspace *ws = tmp.w;
     hipStream_t s = ws->own_stream;
     Setup S;
-    if (mode & ~3) return fail(BBS_ERR_INVALID_ARG, "bbs_score_nodes: mode must be in [0, 3]");
-    st = setup_search(map, ws, scan_xyz, k, 0, range, mode & 1, 0, 1, s, S);
+    if (mode & ~7) return fail(BBS_ERR_INVALID_ARG, "bbs_score_nodes: mode must be in [0, 7]");
+    st = setup_search(map, ws, scan_xyz, k, 0, range, mode & 1, 0, 1, s, S, (mode & 4) != 0);
     if (st) return st;
     if (mode & 2) {
         if ((st = check_margins(map, S.g, "bbs_score_nodes"))) return st;

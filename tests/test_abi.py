@@ -57,6 +57,6 @@ def test_struct_layouts():
     # field offsets the binding relies on
     assert C.sizeof(bbs.SearchRange) == 48
     assert bbs.Options.stream.offset == 16 and bbs.Options.prior.offset == 24 and bbs.Options.graph.offset == 40
-    assert C.sizeof(bbs.Options) == 56
+    assert C.sizeof(bbs.Options) == 64
     assert bbs.Result.nodes_expanded.offset == 56
     assert C.sizeof(bbs.Result) == 56 + 6 * 8 + 8 + 8 + 8 + 8 + 4 * 8 + 24 + 32 + 16 * 8 + 8 + 8 + 4 + 4
