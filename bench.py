@@ -96,13 +96,13 @@ def pct(v, q):
     return v[min(len(v) - 1, int(q * len(v)))] if v else None
 
 
-def golden_parity(results, seeds, k, batch):
+def golden_parity(results, seeds, k, batch, case_name="bench"):
     """How many timed results equal the oracle's stored results (every field)."""
     try:
         doc = json.load(open(GOLDEN_FILE))
     except (OSError, ValueError):
         return None
-    case = doc.get("cases", {}).get("bench", {})
+    case = doc.get("cases", {}).get(case_name, {})
     if case.get("k") != k or case.get("batch") != batch:
         return None
     q = case.get("queries", {})
@@ -115,7 +115,8 @@ def golden_parity(results, seeds, k, batch):
             continue
         n += 1
         eq += all(r[f] == w[f] for f in keys)
-    return f"{eq}/{n} equal to {os.path.relpath(GOLDEN_FILE, ROOT)} (of {len(seeds)} timed queries)"
+    return (f"{eq}/{n} equal to {os.path.relpath(GOLDEN_FILE, ROOT)} case {case_name} (of {len(seeds)} timed queries)"
+            if n else None)
 
 
 def with_one_core(fn):
@@ -406,7 +407,8 @@ def main():
                     "reading": "angular cells nested top down (option nested_angles), not the default grid",
                     "nodes_scored_total": sum(r["nodes_scored"] for r in rr),
                     "found": f"{sum(r['found'] for r in rr)}/{len(seeds)}",
-                    "success_2m_0p05rad": f"{sum(success(r, scans[s].pose) for s, r in zip(seeds, rr))}/{len(seeds)}"})
+                    "success_2m_0p05rad": f"{sum(success(r, scans[s].pose) for s, r in zip(seeds, rr))}/{len(seeds)}",
+                    "parity_vs_oracle": golden_parity(rr, seeds, args.k, args.batch, "nested")})
             print(f"[bench] {mode}: {line['config'][mode]}", file=sys.stderr, flush=True)
         # achievable memory rates: a streaming read of 1 GiB (HBM) and random
         # 8-byte gathers into a table of the size of the map's level grids

@@ -12,7 +12,8 @@ l_max = 6, search x, y +-250 m, z 1.8 +- 2 m, roll/pitch +-3 deg, yaw
   bench    K = 10,000 (0.5 m thinning), b = 10,000, query seeds 0..19 -- the
            queries the benchmark times;
   tuned    b = 64,000 at K = 5,000 / 10,000 / 20,000 (0.25 m thinning), query
-           seeds 0 and 1 -- the batch size the autotuner picks.
+           seeds 0 and 1 -- the batch size the autotuner picks;
+  nested   as bench, on the nested angular grid (option nested_angles).
 Each query records every result field, the sha256 of its scan (so a reader
 can check it regenerated the same input), and the oracle's wall time and
 thread count on the machine that wrote it.
@@ -47,6 +48,7 @@ CASES = {
     "tuned_k5000": {"k": 5000, "voxel": 0.25, "batch": 64000, "seeds": [0, 1]},
     "tuned_k10000": {"k": 10000, "voxel": 0.25, "batch": 64000, "seeds": [0, 1]},
     "tuned_k20000": {"k": 20000, "voxel": 0.25, "batch": 64000, "seeds": [0, 1]},
+    "nested": {"k": 10000, "voxel": 0.5, "batch": 10000, "seeds": list(range(20)), "nested": True},
 }
 FIELDS = ("found", "score", "leaf", "pose", "nodes_expanded", "nodes_scored", "flushes", "leaves_accepted",
           "initial_size", "initial_kept", "bound_checks", "bound_violations")
@@ -87,12 +89,14 @@ def main():
         case = doc["cases"].setdefault(name, {})
         case.update({"k": c["k"], "voxel": c["voxel"], "batch": c["batch"], "threshold": T,
                      "scan": f"synth.city_query(city, seed, {c['k']}, voxel={c['voxel']})"})
+        if c.get("nested"):
+            case["nested"] = True
         queries = case.setdefault("queries", {})
         for seed in c["seeds"]:
             if str(seed) in queries:
                 continue
             scan = synth.city_query(city, seed, c["k"], voxel=c["voxel"])
-            s = oracle.Search(omap, scan.points, lo, hi)
+            s = oracle.Search(omap, scan.points, lo, hi, nested=bool(c.get("nested")))
             t0 = time.perf_counter()
             r = s.localize(T, batch=c["batch"], threads=args.threads)
             dt = time.perf_counter() - t0

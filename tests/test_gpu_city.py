@@ -86,7 +86,8 @@ def test_city_query_equals_stored_oracle(city_map, case, seed):
     for mode, kw in MODES.items():
         say(f"city {case} seed {seed} {mode}: k {spec['k']} b {spec['batch']} "
             f"(oracle scored {want['nodes_scored']})")
-        got = bbs.localize(gmap, dev, lo, hi, spec["threshold"], batch_size=spec["batch"], workspace=ws, **kw)
+        got = bbs.localize(gmap, dev, lo, hi, spec["threshold"], batch_size=spec["batch"], workspace=ws,
+                           nested_angles=bool(spec.get("nested", False)), **kw)
         check(got, want, f"{case}/{seed}/{mode}")
         if mode == "persistent":
             assert got["persistent_used"] == 1
