@@ -445,13 +445,12 @@ __device__ inline int bucket_level(int q, const SearchConst &C)
 // whole workgroup of NT >= 256 threads; thread s < 256 handles slot s.
 template <int NT>
 __device__ void tile_pass(int t, const uint4 *groups, int32_t *scores, State *st, const SearchConst &C,
-                          int n_groups, int32_t *kq, int32_t *krank, uint4 *knode, int32_t *kcnt, int32_t *hist,
+                          int n_groups, int best, int32_t *kq, int32_t *krank, uint4 *knode, int32_t *kcnt, int32_t *hist,
                           uint32_t *qmask, int *sq, int *sm)
 {
     const int s = threadIdx.x;
     const bool slot = s < kTileSlots;
     const int g = t * kTileGroups + s / 8, j = s & 7;
-    const int best = ld_agent(&st->best);
     int q = -1;
     uint4 child = make_uint4(0u, 0u, 0u, 0u);
     if (slot && g < n_groups) {
@@ -474,27 +473,69 @@ __device__ void tile_pass(int t, const uint4 *groups, int32_t *scores, State *st
     }
     if (slot) sq[s] = q;
     __syncthreads();
+    // The slot's rank among the tile's earlier slots of its bucket, and the
+    // bucket's count in the tile.  The slots split into those of earlier
+    // waves (all before s), the slot's own wave and later waves (all after
+    // s); each is read four to a load, with several loads in flight.
     int rank = 0, cnt = 0;
-    if (q >= 0) {
-        for (int i = 0; i < kTileSlots; ++i) {
-            const int e = (sq[i] == q);
-            cnt += e;
-            rank += e & (i < s);
+    if (q >= 0 && slot) {
+        const int4 *sq4 = reinterpret_cast<const int4 *>(sq);
+        const int w0 = (s >> 6) << 4;              // first int4 of the slot's wave
+        int before = 0, after = 0;
+#pragma unroll 4
+        for (int i = 0; i < w0; ++i) {
+            const int4 v = sq4[i];
+            before += (v.x == q) + (v.y == q) + (v.z == q) + (v.w == q);
         }
+#pragma unroll 4
+        for (int i = w0; i < w0 + 16; ++i) {
+            const int4 v = sq4[i];
+            const int i0 = 4 * i;
+            rank += ((v.x == q) & (i0 < s)) + ((v.y == q) & (i0 + 1 < s)) + ((v.z == q) & (i0 + 2 < s)) +
+                    ((v.w == q) & (i0 + 3 < s));
+            after += (v.x == q) + (v.y == q) + (v.z == q) + (v.w == q);
+        }
+#pragma unroll 4
+        for (int i = w0 + 16; i < kTileSlots / 4; ++i) {
+            const int4 v = sq4[i];
+            after += (v.x == q) + (v.y == q) + (v.z == q) + (v.w == q);
+        }
+        rank += before;
+        cnt = before + after;
     }
-    if (q >= 0 && rank == 0) {
-        hist[(int64_t)t * C.q_count + q] = cnt;
-        atomicOr(&qmask[q >> 5], 1u << (q & 31));
+    // One exchange between the waves for the tile's bucket range and its
+    // kept count (with each child's place in the compact list).  The global
+    // writes and atomics come after the last barrier, so that no barrier
+    // waits for them to be performed.
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wmin = __builtin_amdgcn_readlane(wave_scan_min(q >= 0 ? q : INT_MAX), 63);
+    const int wmaxn = __builtin_amdgcn_readlane(wave_scan_min(q >= 0 ? -q : INT_MAX), 63);
+    const int wscan = wave_scan_add(q >= 0 ? 1 : 0);
+    if (lane == 63) {
+        sm[3 * wave] = wmin;
+        sm[3 * wave + 1] = wmaxn;
+        sm[3 * wave + 2] = wscan;
     }
-    const int qmn = block_min_int<NT>(q >= 0 ? q : INT_MAX, sm);
-    const int qmx = -block_min_int<NT>(q >= 0 ? -q : INT_MAX, sm);
-    int tot;
-    const int kin = block_scan_incl<NT>(q >= 0 ? 1 : 0, sm, &tot);
+    __syncthreads();
+    int qmn = INT_MAX, qmxn = INT_MAX, before = 0, tot = 0;
+    for (int w = 0; w < NT / 64; ++w) {
+        qmn = min(qmn, sm[3 * w]);
+        qmxn = min(qmxn, sm[3 * w + 1]);
+        const int c = sm[3 * w + 2];
+        before += w < wave ? c : 0;
+        tot += c;
+    }
+    const int qmx = -qmxn;
+    const int kin = wscan + before;
     if (q >= 0) {
         const int64_t k = (int64_t)t * kTileSlots + kin - 1;
         kq[k] = q;
         krank[k] = rank;
         knode[k] = child;
+    }
+    if (q >= 0 && rank == 0) {
+        hist[(int64_t)t * C.q_count + q] = cnt;
+        atomicOr(&qmask[q >> 5], 1u << (q & 31));
     }
     if (threadIdx.x == 0) kcnt[t] = tot;
     if (threadIdx.x == 0 && tot > 0) {
@@ -534,8 +575,8 @@ struct HistSmem {
 template <int NT>
 struct ScoreSmem {
     int red[NT / 64][16];
-    int sq[kTileSlots];
-    int sm[NT / 64];
+    alignas(16) int sq[kTileSlots];
+    int sm[3 * (NT / 64)];
     int s_last;
     int s_next;
 };
@@ -1062,7 +1103,16 @@ __device__ void score_items_runs(State *st, const ScoreArgs &A, const MapView &m
     int32_t *__restrict__ scores = A.scores;
     int32_t *tile_done = A.tile_done;
     auto &red = sh.red;
-    const int n_groups = st ? (ld_agent(&st->batch) ? ld_agent(&st->n_groups) : 0) : A.n_groups_fixed;
+    // the batch header in one round trip (independent loads, issued together)
+    int n_groups = A.n_groups_fixed, best = 0, hr = 0, hs = 0, hi = 0;
+    if (st) {
+        const int pending = ld_agent(&st->batch), ng = ld_agent(&st->n_groups);
+        best = ld_agent(&st->best);
+        hr = ld_agent(&st->runs);
+        hs = ld_agent(&st->n_slices);
+        hi = ld_agent(&st->n_items);
+        n_groups = pending ? ng : 0;
+    }
     if (n_groups <= 0) return;
     // Work items.  A batch the gather wrote comes as item descriptors over
     // its runs (groups sharing a level and rotation): histogram items, or
@@ -1073,7 +1123,7 @@ __device__ void score_items_runs(State *st, const ScoreArgs &A, const MapView &m
     // groups ways into point slices.  Items go round-robin over the
     // workgroups (the grid is as large as the device holds at once), or, with
     // a ticket counter, to whichever workgroup asks next.
-    const bool runs = st && ld_agent(&st->runs);
+    const bool runs = st && hr;
     const int K = C.K;
     constexpr int kStep = NT * kUnroll;                 // points of one round of the workgroup
     const int max_s = (K + kStep - 1) / kStep;
@@ -1082,9 +1132,8 @@ __device__ void score_items_runs(State *st, const ScoreArgs &A, const MapView &m
     // order, paired, or split into point slices when they are too few
     const int s_min = min(max_s, max(1, (C.score_items + n_groups - 1) / n_groups));
     const bool legacy_pairs = s_min == 1;
-    const int S = runs ? max(1, ld_agent(&st->n_slices)) : (legacy_pairs ? 1 : s_min);
-    const int64_t n_items = runs ? (int64_t)ld_agent(&st->n_items)
-                                 : (legacy_pairs ? (n_groups + 1) / 2 : (int64_t)n_groups * S);
+    const int S = runs ? max(1, hs) : (legacy_pairs ? 1 : s_min);
+    const int64_t n_items = runs ? (int64_t)hi : (legacy_pairs ? (n_groups + 1) / 2 : (int64_t)n_groups * S);
     int32_t *ticket = A.ticket;
     int64_t item = blockIdx.x;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -1190,7 +1239,7 @@ __device__ void score_items_runs(State *st, const ScoreArgs &A, const MapView &m
             const int n_t = sh.h.n_tiles;
             for (int i = 0; i < n_t; ++i) {
                 const int t = sh.h.tiles[i];
-                tile_pass<NT>(t, A.groups, scores, st, C, n_groups, A.kq, A.krank, A.knode, A.kcnt, A.hist, A.qmask,
+                tile_pass<NT>(t, A.groups, scores, st, C, n_groups, best, A.kq, A.krank, A.knode, A.kcnt, A.hist, A.qmask,
                               sh.sq, sh.sm);
                 if (threadIdx.x == 0) __hip_atomic_store(&tile_done[t], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 __syncthreads();
@@ -1224,7 +1273,13 @@ __device__ void score_items(State *st, const ScoreArgs &A, const MapView &map, c
     int32_t *__restrict__ scores = A.scores;
     int32_t *tile_done = A.tile_done;
     auto &red = sh.red;
-    const int n_groups = st ? (ld_agent(&st->batch) ? ld_agent(&st->n_groups) : 0) : A.n_groups_fixed;
+    // the batch header in one round trip (independent loads, issued together)
+    int n_groups = A.n_groups_fixed, best = 0;
+    if (st) {
+        const int pending = ld_agent(&st->batch), ng = ld_agent(&st->n_groups);
+        best = ld_agent(&st->best);
+        n_groups = pending ? ng : 0;
+    }
     if (n_groups <= 0) return;
     const int K = C.K;
     constexpr int kStep = NT * kUnroll;                 // points of one round of the workgroup
@@ -1362,7 +1417,7 @@ __device__ void score_items(State *st, const ScoreArgs &A, const MapView &map, c
             }
             __syncthreads();
             if (sh.s_last) {
-                tile_pass<NT>(t, groups, scores, st, C, n_groups, A.kq, A.krank, A.knode, A.kcnt, A.hist, A.qmask,
+                tile_pass<NT>(t, groups, scores, st, C, n_groups, best, A.kq, A.krank, A.knode, A.kcnt, A.hist, A.qmask,
                               sh.sq, sh.sm);
                 if (threadIdx.x == 0) __hip_atomic_store(&tile_done[t], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
