@@ -437,6 +437,16 @@ __device__ inline int bucket_level(int q, const SearchConst &C)
     return C.depth_first ? q / C.n_scores : q % (C.levels + 1);
 }
 
+// The tile pass's LDS table of buckets: a key per entry and, per entry, the
+// count of each of the four slot waves (a byte each).
+constexpr int kRankBits = 9;
+constexpr int kRankSlots = 1 << kRankBits;      // twice the slots of a tile
+static_assert(kTileSlots / 64 == 4 && kRankSlots >= 2 * kTileSlots, "rank table layout");
+struct RankTab {
+    int key[kRankSlots];
+    uint32_t cnt[kRankSlots];
+};
+
 // One tile of 32 groups (256 node slots) of a scored batch: the queue bucket
 // of every kept child (score >= best), its rank among the tile's earlier
 // children of the same bucket, and the tile's count per bucket.  The kept
@@ -446,7 +456,7 @@ __device__ inline int bucket_level(int q, const SearchConst &C)
 template <int NT>
 __device__ void tile_pass(int t, const uint4 *groups, int32_t *scores, State *st, const SearchConst &C,
                           int n_groups, int best, int32_t *kq, int32_t *krank, uint4 *knode, int32_t *kcnt, int32_t *hist,
-                          uint32_t *qmask, int *sq, int *sm)
+                          uint32_t *qmask, RankTab &rt, int *sm)
 {
     const int s = threadIdx.x;
     const bool slot = s < kTileSlots;
@@ -471,43 +481,48 @@ __device__ void tile_pass(int t, const uint4 *groups, int32_t *scores, State *st
             }
         }
     }
-    if (slot) sq[s] = q;
-    __syncthreads();
     // The slot's rank among the tile's earlier slots of its bucket, and the
-    // bucket's count in the tile.  The slots split into those of earlier
-    // waves (all before s), the slot's own wave and later waves (all after
-    // s); each is read four to a load, with several loads in flight.
-    int rank = 0, cnt = 0;
-    if (q >= 0 && slot) {
-        const int4 *sq4 = reinterpret_cast<const int4 *>(sq);
-        const int w0 = (s >> 6) << 4;              // first int4 of the slot's wave
-        int before = 0, after = 0;
-#pragma unroll 4
-        for (int i = 0; i < w0; ++i) {
-            const int4 v = sq4[i];
-            before += (v.x == q) + (v.y == q) + (v.z == q) + (v.w == q);
-        }
-#pragma unroll 4
-        for (int i = w0; i < w0 + 16; ++i) {
-            const int4 v = sq4[i];
-            const int i0 = 4 * i;
-            rank += ((v.x == q) & (i0 < s)) + ((v.y == q) & (i0 + 1 < s)) + ((v.z == q) & (i0 + 2 < s)) +
-                    ((v.w == q) & (i0 + 3 < s));
-            after += (v.x == q) + (v.y == q) + (v.z == q) + (v.w == q);
-        }
-#pragma unroll 4
-        for (int i = w0 + 16; i < kTileSlots / 4; ++i) {
-            const int4 v = sq4[i];
-            after += (v.x == q) + (v.y == q) + (v.z == q) + (v.w == q);
-        }
-        rank += before;
-        cnt = before + after;
+    // bucket's count in the tile, without a pass over all 256 slots.  Within
+    // a wave, the lanes of one bucket are found with ballots (a round per
+    // distinct bucket of the wave, none for a wave without kept children).
+    // The wave's first lane of a bucket enters the bucket into an LDS table
+    // (open addressing, twice as many entries as slots) and writes the
+    // wave's count there, a byte per wave; a slot then adds the counts of the
+    // earlier waves.  The barrier that publishes the table also publishes
+    // each wave's bucket range and kept count.
+    for (int i = threadIdx.x; i < kRankSlots; i += NT) {
+        rt.key[i] = -1;
+        rt.cnt[i] = 0u;
     }
-    // One exchange between the waves for the tile's bucket range and its
-    // kept count (with each child's place in the compact list).  The global
-    // writes and atomics come after the last barrier, so that no barrier
-    // waits for them to be performed.
+    __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int wrank = 0, hslot = 0;
+    if (wave < kTileSlots / 64) {
+        uint64_t todo = __ballot(q >= 0);
+        int lead = 0, wcnt = 0;
+        while (todo) {
+            const int l = __builtin_ctzll(todo);
+            const int q0 = __builtin_amdgcn_readlane(q, l);
+            const uint64_t m = __ballot(q == q0);
+            if (q == q0) {
+                wrank = __popcll(m & ((1ull << lane) - 1ull));
+                wcnt = __popcll(m);
+                lead = l;
+            }
+            todo &= ~m;
+        }
+        if (q >= 0 && wrank == 0) {
+            uint32_t h = ((uint32_t)q * 2654435761u) >> (32 - kRankBits);
+            for (;;) {
+                const int old = atomicCAS(&rt.key[h], -1, q);
+                if (old == -1 || old == q) break;
+                h = (h + 1) & (kRankSlots - 1);
+            }
+            reinterpret_cast<uint8_t *>(rt.cnt)[4 * h + wave] = (uint8_t)wcnt;
+            hslot = (int)h;
+        }
+        hslot = __builtin_amdgcn_ds_bpermute(lead << 2, hslot);
+    }
     const int wmin = __builtin_amdgcn_readlane(wave_scan_min(q >= 0 ? q : INT_MAX), 63);
     const int wmaxn = __builtin_amdgcn_readlane(wave_scan_min(q >= 0 ? -q : INT_MAX), 63);
     const int wscan = wave_scan_add(q >= 0 ? 1 : 0);
@@ -517,6 +532,17 @@ __device__ void tile_pass(int t, const uint4 *groups, int32_t *scores, State *st
         sm[3 * wave + 2] = wscan;
     }
     __syncthreads();
+    int rank = 0, cnt = 0;
+    if (q >= 0) {
+        const uint32_t c4 = rt.cnt[hslot];
+#pragma unroll
+        for (int w = 0; w < kTileSlots / 64; ++w) {
+            const int c = (int)((c4 >> (8 * w)) & 0xFFu);
+            cnt += c;
+            rank += w < wave ? c : 0;
+        }
+        rank += wrank;
+    }
     int qmn = INT_MAX, qmxn = INT_MAX, before = 0, tot = 0;
     for (int w = 0; w < NT / 64; ++w) {
         qmn = min(qmn, sm[3 * w]);
@@ -575,7 +601,7 @@ struct HistSmem {
 template <int NT>
 struct ScoreSmem {
     int red[NT / 64][16];
-    alignas(16) int sq[kTileSlots];
+    RankTab rt;
     int sm[3 * (NT / 64)];
     int s_last;
     int s_next;
@@ -1240,7 +1266,7 @@ __device__ void score_items_runs(State *st, const ScoreArgs &A, const MapView &m
             for (int i = 0; i < n_t; ++i) {
                 const int t = sh.h.tiles[i];
                 tile_pass<NT>(t, A.groups, scores, st, C, n_groups, best, A.kq, A.krank, A.knode, A.kcnt, A.hist, A.qmask,
-                              sh.sq, sh.sm);
+                              sh.rt, sh.sm);
                 if (threadIdx.x == 0) __hip_atomic_store(&tile_done[t], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 __syncthreads();
             }
@@ -1418,7 +1444,7 @@ __device__ void score_items(State *st, const ScoreArgs &A, const MapView &map, c
             __syncthreads();
             if (sh.s_last) {
                 tile_pass<NT>(t, groups, scores, st, C, n_groups, best, A.kq, A.krank, A.knode, A.kcnt, A.hist, A.qmask,
-                              sh.sq, sh.sm);
+                              sh.rt, sh.sm);
                 if (threadIdx.x == 0) __hip_atomic_store(&tile_done[t], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
         }
