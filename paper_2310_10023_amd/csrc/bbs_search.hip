@@ -505,7 +505,9 @@ __device__ void tile_pass(int t, const uint4 *groups, int32_t *scores, State *st
             const int q0 = __builtin_amdgcn_readlane(q, l);
             const uint64_t m = __ballot(q == q0);
             if (q == q0) {
-                wrank = __popcll(m & ((1ull << lane) - 1ull));
+                // set bits of m below this lane
+                wrank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                       __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
                 wcnt = __popcll(m);
                 lead = l;
             }
