@@ -91,3 +91,28 @@ def test_city_query_equals_stored_oracle(city_map, case, seed):
         check(got, want, f"{case}/{seed}/{mode}")
         if mode == "persistent":
             assert got["persistent_used"] == 1
+
+
+@pytest.mark.skipif(DOC is None, reason="tests/golden/city_localize.json has not been written")
+def test_city_stream_equals_stored_oracle(city_map):
+    """Stream serving on the city (concurrent workers, each with its own
+    workspace and stream, Poisson arrivals) gives the stored oracle result
+    of every query, including one that exhausts the tree."""
+    c, gmap, _ = city_map
+    spec = DOC["cases"]["bench"]
+    seeds = [14, 16, 17, 15, 8, 0, 13, 10, 3, 2]
+    scans = []
+    for s in seeds:
+        sc = synth.city_query(c, s, spec["k"], voxel=spec["voxel"])
+        assert hashlib.sha256(np.ascontiguousarray(sc.points).tobytes()).hexdigest() == \
+            spec["queries"][str(s)]["scan_sha256"]
+        scans.append(sc.points)
+    lo = np.array(DOC["range"]["min"], np.float32)
+    hi = np.array(DOC["range"]["max"], np.float32)
+    arrivals = np.cumsum(np.random.default_rng(1).exponential(0.003, size=len(seeds)))
+    say("city stream", len(seeds), "queries, 4 workers")
+    res, t0, t1 = bbs.serve(gmap, scans, [(lo, hi)] * len(seeds), [spec["threshold"]] * len(seeds), arrivals,
+                            workers=4, batch_size=spec["batch"])
+    for s, got in zip(seeds, res):
+        check(got, spec["queries"][str(s)], f"stream/{s}")
+    assert np.all(t1 >= t0) and np.all(t0 >= arrivals - 1e-6)

@@ -66,3 +66,21 @@ def test_learned_order_localization_equals_oracle(city_net, seed):
     want = oracle.Search(o, sc.points, lo, hi).localize(T, batch=10000, threads=16, prior=prior, seed_beam=16)
     for k in RESULT_KEYS:
         assert got[k] == want[k], (k, got[k], want[k])
+
+
+@pytest.mark.parametrize("bad", [float("nan"), float("inf")])
+def test_non_finite_prior_falls_back_to_plain(city_net, bad):
+    """A prior with a non-finite logit is not used: the search runs plain
+    (no prior ordering, no seed beam) and gives the plain result."""
+    say("non-finite prior", bad)
+    c, g, net, _ = city_net
+    sc = scan(c, 0)
+    lo, hi = synth.search_range_city()
+    T = synth.threshold_95(10000)
+    prior = net.forward(proposal.bev_image(sc.points)[None])[0].astype(np.float32).copy()
+    prior[70] = bad
+    got = bbs.localize(g, sc.points, lo, hi, T, batch_size=10000, prior=prior, seed_beam=16)
+    plain = bbs.localize(g, sc.points, lo, hi, T, batch_size=10000)
+    assert got["prior_used"] == 0 and got["seed_beam_used"] == 0 and got["seeded"] == 0
+    for k in RESULT_KEYS:
+        assert got[k] == plain[k], (k, got[k], plain[k])

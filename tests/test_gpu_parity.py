@@ -267,6 +267,14 @@ def test_autotune_returns_a_measured_pair(room):
     best, allv = bbs.autotune(g, scans, lo, hi, [synth.threshold_95(2000)] * 2, [1000, 10000], [512, 4096])
     assert len(allv) == 4 and all(e["ms"] > 0 for e in allv)
     assert best["ms"] == min(e["ms"] for e in allv)
+    assert sorted((e["batch_size"], e["score_items"]) for e in allv) == [(1000, 512), (1000, 4096), (10000, 512),
+                                                                         (10000, 4096)]
+    # the pick is a configuration like any other: the oracle's result at its batch size
+    _, _, o = room
+    for sc in scans:
+        want = oracle.Search(o, sc, lo, hi).localize(synth.threshold_95(2000), batch=best["batch_size"], threads=8)
+        compare(bbs.localize(g, sc, lo, hi, synth.threshold_95(2000), batch_size=best["batch_size"],
+                             score_items=best["score_items"]), want)
 
 
 @pytest.mark.parametrize("items", [1, 300, 20000])
