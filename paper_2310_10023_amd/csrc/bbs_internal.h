@@ -89,8 +89,8 @@ __host__ __device__ inline uint64_t brick_key(int32_t bx, int32_t by, int32_t bz
 }
 
 // Spatial hash of a brick coordinate: the three-prime XOR hash of Teschner et
-// al. followed by a 32-bit avalanche so that power-of-two tables see mixed
-// low bits.
+// al. followed by a 32-bit avalanche (the finaliser of MurmurHash3, fmix32)
+// so that power-of-two tables see mixed low bits.
 __host__ __device__ inline uint32_t brick_hash(int32_t bx, int32_t by, int32_t bz)
 {
     uint32_t h = ((uint32_t)bx * 73856093u) ^ ((uint32_t)by * 19349663u) ^ ((uint32_t)bz * 83492791u);

@@ -55,6 +55,7 @@ __device__ inline void unpack_voxel(unsigned long long k, int32_t &x, int32_t &y
     z = (int32_t)(k & 0x1FFFFF) - kPackBias;
 }
 
+// 64-bit avalanche of a packed key (the SplitMix64 finaliser).
 __device__ inline unsigned long long mix64(unsigned long long x)
 {
     x ^= x >> 30;

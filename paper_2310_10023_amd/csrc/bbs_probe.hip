@@ -13,8 +13,8 @@ namespace {
 
 constexpr int kProbeThreads = 256;
 
-// 32-bit integer mix (the finaliser of a multiplicative hash): spreads
-// consecutive counters over the table.
+// 32-bit integer mix (the "lowbias32" constants found by C. Wellons'
+// hash-prospector search): spreads consecutive counters over the table.
 __device__ inline uint32_t mix32(uint32_t x)
 {
     x ^= x >> 16;
