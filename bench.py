@@ -260,6 +260,9 @@ def main():
     ap.add_argument("--rot-exact", action="store_true",
                     help="the city queries with the exact rotational bound against plain (grown map tables)")
     ap.add_argument("--nested", action="store_true", help="with --rot-exact: on the nested angular grid")
+    ap.add_argument("--net", action="store_true",
+                    help="the proposal network instead: training step, inference and device prior (MFMA kernels)")
+    ap.add_argument("--net-batch", type=int, default=128, help="training batch of --net")
     ap.add_argument("--table1-cpu-seconds", type=float, default=20.0,
                     help="CPU seconds each CPU configuration of Table I may spend (it runs as many queries as fit)")
     args = ap.parse_args()
@@ -292,6 +295,8 @@ def main():
         return table1_bench(args)
     if args.rot_exact:
         return rot_exact_bench(args)
+    if args.net:
+        return net_bench(args)
     t0 = time.perf_counter()
     city = synth.city_scene(1000)
     lo, hi = synth.search_range_city()
@@ -482,6 +487,83 @@ def learned_order(gmap, dev, seeds, plain, lo, hi, T, args):
         "beam": args.beam,
     }
     return {"summary": summary, "results": out}
+
+
+def net_flops_per_image():
+    """Multiply-adds x 2 of one forward pass: four 3x3 stride-2 convolutions
+    (64x64 input, 1->16->32->64->64 channels) and two FC layers (1024->256,
+    256->1088), each one GEMM of output pixels x output channels x (9 x input
+    channels)."""
+    ch = [1, 16, 32, 64, 64]
+    hw, fwd, dgrad = 64, 0, 0
+    for i in range(4):
+        hw //= 2
+        f = 2 * hw * hw * ch[i + 1] * 9 * ch[i]
+        fwd += f
+        dgrad += f if i > 0 else 0          # no input gradient for the image
+    fc = 2 * 1024 * 256 + 2 * 256 * 1088
+    return fwd + fc, dgrad + fc
+
+
+def net_bench(args):
+    """The learned proposal's MFMA kernels: one AdamW training step at the
+    training batch (forward, input and weight gradients, loss, AdamW), the
+    forward pass at batch 1 and 16, and the device prior of a resident city
+    scan (BEV image + forward pass).  Synthetic images: the GEMM shapes do not
+    depend on their content."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2310_10023_amd import proposal
+    rng = np.random.default_rng(0)
+    B = args.net_batch
+    net = proposal.Net(max_batch=max(256, B), params=np.load(WEIGHTS)["params"])
+    imgs = (rng.random((B, 64, 64)) < 0.1).astype(np.uint8) * rng.integers(1, 255, (B, 64, 64), dtype=np.uint8)
+    yaw = rng.integers(0, 64, B).astype(np.int32)
+    xy = rng.integers(0, 1024, B).astype(np.int32)
+    for _ in range(3):
+        net.train_step(imgs, yaw, xy, lr=1e-6)
+    n_steps = max(5, args.steps)
+    t0 = time.perf_counter()
+    for _ in range(n_steps):
+        net.train_step(imgs, yaw, xy, lr=1e-6)
+    step_s = (time.perf_counter() - t0) / n_steps
+    fwd_f, back_f = net_flops_per_image()
+    train_flops = B * (2 * fwd_f + back_f)       # forward, weight gradient, input gradient
+    out = {}
+    for b in (1, 16):
+        x = imgs[:b]
+        net.forward(x)
+        t0 = time.perf_counter()
+        for _ in range(50):
+            net.forward(x)
+        out[f"forward_b{b}_ms"] = (time.perf_counter() - t0) / 50 * 1e3
+    city = synth.city_scene(1000)
+    dev = torch.from_numpy(synth.city_query(city, 0, args.k, voxel=0.5).points).cuda()
+    net.prior(dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(50):
+        net.prior(dev)
+    prior_ms = (time.perf_counter() - t0) / 50 * 1e3
+    achieved = train_flops / step_s / 1e12
+    line = {
+        "metric": "proposal network: training step and inference (BF16 MFMA), 1 GPU",
+        "value": B / step_s, "unit": "training images/s", "n_gpus": 1, "steps": n_steps, "warmup": 3,
+        "ms_per_step": step_s * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16", "data": "synthetic (random sparse BEV images and labels)",
+        "config": {"workload": f"proposal network, training batch {B}, AdamW; forward at batch 1 and 16; "
+                               f"device prior of a {args.k}-point city scan",
+                   "flops_per_image_forward": fwd_f, "flops_per_training_step": train_flops,
+                   "prior_ms": prior_ms, **out},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": 2500.0, "unit": "TFLOP/s",
+                     "frac": achieved / 2500.0, "traffic": None,
+                     "note": "dense bf16 MFMA peak; the network is small, so each GEMM has few tiles and the step "
+                             "is bound by launches and their latency"},
+    }
+    print(json.dumps(line), flush=True)
+    net.close()
 
 
 def rot_exact_bench(args):

@@ -262,6 +262,26 @@ __global__ void k_colsum(const uint16_t *dy, int M, int N, float *out)
     atomicAdd(&out[n], s);
 }
 
+// The same for N dividing 256 (the convolutions' channel counts): thread t
+// sums column t % N over rows t / N, t / N + 256 / N, ... of its block's
+// rows, so that consecutive threads read consecutive elements; the block's
+// partial sums meet in LDS and each column takes one atomic add per block.
+__global__ __launch_bounds__(256) void k_colsum_narrow(const uint16_t *dy, int64_t M, int N, float *out)
+{
+    __shared__ float red[256];
+    const int col = threadIdx.x % N, rstep = 256 / N;
+    float acc = 0.0f;
+    for (int64_t m = (int64_t)blockIdx.x * rstep + threadIdx.x / N; m < M; m += (int64_t)gridDim.x * rstep)
+        acc += bf2f(dy[m * N + col]);
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    if (threadIdx.x < N) {
+        float t = 0.0f;
+        for (int r = 0; r < rstep; ++r) t += red[r * N + threadIdx.x];
+        atomicAdd(&out[threadIdx.x], t);
+    }
+}
+
 __global__ void k_adamw(float *p, float *m, float *v, const float *g, uint16_t *pb, int64_t n, float lr, float b1,
                         float b2, float eps, float wd, float c1, float c2, const uint8_t *decay)
 {
@@ -448,10 +468,16 @@ bbs_status backward(bbs_net *n, int batch, hipStream_t s)
         const int H = act_hw(i), C = kCh[i], OH = H / 2, Co = kCh[i + 1];
         const uint16_t *dy = n->da[i + 1];
         const int Mo = B * OH * OH;
-        const int splits = std::max(1, std::min(64, Mo / 2048));
+        // the weight gradient reduces over all Mo output pixels into a small
+        // Co x 9C block: split K so that there are enough workgroups to fill
+        // the device (256 output rows a workgroup)
+        const int splits = std::max(1, std::min(1024, Mo / 256));
         gemm(s, Co, 9 * C, Mo, MatT{dy, Co}, Im2col{i == 0 ? n->x0 : n->a[i], H, H, C},
              EpiAtomicF32{n->g + S.off[2 * i], 9 * C}, splits);
-        k_colsum<<<dim3((Co + 255) / 256, 64), 256, 0, s>>>(dy, Mo, Co, n->g + S.off[2 * i + 1]);
+        static_assert(256 % kCh[1] == 0 && 256 % kCh[2] == 0 && 256 % kCh[3] == 0 && 256 % kCh[4] == 0,
+                      "conv channel counts divide the block");
+        k_colsum_narrow<<<std::max(1, std::min(512, Mo / (256 / Co) / 16)), 256, 0, s>>>(dy, Mo, Co,
+                                                                                      n->g + S.off[2 * i + 1]);
         if (i > 0)
             gemm(s, B * H * H, C, 9 * Co, Dgrad{dy, H, H, Co}, WDgrad{n->pb + S.off[2 * i], C, Co},
                  EpiMaskBf16{n->da[i], n->a[i], C});
