@@ -361,6 +361,8 @@ typedef struct {
     int32_t score_threshold;
     bbs_search_range range;
     double arrival_s;         /* arrival time in seconds after the start of bbs_serve (>= 0) */
+    const float *prior;       /* this query's 1088 proposal logits (host memory, read while the query
+                                 runs), or NULL for the prior of the options (if any) */
 } bbs_query;
 
 /*
@@ -368,8 +370,11 @@ typedef struct {
  *   queries, n      queries, sorted by arrival_s (not modified)
  *   workers         concurrent searches (1..64); each worker has its own
  *                   workspace and HIP stream, so one query's serial phase
- *                   overlaps the scoring of others
- *   opt             options for every query (its stream field is ignored)
+ *                   overlaps the scoring of others; 1 with opt->persistent
+ *                   (a persistent search's cooperative grid fills the GPU),
+ *                   else BBS_ERR_INVALID_ARG
+ *   opt             options for every query (its stream field is ignored; a
+ *                   query's own prior, if set, replaces the options' prior)
  *   results         n results, in query order (caller-allocated)
  *   start_s, end_s  n doubles each (caller-allocated, may be NULL): when each
  *                   query started and finished, seconds after the start
@@ -439,7 +444,8 @@ typedef struct {
  * runs every query once after one warm-up query, on one workspace.
  *   batch_sizes, n_b       candidate b values (each in [1, 2^24])
  *   score_items, n_items   candidate score_items values (each in [1, 2^20])
- *   base                   other options (its batch_size and score_items are replaced)
+ *   base                   other options (its batch_size and score_items are replaced;
+ *                          a query's own prior replaces its prior)
  *   best                   fastest pair (caller-allocated)
  *   all                    NULL or n_b * n_items entries, b outer
  * Note: b changes the search schedule (node counts) but not its rules.

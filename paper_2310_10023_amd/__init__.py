@@ -102,7 +102,8 @@ class PreprocessOptions(C.Structure):
 
 class Query(C.Structure):
     _fields_ = [("scan_xyz", C.c_void_p), ("k", C.c_int64), ("scan_on_device", C.c_int32),
-                ("score_threshold", C.c_int32), ("range", SearchRange), ("arrival_s", C.c_double)]
+                ("score_threshold", C.c_int32), ("range", SearchRange), ("arrival_s", C.c_double),
+                ("prior", C.c_void_p)]
 
 
 _lib = None
@@ -393,13 +394,17 @@ def score_nodes(bmap: Map, scan, rmin, rmax, nodes, translation_only: bool = Fal
     return out
 
 
-def _queries(scans, ranges, thresholds, arrivals):
+def _queries(scans, ranges, thresholds, arrivals, priors=None):
     n = len(scans)
     qs = (Query * max(n, 1))()
     keep = []
     for i in range(n):
         ptr, k, dev, kp = _points(scans[i], "scan")
         keep.append(kp)
+        if priors is not None and priors[i] is not None:
+            pr = np.ascontiguousarray(priors[i], np.float32).reshape(1088)
+            keep.append(pr)
+            qs[i].prior = pr.ctypes.data
         qs[i].scan_xyz = ptr
         qs[i].k = k
         qs[i].scan_on_device = dev
@@ -434,16 +439,20 @@ def autotune(bmap: Map, scans, rmin, rmax, thresholds, batch_sizes, score_items,
 
 
 def serve(bmap: Map, scans, ranges, thresholds, arrivals, *, workers: int = 4, batch_size: int = 10000,
-          translation_only: bool = False) -> tuple[list, "np.ndarray", "np.ndarray"]:
+          translation_only: bool = False, persistent: bool = False, priors=None,
+          seed_beam: int = 0) -> tuple[list, "np.ndarray", "np.ndarray"]:
     """Serve a stream of queries (sorted by arrival time, seconds from the
-    start) with `workers` concurrent searches.  Returns (results, start_s,
-    end_s)."""
+    start) with `workers` concurrent searches.  priors: optional per-query
+    1088 proposal logits (None entries run plain).  Returns (results,
+    start_s, end_s)."""
     n = len(scans)
-    qs, keep = _queries(scans, ranges, thresholds, arrivals)
+    qs, keep = _queries(scans, ranges, thresholds, arrivals, priors)
     opt = Options()
     lib().bbs_default_options(C.byref(opt))
     opt.batch_size = int(batch_size)
     opt.translation_only = int(translation_only)
+    opt.persistent = int(persistent)
+    opt.seed_beam = int(seed_beam)
     res = (Result * max(n, 1))()
     t_start = np.zeros(max(n, 1), np.float64)
     t_end = np.zeros(max(n, 1), np.float64)

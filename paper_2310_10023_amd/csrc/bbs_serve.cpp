@@ -32,6 +32,10 @@ extern "C" bbs_status bbs_serve(const bbs_map *map, const bbs_query *queries, in
     bbs_options o;
     bbs_default_options(&o);
     if (opt) o = *opt;
+    // a persistent search is one cooperative grid sized to be resident on
+    // every compute unit at once, so two of them cannot run side by side
+    if (o.persistent && workers > 1)
+        return fail(BBS_ERR_INVALID_ARG, "bbs_serve: the persistent kernel occupies the whole GPU; use one worker");
     int device = 0;
     hipError_t e = hipGetDevice(&device);
     if (e != hipSuccess) return bbs::hip_fail(e, "hipGetDevice");
@@ -64,8 +68,10 @@ extern "C" bbs_status bbs_serve(const bbs_map *map, const bbs_query *queries, in
             if (q.arrival_s > now)
                 std::this_thread::sleep_for(std::chrono::duration<double>(q.arrival_s - now));
             const double ts = secs();
+            bbs_options oq = ow;
+            if (q.prior) oq.prior = q.prior;
             bbs_status s = bbs_localize(map, ws[w], q.scan_xyz, q.k, q.scan_on_device, &q.range, q.score_threshold,
-                                        &ow, &results[i]);
+                                        &oq, &results[i]);
             const double te = secs();
             if (start_s) start_s[i] = ts;
             if (end_s) end_s[i] = te;
@@ -121,13 +127,15 @@ extern "C" bbs_status bbs_autotune(const bbs_map *map, const bbs_query *queries,
         for (int ii = 0; ii < n_items && st == BBS_OK; ++ii) {
             o.batch_size = batch_sizes[ib];
             o.score_items = score_items[ii];
-            const bbs_query &w = queries[0];
-            st = bbs_localize(map, ws, w.scan_xyz, w.k, w.scan_on_device, &w.range, w.score_threshold, &o, &r);
+            // (a query's own prior replaces the options' prior, as in bbs_serve)
+            auto run = [&](const bbs_query &Q) {
+                bbs_options oq = o;
+                if (Q.prior) oq.prior = Q.prior;
+                return bbs_localize(map, ws, Q.scan_xyz, Q.k, Q.scan_on_device, &Q.range, Q.score_threshold, &oq, &r);
+            };
+            st = run(queries[0]);
             const auto t0 = std::chrono::steady_clock::now();
-            for (int64_t q = 0; q < n && st == BBS_OK; ++q) {
-                const bbs_query &Q = queries[q];
-                st = bbs_localize(map, ws, Q.scan_xyz, Q.k, Q.scan_on_device, &Q.range, Q.score_threshold, &o, &r);
-            }
+            for (int64_t q = 0; q < n && st == BBS_OK; ++q) st = run(queries[q]);
             const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
             if (st) break;
             if (all) all[ib * n_items + ii] = bbs_tune_entry{o.batch_size, o.score_items, ms};

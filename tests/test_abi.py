@@ -58,5 +58,6 @@ def test_struct_layouts():
     assert C.sizeof(bbs.SearchRange) == 48
     assert bbs.Options.stream.offset == 16 and bbs.Options.prior.offset == 24 and bbs.Options.graph.offset == 40
     assert C.sizeof(bbs.Options) == 64
+    assert bbs.Query.arrival_s.offset == 72 and bbs.Query.prior.offset == 80 and C.sizeof(bbs.Query) == 88
     assert bbs.Result.nodes_expanded.offset == 56
     assert C.sizeof(bbs.Result) == 56 + 6 * 8 + 8 + 8 + 8 + 8 + 4 * 8 + 24 + 32 + 16 * 8 + 8 + 8 + 4 + 4

@@ -435,6 +435,33 @@ def test_serve_matches_single_queries(room):
     assert np.all(t1 >= t0) and np.all(t0 >= arrivals - 1e-6)
 
 
+def test_serve_with_per_query_priors_matches_single_queries(room):
+    """Learned ordering in a stream: each query's own prior (one query
+    without) and a seed beam give what a single search with the same prior
+    gives; the persistent kernel, which fills the GPU, is refused with more
+    than one worker."""
+    say("serve, per-query priors")
+    scene, g, _ = room
+    lo, hi = synth.search_range_room()
+    rng = np.random.default_rng(3)
+    scans, priors = [], []
+    for seed in range(4):
+        scans.append(synth.scan_scene(scene, 50 + seed, 1800, z=1.5, z_jitter=0.25, rp_deg=2.0).points)
+        priors.append(rng.normal(size=1088).astype(np.float32))
+    priors[2] = None
+    thr = [synth.threshold_95(len(s)) for s in scans]
+    arrivals = np.cumsum(rng.exponential(0.002, size=4))
+    res, t0, t1 = bbs.serve(g, scans, [(lo, hi)] * 4, thr, arrivals, workers=2, batch_size=2000, priors=priors,
+                            seed_beam=8)
+    for sc, p, t, got in zip(scans, priors, thr, res):
+        want = bbs.localize(g, sc, lo, hi, t, batch_size=2000, prior=p, seed_beam=8)
+        compare(got, want)
+        assert got["prior_used"] == (p is not None)
+        assert (got["seeded"], got["seed_score"]) == (want["seeded"], want["seed_score"])
+    with pytest.raises(bbs.BbsError, match="one worker"):
+        bbs.serve(g, scans, [(lo, hi)] * 4, thr, arrivals, workers=2, batch_size=2000, persistent=True)
+
+
 # ------------------------------------------------------------------ full-size city (sampled parity)
 
 @pytest.fixture(scope="module")
