@@ -154,6 +154,12 @@ struct EpiMaskBf16 {    // bf16(acc) where the forward activation is positive, e
     }
 };
 
+struct EpiSplitF32 {    // split-K partial of split blockIdx.z into out[split][M][N]
+    float *out;
+    int M, N;
+    __device__ void operator()(int m, int n, float v) const { out[((int64_t)blockIdx.z * M + m) * N + n] = v; }
+};
+
 struct EpiAtomicF32 {   // accumulate into float (split K)
     float *out;
     int ld;
@@ -200,6 +206,43 @@ void gemm(hipStream_t s, int M, int N, int K, AOp A, BOp B, Epi E, int splits = 
     const int kchunk = ((K + splits - 1) / splits + 15) / 16 * 16;
     dim3 grid((M + 15) / 16, (N + 63) / 64, (K + kchunk - 1) / kchunk);
     k_gemm<<<grid, 256, 0, s>>>(M, N, K, kchunk, A, B, E);
+}
+
+// The partials of a split-K product summed in split order (deterministic),
+// then the layer's epilogue.
+template <class Epi>
+__global__ void k_splitk_finish(const float *part, int splits, int M, int N, Epi E)
+{
+    const int64_t mn = (int64_t)M * N;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < mn; i += (int64_t)gridDim.x * blockDim.x) {
+        float v = 0.0f;
+        for (int sp = 0; sp < splits; ++sp) v += part[sp * mn + i];
+        E((int)(i / N), (int)(i % N), v);
+    }
+}
+
+// A forward product: when its output covers few workgroups (small batches,
+// the inference path), K is split into up to 16 parts whose partials go to a
+// scratch buffer, so that more workgroups share the reduction; a second
+// kernel adds them in order and applies the epilogue.
+template <class AOp, class BOp, class Epi>
+void gemm_fwd(hipStream_t s, int M, int N, int K, AOp A, BOp B, Epi E, float *scratch, int64_t scratch_floats)
+{
+    const int tiles = ((M + 15) / 16) * ((N + 63) / 64);
+    int splits = 1;
+    if (tiles < 64 && K >= 128)
+        splits = (int)std::max<int64_t>(1, std::min<int64_t>({16, K / 64, 128 / tiles,
+                                                              scratch_floats / ((int64_t)M * N)}));
+    if (splits <= 1) {
+        gemm(s, M, N, K, A, B, E);
+        return;
+    }
+    const int kchunk = ((K + splits - 1) / splits + 15) / 16 * 16;
+    const int used = (K + kchunk - 1) / kchunk;            // splits that hold work
+    dim3 grid((M + 15) / 16, (N + 63) / 64, used);
+    k_gemm<<<grid, 256, 0, s>>>(M, N, K, kchunk, A, B, EpiSplitF32{scratch, M, N});
+    const int64_t mn = (int64_t)M * N;
+    k_splitk_finish<<<(int)std::min<int64_t>((mn + 255) / 256, 1024), 256, 0, s>>>(scratch, used, M, N, E);
 }
 
 // ------------------------------------------------------------------ small kernels
@@ -419,8 +462,11 @@ struct bbs_net {
     unsigned long long *maxsq = nullptr;
     int32_t *bev_cnt = nullptr;
     int32_t *bev_bad = nullptr;
+    float *splitk = nullptr;              // split-K partials of small forward products
     std::vector<void *> owned;
 };
+
+constexpr int64_t kSplitKFloats = 1 << 20;
 
 namespace {
 
@@ -441,12 +487,14 @@ void forward(bbs_net *n, int batch, hipStream_t s)
     for (int i = 0; i < 4; ++i) {
         const int H = act_hw(i), C = kCh[i], OH = H / 2, Co = kCh[i + 1];
         const uint16_t *w = n->pb + S.off[2 * i];
-        gemm(s, batch * OH * OH, Co, 9 * C, Im2col{x, H, H, C}, MatT{w, 9 * C},
-             EpiBiasRelu{n->a[i + 1], n->p + S.off[2 * i + 1], Co});
+        gemm_fwd(s, batch * OH * OH, Co, 9 * C, Im2col{x, H, H, C}, MatT{w, 9 * C},
+                 EpiBiasRelu{n->a[i + 1], n->p + S.off[2 * i + 1], Co}, n->splitk, kSplitKFloats);
         x = n->a[i + 1];
     }
-    gemm(s, batch, kF1, kF0, MatRM{n->a[4], kF0}, MatT{n->pb + S.off[8], kF0}, EpiBiasRelu{n->h1, n->p + S.off[9], kF1});
-    gemm(s, batch, kOut, kF1, MatRM{n->h1, kF1}, MatT{n->pb + S.off[10], kF1}, EpiBiasF32{n->logits, n->p + S.off[11], kOut});
+    gemm_fwd(s, batch, kF1, kF0, MatRM{n->a[4], kF0}, MatT{n->pb + S.off[8], kF0},
+             EpiBiasRelu{n->h1, n->p + S.off[9], kF1}, n->splitk, kSplitKFloats);
+    gemm_fwd(s, batch, kOut, kF1, MatRM{n->h1, kF1}, MatT{n->pb + S.off[10], kF1},
+             EpiBiasF32{n->logits, n->p + S.off[11], kOut}, n->splitk, kSplitKFloats);
 }
 
 // Backward pass from n->dlog into n->g (zeroed here).
@@ -519,7 +567,8 @@ extern "C" bbs_status bbs_net_create(int32_t max_batch, bbs_net **out)
                net_alloc(n, (void **)&n->h1, B * kF1 * 2) || net_alloc(n, (void **)&n->logits, B * kOut * 4) ||
                net_alloc(n, (void **)&n->dlog, B * kOut * 2) || net_alloc(n, (void **)&n->dh1, B * kF1 * 2) ||
                net_alloc(n, (void **)&n->loss, 64) || net_alloc(n, (void **)&n->maxsq, 64) ||
-               net_alloc(n, (void **)&n->bev_cnt, kBins * kBins * 4) || net_alloc(n, (void **)&n->bev_bad, 64);
+               net_alloc(n, (void **)&n->bev_cnt, kBins * kBins * 4) || net_alloc(n, (void **)&n->bev_bad, 64) ||
+               net_alloc(n, (void **)&n->splitk, kSplitKFloats * 4);
     for (int i = 1; i <= 4 && !bad; ++i) {
         const int64_t e = B * act_hw(i) * act_hw(i) * kCh[i];
         bad = net_alloc(n, (void **)&n->a[i], e * 2) || net_alloc(n, (void **)&n->da[i], std::max<int64_t>(e, B * 4096) * 2);
